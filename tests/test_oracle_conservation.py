@@ -1,0 +1,82 @@
+"""Pins of the coupled oracle step: conservation laws and the force sign.
+
+* Mass and total psi are conserved to rounding (Sec. I, Sec. V: both
+  discretisations are conservative).
+* Momentum balance: sum fbar c changes each step by exactly sum F, with F the
+  force density (App. B moment relations, force-density reading).  With B = 0
+  the central and Gamma gradients make sum F vanish, so momentum is conserved.
+* Force sign (reading F = -psi grad mu): with M = 0 and kT = 0 the order
+  parameter moves only by advection, the force and the advection exchange
+  energy, and viscosity dissipates it, so free energy plus kinetic energy must
+  fall at every step.  The opposite sign feeds energy in and blows up.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+
+CASES = [(O.D2Q9, O.FD, (20, 14, 1)), (O.D2Q9, O.FV, (20, 14, 1)),
+         (O.D3Q19, O.FD, (8, 7, 6)), (O.D3Q19, O.FV, (8, 7, 6))]
+
+
+def _momentum(p, f):
+    c, _ = O.velocities(p.lattice)
+    return (c[:, :O.d_of(p)].T.astype(float) @ f)
+
+
+@pytest.mark.parametrize("lattice,smol,shape", CASES)
+def test_mass_psi_momentum_balance(lattice, smol, shape):
+    p = O.make_params(lattice=lattice, smol=smol, shape=shape, a=-0.04, b=0.04, kappa=0.05,
+                      kT=1e-4, M=0.1)
+    f, psi = O.init(p, 0, 0.3)
+    for n in range(12):
+        t0 = O.totals(p, f, psi)
+        F = O.force(p, psi)
+        P0 = _momentum(p, f).sum(axis=1)
+        O.step(p, f, psi, n)
+        t1 = O.totals(p, f, psi)
+        P1 = _momentum(p, f).sum(axis=1)
+        assert abs(t1[0] - t0[0]) <= 1e-13 * t0[5]
+        assert abs(t1[4] - t0[4]) <= 1e-13 * t0[9]
+        scale = np.abs(_momentum(p, f)).sum() + np.abs(F).sum()
+        np.testing.assert_allclose(P1 - P0, F.sum(axis=1), atol=1e-13 * scale)
+
+
+@pytest.mark.parametrize("lattice,smol,shape", CASES)
+def test_momentum_conserved_without_quartic_term(lattice, smol, shape):
+    p = O.make_params(lattice=lattice, smol=smol, shape=shape, a=0.04, b=0.0, kappa=0.05,
+                      kT=1e-4, M=0.1)
+    f, psi = O.init(p, 0, 0.3)
+    for n in range(8):
+        F = O.force(p, psi)
+        assert np.abs(F.sum(axis=1)).max() <= 1e-15 * max(1.0, np.abs(F).sum())
+        P0 = _momentum(p, f).sum(axis=1)
+        O.step(p, f, psi, n)
+        P1 = _momentum(p, f).sum(axis=1)
+        np.testing.assert_allclose(P1, P0, atol=1e-14 * np.abs(_momentum(p, f)).sum())
+
+
+def _energy(p, f, psi):
+    F = O.force(p, psi)
+    rho = f.sum(axis=0)
+    mom = _momentum(p, f) + F / 2
+    ke = 0.5 * (mom ** 2).sum(axis=0) / rho
+    fe = p.a * psi ** 2 / 2 + p.b * psi ** 4 / 4 - 0.5 * p.kappa * psi * O.laplacian(p, psi)
+    return fe.sum() + ke.sum()
+
+
+@pytest.mark.parametrize("lattice,smol,shape", [(O.D2Q9, O.FD, (24, 24, 1)),
+                                                (O.D2Q9, O.FV, (24, 24, 1)),
+                                                (O.D3Q19, O.FD, (10, 10, 10)),
+                                                (O.D3Q19, O.FV, (10, 10, 10))])
+def test_force_sign_dissipates_energy(lattice, smol, shape):
+    p = O.make_params(lattice=lattice, smol=smol, shape=shape, a=-0.04, b=0.04, kappa=0.05,
+                      kT=0.0, M=0.0)
+    f, psi = O.init(p, 0, 0.5)
+    E = [_energy(p, f, psi)]
+    for n in range(150):
+        O.step(p, f, psi, n)
+        E.append(_energy(p, f, psi))
+    E = np.array(E)
+    assert np.all(np.diff(E) < 0)
+    assert E[-1] < 0.7 * E[0]

@@ -1,0 +1,67 @@
+"""Pins of the oracle's initial states and observables.
+
+* Two flat interfaces: psi = psi_eq [tanh((h - L/4)/l) - tanh((h - 3L/4)/l) - 1]
+  with psi_eq = sqrt(-A/B) and l = sqrt(-2K/A) (Eqs. tanh, intthick with A < 0).
+* The rest state is the second-order equilibrium: density rho0, velocity U.
+* Axis structure factors equal numpy's FFT of the field along the axes.
+* Totals equal direct sums.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+
+
+def test_tanh_two_interfaces():
+    p = O.make_params(lattice=O.D3Q19, shape=(4, 3, 40), a=-0.04, b=0.04, kappa=0.05)
+    f, psi = O.init(p, 1, 0.0)
+    h = np.arange(O.nsites(p)) // (p.nx * p.ny)
+    l = np.sqrt(2 * 0.05 / 0.04)
+    expect = np.tanh((h - 10) / l) - np.tanh((h - 30) / l) - 1
+    np.testing.assert_allclose(psi, expect, atol=1e-15)
+    assert abs(l - 1.5811388300841898) < 1e-15
+    p2 = O.make_params(lattice=O.D2Q9, shape=(5, 32, 1), a=-0.09, b=0.04, kappa=0.05)
+    _, psi2 = O.init(p2, 1, 0.0)
+    h2 = (np.arange(O.nsites(p2)) // p2.nx) % p2.ny
+    l2 = np.sqrt(2 * 0.05 / 0.09)
+    np.testing.assert_allclose(psi2, 1.5 * (np.tanh((h2 - 8) / l2) - np.tanh((h2 - 24) / l2) - 1),
+                               atol=1e-15)
+    with pytest.raises(ValueError):
+        O.init(O.make_params(a=0.04), 1, 0.0)
+
+
+def test_rest_state_and_noise():
+    p = O.make_params(lattice=O.D2Q9, shape=(64, 64, 1), rho0=1.2)
+    f, psi = O.init(p, 0, 1e-3, boost=(0.01, -0.02))
+    c, w = O.velocities(O.D2Q9)
+    rho = f.sum(0)
+    j = c[:, :2].T.astype(float) @ f
+    np.testing.assert_allclose(rho, 1.2, rtol=1e-15)
+    np.testing.assert_allclose(j[0], 1.2 * 0.01, rtol=1e-13)
+    np.testing.assert_allclose(j[1], -1.2 * 0.02, rtol=1e-13)
+    assert abs(psi.std() / 1e-3 - 1) < 0.05
+    assert abs(psi.mean()) < 5e-3 / 64
+    for s in (0, 17, 4095):
+        assert psi[s] == 1e-3 * O.normal(p.seed, s, 0, O.TAG_INIT, 0)
+
+
+def test_axis_spectrum_and_totals():
+    rng = np.random.default_rng(5)
+    p = O.make_params(lattice=O.D3Q19, shape=(7, 5, 6))
+    N = O.nsites(p)
+    field = rng.standard_normal(N)
+    S = O.axis_spectrum(p, field)
+    F = np.fft.fftn(field.reshape(6, 5, 7))
+    np.testing.assert_allclose(S[0][:7], np.abs(F[0, 0, :]) ** 2 / N, rtol=1e-12)
+    np.testing.assert_allclose(S[1][:5], np.abs(F[0, :, 0]) ** 2 / N, rtol=1e-12)
+    np.testing.assert_allclose(S[2][:6], np.abs(F[:, 0, 0]) ** 2 / N, rtol=1e-12)
+    f = rng.standard_normal((19, N))
+    t = O.totals(p, f, field)
+    c, _ = O.velocities(O.D3Q19)
+    j = c.T.astype(float) @ f
+    np.testing.assert_allclose(t[0], f.sum(), rtol=1e-12)
+    np.testing.assert_allclose(t[1:4], j.sum(1), rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(t[4], field.sum(), rtol=1e-12)
+    np.testing.assert_allclose(t[5], np.abs(f.sum(0)).sum(), rtol=1e-12)
+    np.testing.assert_allclose(t[6:9], np.abs(j).sum(1), rtol=1e-12)
+    np.testing.assert_allclose(t[9], np.abs(field).sum(), rtol=1e-12)
