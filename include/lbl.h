@@ -1,0 +1,199 @@
+/*
+ * lbl.h -- C ABI of the MI355X (gfx950) coupled lattice Boltzmann - Langevin
+ * sweep for model H.
+ *
+ * One simulation advances a binary fluid on a periodic D2Q9 or D3Q19 lattice
+ * by the hybrid scheme of Sumesh, Pagonabarraga & Adhikari (arXiv:1104.0078):
+ *   - momentum: fluctuating lattice Boltzmann (FLBE, Sec. IV and App. B),
+ *     multiple-relaxation-time collision with the force density
+ *     F = -psi grad mu and Landau-Lifshitz noise on every non-conserved mode;
+ *   - order parameter psi: stochastic method of lines (SMOL, Sec. V) with the
+ *     Landau chemical potential mu = A psi + B psi^3 - K lap psi (Sec. II.A),
+ *     advection by the LB velocity, diffusion M lap mu and a conserved
+ *     Langevin flux, in the finite-difference (Sec. V.A) or finite-volume
+ *     (Sec. V.B) variant, integrated by Runge-Kutta with the noise held
+ *     constant through the step.
+ * Lattice units: dx = dt = 1, c_s^2 = 1/3 (Sec. VI).
+ *
+ * Conventions shared by every entry point:
+ *   - Status codes: LBL_OK (0) or a negative lbl_status.  No C++ exception
+ *     crosses this boundary.
+ *   - Site index s = x + nx*(y + ny*z) with 0 <= x < nx etc.; 2-D lattices
+ *     have nz = 1.
+ *   - Populations are exchanged as "structure of arrays" FP64, element
+ *     [i*N + s] for velocity i in the canonical order
+ *       D2Q9 : 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1)
+ *              7:(-1,-1) 8:(1,-1)
+ *       D3Q19: 0:(0,0,0) 1:(1,0,0) 2:(-1,0,0) 3:(0,1,0) 4:(0,-1,0) 5:(0,0,1)
+ *              6:(0,0,-1) 7:(1,1,0) 8:(-1,-1,0) 9:(1,-1,0) 10:(-1,1,0)
+ *              11:(1,0,1) 12:(-1,0,-1) 13:(1,0,-1) 14:(-1,0,1) 15:(0,1,1)
+ *              16:(0,-1,-1) 17:(0,1,-1) 18:(0,-1,1)
+ *     and they are the auxiliary distribution fbar of Eq. (barreln) after
+ *     streaming, before collision, at the current step.
+ *   - Vector fields are [alpha*N + s].
+ *   - A simulation handle is not thread-safe; distinct handles are
+ *     independent.  All device work of a handle is ordered on its stream.
+ */
+#ifndef LBL_H
+#define LBL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBL_ABI_VERSION 1
+
+typedef struct lbl_sim lbl_sim;
+
+enum lbl_status {
+  LBL_OK = 0,
+  LBL_E_INVAL = -1,      /* invalid argument, parameter or combination */
+  LBL_E_NOMEM = -2,      /* device memory could not be obtained */
+  LBL_E_DEVICE = -3,     /* a HIP runtime call failed */
+  LBL_E_NONFINITE = -4,  /* a conserved total became NaN or infinite */
+  LBL_E_BUFSIZE = -5,    /* destination buffer smaller than the observable */
+  LBL_E_UNSUPPORTED = -6 /* observable not available for this simulation */
+};
+
+enum lbl_lattice { LBL_D2Q9 = 9, LBL_D3Q19 = 19 };
+enum lbl_smol { LBL_SMOL_FD = 0, LBL_SMOL_FV = 1 };
+enum lbl_precision {
+  LBL_FP64 = 0,   /* populations, psi and all arithmetic in FP64 */
+  LBL_FP32DEV = 1 /* populations stored as FP32 deviations fbar - w_i rho,
+                     psi in FP32, FP32 arithmetic; FP64 reductions */
+};
+enum lbl_coupling {
+  LBL_FULL = 0,      /* the coupled model H step */
+  LBL_SMOL_ONLY = 1, /* psi only, advected by the uniform u_imposed; fluid frozen
+                        ("diffusion alone" runs of Sec. VI) */
+  LBL_LB_ONLY = 2    /* fluctuating fluid only, no force, psi frozen */
+};
+
+/* Model H parameters (Sec. II) and numerical choices.
+ *   rho   : mean density rho0 (also the density in the noise amplitudes);
+ *   eta   : shear viscosity; the shear modes relax with
+ *           omega_s = 1 / (1/2 + eta / (rho c_s^2)), which must lie in (0, 2);
+ *   M     : mobility (Eq. advdiff);  a, b, kappa: A, B, K of Eqs. (Feng), (feng);
+ *   kT    : temperature in energy units (>= 0);
+ *   omega_bulk, omega_ghost : relaxation rates of the bulk stress mode and of
+ *           every ghost mode, in (0, 2]; 1 projects them onto equilibrium;
+ *   u_imposed: advecting velocity when coupling == LBL_SMOL_ONLY;
+ *   rk_stages: 1 (Euler), 2 (Heun, default) or 4 (classical RK4);
+ *   seed  : key of the Philox4x32-10 noise stream;
+ *   sample_every: if > 0, the axis structure factors are accumulated on the
+ *           device after every sample_every-th step (LBL_OBS_SK_AXES etc.). */
+typedef struct lbl_params {
+  int32_t lattice;   /* enum lbl_lattice */
+  int32_t smol;      /* enum lbl_smol */
+  int32_t precision; /* enum lbl_precision */
+  int32_t coupling;  /* enum lbl_coupling */
+  int32_t rk_stages;
+  int32_t nx, ny, nz; /* each >= 4; nz == 1 for D2Q9; N = nx*ny*nz < 2^31 */
+  double rho, eta, M, a, b, kappa, kT;
+  double omega_bulk, omega_ghost;
+  double u_imposed[3];
+  uint64_t seed;
+  int32_t sample_every;
+  int32_t reserved; /* must be 0 */
+} lbl_params;
+
+enum lbl_init_kind {
+  LBL_INIT_REST = 0,     /* fbar = equilibrium at (rho, boost_u); psi = psi_std * z */
+  LBL_INIT_TANH_2IF = 1, /* as REST, plus two flat tanh interfaces (Eqs. tanh,
+                            intthick) at L/4 and 3L/4 along the last axis;
+                            needs a < 0 < b and kappa > 0 */
+  LBL_INIT_USER = 2      /* fbar and psi copied from f0 and psi0 */
+};
+
+/* Initial state.  z is the normal of Philox slot 0, tag 2, step 0 at each
+ * site.  f0 (Q*N FP64, canonical order) and psi0 (N FP64) are read during
+ * lbl_create only; they are device pointers if user_on_device != 0. */
+typedef struct lbl_init {
+  int32_t kind;
+  int32_t user_on_device;
+  double psi_std;
+  double boost_u[3];
+  const double *psi0;
+  const double *f0;
+} lbl_init;
+
+/* Device memory and stream injection.  If alloc is NULL the library uses
+ * hipMalloc / hipFree.  alloc must return device memory valid on `stream`
+ * (NULL on failure); free receives the same ctx and stream.  stream is a
+ * hipStream_t (NULL selects the device's null stream). */
+typedef void *(*lbl_alloc_fn)(void *ctx, size_t bytes, void *stream);
+typedef void (*lbl_free_fn)(void *ctx, void *ptr, void *stream);
+typedef struct lbl_env {
+  int32_t device;
+  int32_t reserved;
+  void *stream;
+  lbl_alloc_fn alloc;
+  lbl_free_fn free;
+  void *ctx;
+} lbl_env;
+
+/* Create a simulation: validates the parameters, allocates its device state
+ * and writes the initial state (step 0) on env->stream.  On success *out owns
+ * the state until lbl_destroy; on failure *out is NULL and nothing leaks.
+ * Errors: LBL_E_INVAL (unknown enum, size out of range, omega outside (0,2),
+ * kT < 0, TANH_2IF without a < 0 < b, missing USER pointers), LBL_E_NOMEM,
+ * LBL_E_DEVICE. */
+int lbl_create(const lbl_params *params, const lbl_init *init, const lbl_env *env,
+               lbl_sim **out);
+
+/* Enqueue nsteps coupled steps (Sec. VI: FLBE and SMOL marched alternately)
+ * on the simulation's stream and return without waiting.  Step n draws the
+ * noise of counter step n.  Errors of earlier asynchronous work (including
+ * LBL_E_NONFINITE from the sampled totals) are reported by the next call that
+ * synchronises (lbl_observe).  nsteps < 0 gives LBL_E_INVAL. */
+int lbl_step(lbl_sim *sim, int64_t nsteps);
+
+enum lbl_observable {
+  LBL_OBS_PSI = 0,      /* N FP64: psi */
+  LBL_OBS_RHO = 1,      /* N FP64: rho = sum_i fbar_i */
+  LBL_OBS_U = 2,        /* d*N FP64: u = (sum_i fbar_i c_i + F/2)/rho, F = -psi grad mu
+                           (F = 0 for LB_ONLY; u_imposed for SMOL_ONLY) */
+  LBL_OBS_POP = 3,      /* Q*N FP64: fbar, canonical order */
+  LBL_OBS_TOTALS = 4,   /* 10 FP64: mass, Px, Py, Pz, Psi, then the L1 norms
+                           sum|rho|, sum|jx|, sum|jy|, sum|jz|, sum|psi|,
+                           with j = sum_i fbar_i c_i; reduced in FP64 */
+  LBL_OBS_SK_AXES = 5,  /* d*Lmax FP64, Lmax = max(nx,ny,nz): mean over samples of
+                           |sum_x psi e^{-i k x_alpha}|^2 / N at k = 2 pi m / L_alpha,
+                           element [alpha*Lmax + m] (0 beyond L_alpha) */
+  LBL_OBS_UK_AXES = 6,  /* d*d*Lmax FP64: the same for each velocity component beta,
+                           element [(alpha*d + beta)*Lmax + m] */
+  LBL_OBS_STEP = 7,     /* 1 int64: steps taken */
+  LBL_OBS_NSAMPLES = 8  /* 1 int64: samples accumulated into SK/UK */
+};
+
+/* Copy an observable of the current state into dst (host memory, or device
+ * memory if dst_is_device != 0).  Synchronises the simulation's stream first.
+ * The caller owns dst.  Errors: LBL_E_INVAL (unknown `what`, NULL dst),
+ * LBL_E_BUFSIZE (bytes too small), LBL_E_UNSUPPORTED, LBL_E_DEVICE, or a
+ * deferred error of earlier steps. */
+int lbl_observe(lbl_sim *sim, int what, void *dst, size_t bytes, int dst_is_device);
+
+/* Size in bytes of an observable for this simulation (0 for unknown `what`). */
+size_t lbl_observable_bytes(const lbl_sim *sim, int what);
+
+/* Release the simulation's device memory through the injected allocator
+ * (after its stream has drained).  NULL is accepted. */
+int lbl_destroy(lbl_sim *sim);
+
+/* Static text for a status code. */
+const char *lbl_strerror(int status);
+
+/* Text of the last error raised on this handle ("" if none).  With a NULL
+ * handle: the last error of a failed lbl_create on this thread. */
+const char *lbl_last_error(const lbl_sim *sim);
+
+/* LBL_ABI_VERSION of the loaded library. */
+int lbl_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBL_H */

@@ -1,0 +1,238 @@
+// lbl_device.hpp -- device-side building blocks of the gfx950 sweep:
+// lattice tables, the orthonormal mode basis (built at compile time), the
+// Philox4x32-10 counter generator with Box-Muller normals, and periodic
+// indexing.  Everything here is header-only and constexpr where possible so
+// that fully unrolled loops fold the tables into immediates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbl {
+
+constexpr double kCs2 = 1.0 / 3.0;  // c_s^2 for dx = dt = 1 (Sec. VI)
+
+// ---------------------------------------------------------------------------
+// Velocity sets in the canonical order of the C ABI.
+// ---------------------------------------------------------------------------
+template <int Q>
+struct Lat;
+
+template <>
+struct Lat<9> {
+  static constexpr int Q = 9, D = 2, NSTRESS = 3, NLINKS = 4;
+  static constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  static constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                  1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  // Monomials whose Gram-Schmidt orthonormalisation is the mode basis:
+  // 1, x, y, x^2+y^2, x^2-y^2, xy, xy^2, x^2y, x^2y^2.
+  static constexpr double mono(int k, double x, double y, double) {
+    return k == 0 ? 1.0 : k == 1 ? x : k == 2 ? y : k == 3 ? x * x + y * y
+         : k == 4 ? x * x - y * y : k == 5 ? x * y : k == 6 ? x * y * y
+         : k == 7 ? x * x * y : x * x * y * y;
+  }
+  // Undirected Laplacian links (first non-zero component +1), by |c|^2 then
+  // descending lexicographic order; weight 1/2 (|c|^2 = 1) or 1/4.
+  static constexpr int lx[4] = {1, 0, 1, 1};
+  static constexpr int ly[4] = {0, 1, 1, -1};
+  static constexpr int lz[4] = {0, 0, 0, 0};
+  static constexpr double lw[4] = {0.5, 0.5, 0.25, 0.25};
+};
+
+template <>
+struct Lat<19> {
+  static constexpr int Q = 19, D = 3, NSTRESS = 6, NLINKS = 13;
+  static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  static constexpr double w[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                                   1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  // 1, x, y, z, c^2, x^2, y^2, xy, xz, yz, xy^2, xz^2, yx^2, yz^2, zx^2, zy^2,
+  // x^2y^2, x^2z^2, y^2z^2.
+  static constexpr double mono(int k, double x, double y, double z) {
+    return k == 0 ? 1.0 : k == 1 ? x : k == 2 ? y : k == 3 ? z
+         : k == 4 ? x * x + y * y + z * z : k == 5 ? x * x : k == 6 ? y * y
+         : k == 7 ? x * y : k == 8 ? x * z : k == 9 ? y * z
+         : k == 10 ? x * y * y : k == 11 ? x * z * z : k == 12 ? y * x * x
+         : k == 13 ? y * z * z : k == 14 ? z * x * x : k == 15 ? z * y * y
+         : k == 16 ? x * x * y * y : k == 17 ? x * x * z * z : y * y * z * z;
+  }
+  // Shinozaki-Oono links: 6/22, 3/22, 1/22 by |c|^2 = 1, 2, 3.
+  static constexpr int lx[13] = {1, 0, 0, 1, 1, 1, 1, 0, 0, 1, 1, 1, 1};
+  static constexpr int ly[13] = {0, 1, 0, 1, 0, 0, -1, 1, 1, 1, 1, -1, -1};
+  static constexpr int lz[13] = {0, 0, 1, 0, 1, -1, 0, 1, -1, 1, -1, 1, -1};
+  static constexpr double lw[13] = {6.0 / 22, 6.0 / 22, 6.0 / 22, 3.0 / 22, 3.0 / 22,
+                                    3.0 / 22, 3.0 / 22, 3.0 / 22, 3.0 / 22, 1.0 / 22,
+                                    1.0 / 22, 1.0 / 22, 1.0 / 22};
+};
+
+// ---------------------------------------------------------------------------
+// Compile-time orthonormal mode basis: classical Gram-Schmidt of the
+// monomials under <a,b> = sum_i w_i a(c_i) b(c_i).  e[k][i] = e_k(c_i).
+// ---------------------------------------------------------------------------
+constexpr double ce_sqrt(double x) {
+  double r = x > 1.0 ? x : 1.0;
+  for (int it = 0; it < 200; ++it) r = 0.5 * (r + x / r);
+  return r;
+}
+
+template <int Q>
+struct Basis {
+  double e[Q][Q];
+};
+
+template <int Q>
+constexpr Basis<Q> make_basis() {
+  using L = Lat<Q>;
+  Basis<Q> B{};
+  for (int k = 0; k < Q; ++k) {
+    double m[Q] = {};
+    double v[Q] = {};
+    for (int i = 0; i < Q; ++i) {
+      m[i] = L::mono(k, L::cx[i], L::cy[i], L::cz[i]);
+      v[i] = m[i];
+    }
+    for (int l = 0; l < k; ++l) {
+      double pr = 0.0;
+      for (int i = 0; i < Q; ++i) pr += L::w[i] * m[i] * B.e[l][i];
+      for (int i = 0; i < Q; ++i) v[i] -= pr * B.e[l][i];
+    }
+    double n2 = 0.0;
+    for (int i = 0; i < Q; ++i) n2 += L::w[i] * v[i] * v[i];
+    double n = ce_sqrt(n2);
+    for (int i = 0; i < Q; ++i) B.e[k][i] = v[i] / n;
+  }
+  return B;
+}
+
+template <int Q>
+struct Modes {
+  static constexpr Basis<Q> B = make_basis<Q>();
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+// ---------------------------------------------------------------------------
+struct u32x4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c.x;
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c.z;
+    c = u32x4{static_cast<uint32_t>(p1 >> 32) ^ c.y ^ k0, static_cast<uint32_t>(p1),
+              static_cast<uint32_t>(p0 >> 32) ^ c.w ^ k1, static_cast<uint32_t>(p0)};
+  }
+  return c;
+}
+
+enum : uint32_t { kTagLB = 0, kTagSMOL = 1, kTagInit = 2 };
+
+// Four normals of Philox block (site, step, block, tag): uniforms
+// (x + 1/2) 2^-32, Box-Muller on (u0,u1) and (u2,u3).
+template <typename C>
+struct Normal4;
+
+template <>
+struct Normal4<double> {
+  __device__ __forceinline__ static void gen(uint32_t site, uint32_t step, uint32_t block,
+                                             uint32_t tag, uint32_t k0, uint32_t k1,
+                                             double z[4]) {
+    const u32x4 r = philox4x32_10(u32x4{site, step, block, tag}, k0, k1);
+    const double u0 = (static_cast<double>(r.x) + 0.5) * 0x1p-32;
+    const double u1 = (static_cast<double>(r.y) + 0.5) * 0x1p-32;
+    const double u2 = (static_cast<double>(r.z) + 0.5) * 0x1p-32;
+    const double u3 = (static_cast<double>(r.w) + 0.5) * 0x1p-32;
+    const double ra = sqrt(-2.0 * log(u0));
+    const double rb = sqrt(-2.0 * log(u2));
+    double sa, ca, sb, cb;
+    sincospi(2.0 * u1, &sa, &ca);
+    sincospi(2.0 * u3, &sb, &cb);
+    z[0] = ra * ca;
+    z[1] = ra * sa;
+    z[2] = rb * cb;
+    z[3] = rb * sb;
+  }
+  // Only the first pair (slots 0, 1 of the block).
+  __device__ __forceinline__ static void gen2(uint32_t site, uint32_t step, uint32_t block,
+                                              uint32_t tag, uint32_t k0, uint32_t k1,
+                                              double z[2]) {
+    const u32x4 r = philox4x32_10(u32x4{site, step, block, tag}, k0, k1);
+    const double u0 = (static_cast<double>(r.x) + 0.5) * 0x1p-32;
+    const double u1 = (static_cast<double>(r.y) + 0.5) * 0x1p-32;
+    const double ra = sqrt(-2.0 * log(u0));
+    double sa, ca;
+    sincospi(2.0 * u1, &sa, &ca);
+    z[0] = ra * ca;
+    z[1] = ra * sa;
+  }
+};
+
+template <>
+struct Normal4<float> {
+  __device__ __forceinline__ static float unif(uint32_t x) {
+    return fmaf(static_cast<float>(x), 0x1p-32f, 0x1p-33f);
+  }
+  __device__ __forceinline__ static void gen(uint32_t site, uint32_t step, uint32_t block,
+                                             uint32_t tag, uint32_t k0, uint32_t k1, float z[4]) {
+    const u32x4 r = philox4x32_10(u32x4{site, step, block, tag}, k0, k1);
+    const float ra = sqrtf(-2.0f * logf(unif(r.x)));
+    const float rb = sqrtf(-2.0f * logf(unif(r.z)));
+    float sa, ca, sb, cb;
+    sincospif(2.0f * unif(r.y), &sa, &ca);
+    sincospif(2.0f * unif(r.w), &sb, &cb);
+    z[0] = ra * ca;
+    z[1] = ra * sa;
+    z[2] = rb * cb;
+    z[3] = rb * sb;
+  }
+  __device__ __forceinline__ static void gen2(uint32_t site, uint32_t step, uint32_t block,
+                                              uint32_t tag, uint32_t k0, uint32_t k1,
+                                              float z[2]) {
+    const u32x4 r = philox4x32_10(u32x4{site, step, block, tag}, k0, k1);
+    const float ra = sqrtf(-2.0f * logf(unif(r.x)));
+    float sa, ca;
+    sincospif(2.0f * unif(r.y), &sa, &ca);
+    z[0] = ra * ca;
+    z[1] = ra * sa;
+  }
+};
+
+// Normal of one slot (used where only a single value of a block is needed).
+template <typename C>
+__device__ __forceinline__ C normal_slot(uint32_t site, uint32_t step, uint32_t slot,
+                                         uint32_t tag, uint32_t k0, uint32_t k1) {
+  C z[4];
+  Normal4<C>::gen(site, step, slot >> 2, tag, k0, k1, z);
+  const uint32_t lane = slot & 3u;
+  return lane == 0 ? z[0] : lane == 1 ? z[1] : lane == 2 ? z[2] : z[3];
+}
+
+// ---------------------------------------------------------------------------
+// Periodic lattice geometry.
+// ---------------------------------------------------------------------------
+struct Geom {
+  int nx, ny, nz;
+  int N;
+  __device__ __forceinline__ int wrapx(int x) const { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
+  __device__ __forceinline__ int wrapy(int y) const { return y < 0 ? y + ny : (y >= ny ? y - ny : y); }
+  __device__ __forceinline__ int wrapz(int z) const { return z < 0 ? z + nz : (z >= nz ? z - nz : z); }
+  __device__ __forceinline__ int idx(int x, int y, int z) const { return x + nx * (y + ny * z); }
+  // Site at (x+dx, y+dy, z+dz) for |d| <= 1 per axis (lattice sides >= 4).
+  __device__ __forceinline__ int nb(int x, int y, int z, int dx, int dy, int dz) const {
+    return idx(wrapx(x + dx), wrapy(y + dy), wrapz(z + dz));
+  }
+};
+
+}  // namespace lbl

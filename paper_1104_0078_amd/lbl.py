@@ -1,0 +1,275 @@
+"""Thin ctypes binding of the C ABI in include/lbl.h (liblbl.so, gfx950).
+
+Argument marshalling only: every step of the sweep runs in the HIP library.
+The functions ``lbl_create``, ``lbl_step``, ``lbl_observe``, ``lbl_destroy``,
+``lbl_strerror``, ``lbl_last_error``, ``lbl_abi_version`` and
+``lbl_observable_bytes`` mirror the C entry points.  ``Sim`` is a small
+convenience wrapper that takes its device memory from PyTorch's caching
+allocator and its stream from ``torch.cuda.current_stream()``.
+
+The library must have been built (``__graft_entry__.build()``); importing this
+module without it raises, and there is no fallback implementation.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbl.so")
+
+LBL_OK = 0
+LBL_E_INVAL, LBL_E_NOMEM, LBL_E_DEVICE = -1, -2, -3
+LBL_E_NONFINITE, LBL_E_BUFSIZE, LBL_E_UNSUPPORTED = -4, -5, -6
+LBL_D2Q9, LBL_D3Q19 = 9, 19
+LBL_SMOL_FD, LBL_SMOL_FV = 0, 1
+LBL_FP64, LBL_FP32DEV = 0, 1
+LBL_FULL, LBL_SMOL_ONLY, LBL_LB_ONLY = 0, 1, 2
+LBL_INIT_REST, LBL_INIT_TANH_2IF, LBL_INIT_USER = 0, 1, 2
+(LBL_OBS_PSI, LBL_OBS_RHO, LBL_OBS_U, LBL_OBS_POP, LBL_OBS_TOTALS, LBL_OBS_SK_AXES,
+ LBL_OBS_UK_AXES, LBL_OBS_STEP, LBL_OBS_NSAMPLES) = range(9)
+
+
+class lbl_params(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int32), ("smol", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("coupling", ctypes.c_int32), ("rk_stages", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("rho", ctypes.c_double), ("eta", ctypes.c_double), ("M", ctypes.c_double),
+        ("a", ctypes.c_double), ("b", ctypes.c_double), ("kappa", ctypes.c_double),
+        ("kT", ctypes.c_double), ("omega_bulk", ctypes.c_double),
+        ("omega_ghost", ctypes.c_double), ("u_imposed", ctypes.c_double * 3),
+        ("seed", ctypes.c_uint64), ("sample_every", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class lbl_init(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("user_on_device", ctypes.c_int32),
+        ("psi_std", ctypes.c_double), ("boost_u", ctypes.c_double * 3),
+        ("psi0", ctypes.POINTER(ctypes.c_double)), ("f0", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class lbl_env(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32), ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p),
+        ("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def library():
+    """Load liblbl.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "liblbl.so is not built (run __graft_entry__.build()); the sweep has no "
+                "fallback implementation")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.lbl_create.argtypes = [P(lbl_params), P(lbl_init), P(lbl_env), P(ctypes.c_void_p)]
+        L.lbl_create.restype = ctypes.c_int
+        L.lbl_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        L.lbl_step.restype = ctypes.c_int
+        L.lbl_observe.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_int]
+        L.lbl_observe.restype = ctypes.c_int
+        L.lbl_observable_bytes.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.lbl_observable_bytes.restype = ctypes.c_size_t
+        L.lbl_destroy.argtypes = [ctypes.c_void_p]
+        L.lbl_destroy.restype = ctypes.c_int
+        L.lbl_strerror.argtypes = [ctypes.c_int]
+        L.lbl_strerror.restype = ctypes.c_char_p
+        L.lbl_last_error.argtypes = [ctypes.c_void_p]
+        L.lbl_last_error.restype = ctypes.c_char_p
+        L.lbl_abi_version.argtypes = []
+        L.lbl_abi_version.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class LblError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (lbl_strerror(code), code, msg))
+        self.code = code
+
+
+def lbl_abi_version():
+    return library().lbl_abi_version()
+
+
+def lbl_strerror(code):
+    return library().lbl_strerror(code).decode()
+
+
+def lbl_last_error(sim=None):
+    return library().lbl_last_error(sim).decode()
+
+
+def lbl_create(params, init, env):
+    out = ctypes.c_void_p()
+    rc = library().lbl_create(ctypes.byref(params), ctypes.byref(init), ctypes.byref(env),
+                              ctypes.byref(out))
+    return rc, out
+
+
+def lbl_step(sim, nsteps):
+    return library().lbl_step(sim, nsteps)
+
+
+def lbl_observe(sim, what, dst_ptr, nbytes, dst_is_device):
+    return library().lbl_observe(sim, what, dst_ptr, nbytes, dst_is_device)
+
+
+def lbl_observable_bytes(sim, what):
+    return library().lbl_observable_bytes(sim, what)
+
+
+def lbl_destroy(sim):
+    return library().lbl_destroy(sim)
+
+
+def make_params(lattice=LBL_D2Q9, smol=LBL_SMOL_FD, precision=LBL_FP64, coupling=LBL_FULL,
+                rk_stages=2, shape=(64, 64, 1), rho=1.0, eta=0.1, M=0.1, a=0.04, b=0.1,
+                kappa=0.05, kT=1e-5, omega_bulk=1.0, omega_ghost=1.0, u_imposed=(0, 0, 0),
+                seed=1234, sample_every=0):
+    nx, ny, nz = (tuple(shape) + (1, 1, 1))[:3]
+    p = lbl_params()
+    p.lattice, p.smol, p.precision, p.coupling, p.rk_stages = (lattice, smol, precision,
+                                                               coupling, rk_stages)
+    p.nx, p.ny, p.nz = nx, ny, nz
+    p.rho, p.eta, p.M, p.a, p.b, p.kappa, p.kT = rho, eta, M, a, b, kappa, kT
+    p.omega_bulk, p.omega_ghost = omega_bulk, omega_ghost
+    for k in range(3):
+        p.u_imposed[k] = float(u_imposed[k])
+    p.seed = seed
+    p.sample_every = sample_every
+    p.reserved = 0
+    return p
+
+
+def make_init(kind=LBL_INIT_REST, psi_std=1e-3, boost=(0, 0, 0), f0=None, psi0=None):
+    """f0 (q, N) and psi0 (N,) float64 numpy arrays for LBL_INIT_USER."""
+    ini = lbl_init()
+    ini.kind = kind
+    ini.user_on_device = 0
+    ini.psi_std = psi_std
+    for k in range(3):
+        ini.boost_u[k] = float(boost[k]) if k < len(boost) else 0.0
+    keep = []
+    if kind == LBL_INIT_USER:
+        f0 = np.ascontiguousarray(f0, dtype=np.float64)
+        psi0 = np.ascontiguousarray(psi0, dtype=np.float64)
+        keep = [f0, psi0]
+        ini.f0 = f0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        ini.psi0 = psi0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    ini._keep = keep
+    return ini
+
+
+class TorchMemory:
+    """lbl_env callbacks backed by torch's caching allocator on one device."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+
+        def _alloc(ctx, nbytes, stream):
+            try:
+                return self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device,
+                                                               self.stream)
+            except RuntimeError:
+                return None
+
+        def _free(ctx, ptr, stream):
+            self.torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+
+    def env(self):
+        e = lbl_env()
+        e.device = self.device
+        e.stream = self.stream.cuda_stream
+        e.alloc = self._alloc
+        e.free = self._free
+        e.ctx = None
+        return e
+
+
+class Sim:
+    """One simulation handle on one GPU (device memory from torch)."""
+
+    def __init__(self, params, init=None, device=0, stream=None, memory=None):
+        self.params = params
+        self.init = init if init is not None else make_init()
+        self.memory = memory if memory is not None else TorchMemory(device, stream)
+        self.env = self.memory.env()
+        rc, h = lbl_create(params, self.init, self.env)
+        if rc != LBL_OK:
+            raise LblError(rc, lbl_last_error(None))
+        self.handle = h
+        self.d = 2 if params.lattice == LBL_D2Q9 else 3
+        self.q = params.lattice
+        self.N = params.nx * params.ny * params.nz
+
+    def step(self, nsteps=1):
+        rc = lbl_step(self.handle, nsteps)
+        if rc != LBL_OK:
+            raise LblError(rc, lbl_last_error(self.handle))
+
+    def observe(self, what):
+        nbytes = lbl_observable_bytes(self.handle, what)
+        if what in (LBL_OBS_STEP, LBL_OBS_NSAMPLES):
+            out = np.zeros(1, dtype=np.int64)
+        else:
+            out = np.zeros(nbytes // 8, dtype=np.float64)
+        rc = lbl_observe(self.handle, what, out.ctypes.data, nbytes, 0)
+        if rc != LBL_OK:
+            raise LblError(rc, lbl_last_error(self.handle))
+        if what == LBL_OBS_POP:
+            return out.reshape(self.q, self.N)
+        if what == LBL_OBS_U:
+            return out.reshape(self.d, self.N)
+        if what in (LBL_OBS_STEP, LBL_OBS_NSAMPLES):
+            return int(out[0])
+        return out
+
+    def observe_into(self, what, tensor):
+        """Write an observable into a torch CUDA tensor (float64/int64) on the device."""
+        nbytes = lbl_observable_bytes(self.handle, what)
+        if tensor.numel() * tensor.element_size() < nbytes:
+            raise ValueError("tensor too small")
+        rc = lbl_observe(self.handle, what, tensor.data_ptr(), tensor.numel() *
+                         tensor.element_size(), 1)
+        if rc != LBL_OK:
+            raise LblError(rc, lbl_last_error(self.handle))
+        return tensor
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lbl_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,96 @@
+"""The C-ABI library loads, exports every entry point that include/lbl.h
+declares, matches the header's struct layout, and rejects invalid parameters
+before touching a device.  No compute call is made (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1104_0078_amd import lbl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbl.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(lbl_\w+)\s*\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert {"lbl_create", "lbl_step", "lbl_observe", "lbl_destroy"} <= set(names)
+    L = lbl.library()
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", lbl.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (lbl_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "lbl.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(lbl_params), offsetof(lbl_params, rho),
+         offsetof(lbl_params, seed), offsetof(lbl_params, sample_every), sizeof(lbl_init),
+         offsetof(lbl_init, f0));
+  printf("%zu %zu %zu\n", sizeof(lbl_env), offsetof(lbl_env, stream), offsetof(lbl_env, ctx));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    a, b = subprocess.run([str(exe)], capture_output=True, text=True,
+                          check=True).stdout.split("\n")[:2]
+    P, I, E = lbl.lbl_params, lbl.lbl_init, lbl.lbl_env
+    assert [int(v) for v in a.split()] == [ctypes.sizeof(P), P.rho.offset, P.seed.offset,
+                                           P.sample_every.offset, ctypes.sizeof(I), I.f0.offset]
+    assert [int(v) for v in b.split()] == [ctypes.sizeof(E), E.stream.offset, E.ctx.offset]
+
+
+def test_constants_and_strings():
+    assert lbl.lbl_abi_version() == 1
+    assert lbl.lbl_strerror(0) == "ok"
+    assert "buffer" in lbl.lbl_strerror(lbl.LBL_E_BUFSIZE)
+    assert lbl.lbl_strerror(12345) == "unknown status"
+
+
+@pytest.mark.parametrize("field,value", [
+    ("lattice", 15), ("smol", 2), ("precision", 3), ("coupling", 7), ("rk_stages", 3),
+    ("nx", 3), ("nz", 2), ("eta", -1.0), ("rho", 0.0), ("kT", -1e-5), ("omega_bulk", 2.5),
+    ("omega_ghost", 0.0), ("M", float("nan")), ("reserved", 1), ("sample_every", -2),
+])
+def test_invalid_parameters_rejected(field, value):
+    p = lbl.make_params(lattice=lbl.LBL_D3Q19, shape=(8, 8, 8))
+    setattr(p, field, value)
+    rc, h = lbl.lbl_create(p, lbl.make_init(), lbl.lbl_env())
+    assert rc == lbl.LBL_E_INVAL
+    assert not h.value
+    assert lbl.lbl_last_error(None)
+
+
+def test_invalid_init_rejected():
+    p = lbl.make_params(lattice=lbl.LBL_D2Q9, shape=(8, 8, 1), a=0.04)
+    rc, _ = lbl.lbl_create(p, lbl.make_init(kind=lbl.LBL_INIT_TANH_2IF), lbl.lbl_env())
+    assert rc == lbl.LBL_E_INVAL and "a < 0" in lbl.lbl_last_error(None)
+    ini = lbl.make_init(kind=lbl.LBL_INIT_USER, f0=[0.0], psi0=[0.0])
+    ini.f0 = None
+    rc, _ = lbl.lbl_create(p, ini, lbl.lbl_env())
+    assert rc == lbl.LBL_E_INVAL
+    p2 = lbl.make_params(lattice=lbl.LBL_D2Q9, shape=(8, 8, 2))
+    rc, _ = lbl.lbl_create(p2, lbl.make_init(), lbl.lbl_env())
+    assert rc == lbl.LBL_E_INVAL
+
+
+def test_null_handles():
+    assert lbl.lbl_destroy(None) == 0
+    assert lbl.lbl_step(None, 1) == lbl.LBL_E_INVAL
+    assert lbl.lbl_observe(None, 0, None, 0, 0) == lbl.LBL_E_INVAL

@@ -1,0 +1,120 @@
+"""GPU parity: the HIP sweep against the FP64 oracle, element by element, on
+the same seeded inputs and the same Philox stream.
+
+Sizes span several thread blocks and end in a ragged tail.  Bar: FP64 fields
+within 1e-12 and FP32-deviation fields within 1e-5 of the oracle, relative to
+the largest magnitude of the oracle field.
+"""
+import numpy as np
+import pytest
+
+from tests import harness as H
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = {H.D2Q9: (70, 45, 1), H.D3Q19: (21, 13, 11)}
+
+
+def _gpu(c, nsteps, init=None):
+    from paper_1104_0078_amd import lbl
+    ini = init if init is not None else lbl.make_init(kind=c["init"], psi_std=c["psi_std"],
+                                                      boost=c["boost"])
+    with lbl.Sim(H.lbl_params(c), ini) as sim:
+        sim.step(nsteps)
+        return sim.observe(lbl.LBL_OBS_POP), sim.observe(lbl.LBL_OBS_PSI), sim
+
+
+def _check(c, nsteps, tol=None):
+    print("parity case:", c, "steps", nsteps, flush=True)
+    f_gpu, psi_gpu, _ = _gpu(c, nsteps)
+    f_ref, psi_ref = H.oracle_run(c, nsteps)
+    tol = tol if tol is not None else H.TOL[c["precision"]]
+    ef, ep = H.rel_err(f_gpu, f_ref), H.rel_err(psi_gpu, psi_ref)
+    print("  rel err populations %.3e psi %.3e" % (ef, ep), flush=True)
+    assert ef <= tol and ep <= tol
+
+
+@pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q19])
+@pytest.mark.parametrize("smol", [H.FD, H.FV])
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
+def test_coupled_one_phase(lattice, smol, precision):
+    c = H.config(lattice=lattice, smol=smol, precision=precision, shape=SHAPES[lattice])
+    _check(c, 20)
+
+
+@pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q19])
+@pytest.mark.parametrize("smol", [H.FD, H.FV])
+def test_coupled_two_phase_tanh(lattice, smol):
+    c = H.config(lattice=lattice, smol=smol, shape=SHAPES[lattice], a=-0.04, b=0.04,
+                 kappa=0.05, init=1, kT=1e-5)
+    _check(c, 20)
+
+
+@pytest.mark.parametrize("coupling", [H.SMOL_ONLY, H.LB_ONLY])
+@pytest.mark.parametrize("rk", [1, 2, 4])
+def test_partial_couplings_and_stages(coupling, rk):
+    c = H.config(lattice=H.D2Q9, smol=H.FV, coupling=coupling, rk=rk, shape=(70, 45, 1),
+                 u_imposed=(0.03, -0.02, 0.0), kT=1e-4)
+    _check(c, 15)
+
+
+def test_mrt_rates_and_boost():
+    c = H.config(lattice=H.D3Q19, smol=H.FV, shape=SHAPES[H.D3Q19], omega_bulk=1.3,
+                 omega_ghost=0.8, eta=0.05, boost=(0.02, -0.01, 0.015), kT=1e-4)
+    _check(c, 15)
+
+
+def test_user_init_roundtrip():
+    from paper_1104_0078_amd import lbl
+    import oracle as O
+    from tests import inputs
+    c = H.config(lattice=H.D3Q19, smol=H.FD, shape=SHAPES[H.D3Q19], kT=1e-5)
+    p = H.oracle_params(c)
+    _, w = O.velocities(H.D3Q19)
+    N = O.nsites(p)
+    f0 = inputs.perturbed_populations(w, N, 0.05, seed=3)
+    psi0 = inputs.random_field(N, 0.02, seed=4)
+    ini = lbl.make_init(kind=lbl.LBL_INIT_USER, f0=f0, psi0=psi0)
+    with lbl.Sim(H.lbl_params(c), ini) as sim:
+        np.testing.assert_array_equal(sim.observe(lbl.LBL_OBS_POP), f0)
+        np.testing.assert_array_equal(sim.observe(lbl.LBL_OBS_PSI), psi0)
+        sim.step(10)
+        f_gpu, psi_gpu = sim.observe(lbl.LBL_OBS_POP), sim.observe(lbl.LBL_OBS_PSI)
+    f, psi = f0.copy(), psi0.copy()
+    O.run(p, f, psi, 0, 10)
+    assert H.rel_err(f_gpu, f) < 1e-12 and H.rel_err(psi_gpu, psi) < 1e-12
+
+
+@pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q19])
+def test_observables_match_oracle(lattice):
+    from paper_1104_0078_amd import lbl
+    import oracle as O
+    c = H.config(lattice=lattice, smol=H.FV, shape=SHAPES[lattice], a=-0.04, b=0.04, init=1)
+    p = H.oracle_params(c)
+    with lbl.Sim(H.lbl_params(c), lbl.make_init(kind=1, psi_std=1e-3)) as sim:
+        sim.step(5)
+        rho = sim.observe(lbl.LBL_OBS_RHO)
+        u = sim.observe(lbl.LBL_OBS_U)
+        tot = sim.observe(lbl.LBL_OBS_TOTALS)
+        assert sim.observe(lbl.LBL_OBS_STEP) == 5
+    f, psi = H.oracle_run(c, 5)
+    assert H.rel_err(rho, f.sum(0)) < 1e-13
+    uref = O.velocity(p, f, O.force(p, psi))
+    assert H.rel_err(u, uref) < 1e-11
+    tref = O.totals(p, f, psi)
+    np.testing.assert_allclose(tot, tref, rtol=1e-12, atol=1e-13 * tref[5])
+
+
+@pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q19])
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
+def test_conservation_on_gpu(lattice, precision):
+    from paper_1104_0078_amd import lbl
+    c = H.config(lattice=lattice, smol=H.FV, precision=precision, shape=SHAPES[lattice],
+                 a=-0.04, b=0.04, init=1, kT=1e-5)
+    with lbl.Sim(H.lbl_params(c), lbl.make_init(kind=1, psi_std=1e-3)) as sim:
+        t0 = sim.observe(lbl.LBL_OBS_TOTALS)
+        sim.step(100)
+        t1 = sim.observe(lbl.LBL_OBS_TOTALS)
+    tol = 1e-13 if precision == H.FP64 else 1e-6
+    assert abs(t1[0] - t0[0]) <= tol * t0[5]
+    assert abs(t1[4] - t0[4]) <= tol * t0[9]
