@@ -183,6 +183,20 @@ size_t lbl_observable_bytes(const lbl_sim *sim, int what);
  * (after its stream has drained).  NULL is accepted. */
 int lbl_destroy(lbl_sim *sim);
 
+/* Per-kernel timing with HIP events recorded on the simulation's stream
+ * around every kernel that lbl_step launches.  lbl_timing_enable(sim, 1)
+ * clears the accumulators and starts recording; 0 stops.  lbl_timing_read
+ * synchronises the stream and writes up to max_entries records (one per
+ * kernel name, in first-launch order) and their count to *n_entries.
+ * Errors: LBL_E_INVAL (NULL pointers), LBL_E_DEVICE. */
+typedef struct lbl_kernel_time {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+} lbl_kernel_time;
+int lbl_timing_enable(lbl_sim *sim, int enable);
+int lbl_timing_read(lbl_sim *sim, lbl_kernel_time *out, int max_entries, int *n_entries);
+
 /* Static text for a status code. */
 const char *lbl_strerror(int status);
 

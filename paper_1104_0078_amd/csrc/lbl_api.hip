@@ -41,7 +41,6 @@ struct lbl_sim {
   void* phi[2] = {nullptr, nullptr};
   void* acc = nullptr;
   void* mu = nullptr;
-  void* gmu = nullptr;
   void* u = nullptr;
   void* noise = nullptr;
   double* part = nullptr;
@@ -50,9 +49,19 @@ struct lbl_sim {
   int64_t step = 0;
   int64_t nsamples = 0;
   uint32_t k0 = 0, k1 = 0;
+  int zc = 1;  // planes per block of the z-marching kernels
   double gamma_s = 0, gamma_b = 0, gamma_g = 0, sigma_s = 0, sigma_b = 0, sigma_g = 0;
   int deferred = LBL_OK;
   std::string err;
+  // Event timing of step kernels.
+  bool timing = false;
+  struct Pending {
+    int slot;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<lbl_kernel_time> kt;
 };
 
 namespace {
@@ -110,6 +119,71 @@ void release_all(lbl_sim* s) {
 }
 
 inline int grid_for(int n) { return (n + kBlock - 1) / kBlock; }
+
+hipEvent_t take_event(lbl_sim* s) {
+  if (!s->event_pool.empty()) {
+    hipEvent_t e = s->event_pool.back();
+    s->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int kernel_slot(lbl_sim* s, const char* name) {
+  for (size_t k = 0; k < s->kt.size(); ++k)
+    if (std::strncmp(s->kt[k].name, name, sizeof(s->kt[k].name)) == 0) return static_cast<int>(k);
+  lbl_kernel_time t{};
+  std::strncpy(t.name, name, sizeof(t.name) - 1);
+  s->kt.push_back(t);
+  return static_cast<int>(s->kt.size()) - 1;
+}
+
+// Launch `fn` (a kernel launch on s->stream), bracketed by timing events when
+// timing is enabled, and check the launch.
+template <class Fn>
+int launch(lbl_sim* s, const char* name, Fn&& fn) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (s->timing) {
+    a = take_event(s);
+    b = take_event(s);
+    if (a) (void)hipEventRecord(a, s->stream);
+  }
+  fn();
+  const hipError_t e = hipGetLastError();
+  if (s->timing && a && b) {
+    (void)hipEventRecord(b, s->stream);
+    s->pending.push_back(lbl_sim::Pending{kernel_slot(s, name), a, b});
+  }
+  return hip_check(s, e, name);
+}
+
+int drain_timing(lbl_sim* s) {
+  if (s->pending.empty()) return LBL_OK;
+  if (int rc = hip_check(s, hipStreamSynchronize(s->stream), "timing sync")) return rc;
+  for (auto& p : s->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      s->kt[p.slot].total_ms += ms;
+      s->kt[p.slot].launches += 1;
+    }
+    s->event_pool.push_back(p.a);
+    s->event_pool.push_back(p.b);
+  }
+  s->pending.clear();
+  return LBL_OK;
+}
+
+void destroy_events(lbl_sim* s) {
+  for (auto& p : s->pending) {
+    s->event_pool.push_back(p.a);
+    s->event_pool.push_back(p.b);
+  }
+  s->pending.clear();
+  for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+  s->event_pool.clear();
+}
 
 bool finite_all(const lbl_params& p) {
   const double v[] = {p.rho, p.eta, p.M, p.a, p.b, p.kappa, p.kT, p.omega_bulk, p.omega_ghost,
@@ -224,7 +298,7 @@ struct Impl {
   }
 
   static LBArgs<S> lb_args(lbl_sim* s, const S* fin, S* fout, const S* psi, S* u_out,
-                           int force, int collide, uint32_t step) {
+                           int force, uint32_t step) {
     LBArgs<S> a;
     a.g = geom(s);
     a.f_in = fin;
@@ -244,74 +318,117 @@ struct Impl {
     a.step = step;
     a.force = force;
     a.noise = s->p.kT > 0;
-    a.collide = collide;
     return a;
+  }
+
+  static dim3 site_grid(const lbl_sim* s) {
+    return dim3((s->p.nx + kBX - 1) / kBX, (s->p.ny + kBY - 1) / kBY, s->p.nz);
+  }
+  static dim3 tile_grid(const lbl_sim* s) {
+    return dim3((s->p.nx + kTX - 1) / kTX, (s->p.ny + kTY - 1) / kTY,
+                Lat<Q>::D == 3 ? (s->p.nz + s->zc - 1) / s->zc : 1);
+  }
+
+  static int launch_lb(lbl_sim* s, const LBArgs<S>& a, bool collide) {
+    const dim3 grid = site_grid(s), block(kBX, kBY);
+    const bool ghost = s->gamma_g != 0.0;
+    if (!collide)
+      return launch(s, "k_lb_u", [&] {
+        k_lb<S, DEV, Q, SMOL, false, false><<<grid, block, 0, s->stream>>>(a);
+      });
+    if (ghost)
+      return launch(s, "k_lb", [&] {
+        k_lb<S, DEV, Q, SMOL, true, true><<<grid, block, 0, s->stream>>>(a);
+      });
+    return launch(s, "k_lb", [&] {
+      k_lb<S, DEV, Q, SMOL, false, true><<<grid, block, 0, s->stream>>>(a);
+    });
+  }
+
+  static int launch_mu(lbl_sim* s, const S* phi, S* mu) {
+    const dim3 grid = site_grid(s), block(kBX, kBY);
+    const Geom g = geom(s);
+    const Coef<S> c = coef(s);
+    return launch(s, "k_mu", [&] { k_mu<S, Q><<<grid, block, 0, s->stream>>>(g, c, phi, mu); });
   }
 
   static int one_step(lbl_sim* s) {
     const Geom g = geom(s);
-    const int grid = grid_for(s->N);
     const uint32_t n = static_cast<uint32_t>(s->step);
     const int cpl = s->p.coupling;
     S* fin = static_cast<S*>(s->f[s->cur]);
     S* fout = static_cast<S*>(s->f[1 - s->cur]);
     S* psin = static_cast<S*>(s->psi[s->pcur]);
     S* psout = static_cast<S*>(s->psi[1 - s->pcur]);
-    S* mu = static_cast<S*>(s->mu);
     S* u = static_cast<S*>(s->u);
 
-    if (cpl != LBL_LB_ONLY) {
-      k_mu<S, Q><<<grid, kBlock, 0, s->stream>>>(g, coef(s), psin, mu);
-      if (int rc = launched(s, "k_mu")) return rc;
+    S* noise = static_cast<S*>(s->noise);
+    const dim3 tg = tile_grid(s), tb(kTX, kTY);
+    const bool want_noise = cpl != LBL_LB_ONLY && s->p.kT > 0;
+    const bool want_mu = cpl == LBL_FULL;
+    if (want_noise || want_mu) {
+      PrepArgs<S> pa;
+      pa.g = g;
+      pa.c = coef(s);
+      pa.amp = S(std::sqrt(2.0 * s->p.kT * s->p.M));
+      pa.k0 = s->k0;
+      pa.k1 = s->k1;
+      pa.step = n;
+      pa.zc = s->zc;
+      pa.psi = psin;
+      pa.noise = want_noise ? noise : nullptr;
+      pa.mu = want_mu ? static_cast<S*>(s->mu) : nullptr;
+      int rc;
+      if (SMOL == kFV)
+        rc = launch(s, "k_prep", [&] { k_prep_fv<S, Q><<<tg, tb, 0, s->stream>>>(pa); });
+      else
+        rc = launch(s, "k_prep", [&] { k_prep_fd<S, Q><<<tg, tb, 0, s->stream>>>(pa); });
+      if (rc) return rc;
     }
     if (cpl != LBL_SMOL_ONLY) {
-      LBArgs<S> a = lb_args(s, fin, fout, psin, cpl == LBL_FULL ? u : nullptr,
-                            cpl == LBL_FULL, 1, n);
-      k_lb<S, DEV, Q, SMOL><<<grid, kBlock, 0, s->stream>>>(a);
-      if (int rc = launched(s, "k_lb")) return rc;
+      const LBArgs<S> a = lb_args(s, fin, fout, psin, cpl == LBL_FULL ? u : nullptr,
+                                  cpl == LBL_FULL, n);
+      if (int rc = launch_lb(s, a, true)) return rc;
     }
     if (cpl != LBL_LB_ONLY) {
-      S* noise = static_cast<S*>(s->noise);
-      if (s->p.kT > 0) {
-        const S amp = S(std::sqrt(2.0 * s->p.kT * s->p.M));
-        k_smol_noise<S, Q, SMOL><<<grid, kBlock, 0, s->stream>>>(g, amp, s->k0, s->k1, n, noise);
-        if (int rc = launched(s, "k_smol_noise")) return rc;
-      }
       const int ns = s->p.rk_stages;
-      static const double cn2[2] = {1.0, 0.0}, ca2[2] = {0.5, 0.5};
       static const double cn4[4] = {0.5, 0.5, 1.0, 0.0};
       static const double ca4[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
       const S* phi = psin;
       for (int st = 0; st < ns; ++st) {
-        if (st > 0) {
-          k_mu<S, Q><<<grid, kBlock, 0, s->stream>>>(g, coef(s), phi, mu);
-          if (int rc = launched(s, "k_mu")) return rc;
-        }
-        if (SMOL == kFV) {
-          k_grad_fv<S, Q><<<grid, kBlock, 0, s->stream>>>(g, mu, static_cast<S*>(s->gmu));
-          if (int rc = launched(s, "k_grad_fv")) return rc;
-        }
         StageArgs<S> a;
         a.g = g;
         a.c = coef(s);
         a.phi = phi;
-        a.mu = mu;
-        a.gmu = static_cast<const S*>(s->gmu);
         a.u = cpl == LBL_FULL ? u : nullptr;
         a.u0 = S(s->p.u_imposed[0]);
         a.u1 = S(s->p.u_imposed[1]);
         a.u2 = S(Lat<Q>::D == 3 ? s->p.u_imposed[2] : 0.0);
         a.noise = noise;
         a.psi_n = psin;
-        a.acc = static_cast<S*>(s->acc);
         a.first = st == 0;
         a.last = st == ns - 1;
-        a.cnext = S(ns == 1 ? 0.0 : (ns == 2 ? cn2[st] : cn4[st]));
-        a.cacc = S(ns == 1 ? 1.0 : (ns == 2 ? ca2[st] : ca4[st]));
-        a.next = a.last ? psout : static_cast<S*>(s->phi[st & 1]);
-        k_smol_stage<S, Q, SMOL><<<grid, kBlock, 0, s->stream>>>(a);
-        if (int rc = launched(s, "k_smol_stage")) return rc;
-        phi = a.next;
+        a.zc = s->zc;
+        a.acc = nullptr;
+        a.cacc = S(0);
+        a.cnext = S(1);
+        a.mode = kComb;
+        if (ns == 2 && st == 1) a.mode = kHeun2;
+        if (ns == 4) {
+          a.acc = static_cast<S*>(s->acc);
+          a.cnext = S(cn4[st]);
+          a.cacc = S(ca4[st]);
+        }
+        a.out = a.last ? psout : static_cast<S*>(s->phi[st & 1]);
+        int rc;
+        if (SMOL == kFV)
+          rc = launch(s, "k_stage",
+                      [&] { k_stage_fv<S, Q><<<tg, tb, 0, s->stream>>>(a); });
+        else
+          rc = launch(s, "k_stage",
+                      [&] { k_stage_fd<S, Q><<<tg, tb, 0, s->stream>>>(a); });
+        if (rc) return rc;
+        phi = a.out;
       }
       s->pcur = 1 - s->pcur;
     }
@@ -346,13 +463,10 @@ struct Impl {
         if (s->p.coupling == LBL_SMOL_ONLY) return LBL_E_UNSUPPORTED;
         S* ubuf = static_cast<S*>(s->u);
         const int full = s->p.coupling == LBL_FULL;
-        if (full) {
-          k_mu<S, Q><<<grid, kBlock, 0, s->stream>>>(g, coef(s), psi, static_cast<S*>(s->mu));
-          if (int rc = launched(s, "k_mu")) return rc;
-        }
-        LBArgs<S> a = lb_args(s, f, nullptr, psi, ubuf, full, 0, 0);
-        k_lb<S, DEV, Q, SMOL><<<grid, kBlock, 0, s->stream>>>(a);
-        if (int rc = launched(s, "k_lb(u)")) return rc;
+        if (full)
+          if (int rc = launch_mu(s, psi, static_cast<S*>(s->mu))) return rc;
+        const LBArgs<S> a = lb_args(s, f, nullptr, psi, ubuf, full, 0);
+        if (int rc = launch_lb(s, a, false)) return rc;
         k_to_f64<S><<<grid_for(s->d * s->N), kBlock, 0, s->stream>>>(s->d * s->N, ubuf, dst);
         return launched(s, "k_to_f64");
       }
@@ -479,9 +593,15 @@ int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* e
   s->phi[1] = A(sz * N);
   s->acc = A(sz * N);
   s->mu = A(sz * N);
-  s->gmu = A(sz * N * s->d);
   s->u = A(sz * N * s->d);
   s->noise = A(sz * N);
+  // z-chunk of the tiled SMOL kernels: at least ~2048 blocks when possible.
+  {
+    const int bxy = ((params->nx + kTX - 1) / kTX) * ((params->ny + kTY - 1) / kTY);
+    int zc = params->nz;
+    while (zc > 8 && bxy * ((params->nz + zc - 1) / zc) < 2048) zc = (zc + 1) / 2;
+    s->zc = std::max(1, zc);
+  }
   s->nparts = std::min(1024, std::max(1, grid_for(s->N)));
   s->part = static_cast<double*>(A(sizeof(double) * 10 * s->nparts));
   s->tot = static_cast<double*>(A(sizeof(double) * 16));
@@ -601,9 +721,34 @@ int lbl_observe(lbl_sim* sim, int what, void* dst, size_t bytes, int dst_is_devi
   }
 }
 
+int lbl_timing_enable(lbl_sim* sim, int enable) {
+  if (!sim) return LBL_E_INVAL;
+  if (int rc = hip_check(sim, hipSetDevice(sim->device), "hipSetDevice")) return rc;
+  if (int rc = drain_timing(sim)) return rc;
+  for (auto& t : sim->kt) {
+    t.launches = 0;
+    t.total_ms = 0.0;
+  }
+  sim->kt.clear();
+  sim->timing = enable != 0;
+  return LBL_OK;
+}
+
+int lbl_timing_read(lbl_sim* sim, lbl_kernel_time* out, int max_entries, int* n_entries) {
+  if (!sim || !n_entries || (max_entries > 0 && !out)) return LBL_E_INVAL;
+  if (int rc = hip_check(sim, hipSetDevice(sim->device), "hipSetDevice")) return rc;
+  if (int rc = drain_timing(sim)) return rc;
+  const int n = static_cast<int>(sim->kt.size());
+  for (int k = 0; k < n && k < max_entries; ++k) out[k] = sim->kt[k];
+  *n_entries = n;
+  return LBL_OK;
+}
+
 int lbl_destroy(lbl_sim* sim) {
   if (!sim) return LBL_OK;
   if (sim->stream || !sim->owned.empty()) (void)hipSetDevice(sim->device);
+  (void)hipStreamSynchronize(sim->stream);
+  destroy_events(sim);
   release_all(sim);
   delete sim;
   return LBL_OK;

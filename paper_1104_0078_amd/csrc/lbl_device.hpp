@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
 
 namespace lbl {
 
@@ -114,6 +115,67 @@ template <int Q>
 struct Modes {
   static constexpr Basis<Q> B = make_basis<Q>();
 };
+
+// Every basis vector is a scale times a vector of small integers:
+// e_k(c_i) = scale[k] * I[k][i].  Kernels project with the integers (inline
+// constants) and one multiply by the scale per mode.
+template <int Q>
+struct IntBasis {
+  double scale[Q];
+  int I[Q][Q];
+};
+
+constexpr double ce_abs(double v) { return v < 0 ? -v : v; }
+constexpr int ce_round(double v) { return v >= 0 ? static_cast<int>(v + 0.5) : -static_cast<int>(-v + 0.5); }
+
+template <int Q>
+constexpr IntBasis<Q> make_int_basis() {
+  const Basis<Q> B = make_basis<Q>();
+  IntBasis<Q> R{};
+  for (int k = 0; k < Q; ++k) {
+    double mn = 1e300;
+    for (int i = 0; i < Q; ++i)
+      if (ce_abs(B.e[k][i]) > 1e-9 && ce_abs(B.e[k][i]) < mn) mn = ce_abs(B.e[k][i]);
+    R.scale[k] = mn;
+    for (int i = 0; i < Q; ++i) R.I[k][i] = ce_round(B.e[k][i] / mn);
+  }
+  return R;
+}
+
+template <int Q>
+constexpr double int_basis_error() {
+  const Basis<Q> B = make_basis<Q>();
+  const IntBasis<Q> R = make_int_basis<Q>();
+  double err = 0.0;
+  for (int k = 0; k < Q; ++k)
+    for (int i = 0; i < Q; ++i) {
+      const double e = ce_abs(B.e[k][i] - R.scale[k] * R.I[k][i]);
+      if (e > err) err = e;
+    }
+  return err;
+}
+
+template <int Q>
+struct IntModes {
+  static constexpr IntBasis<Q> B = make_int_basis<Q>();
+  static_assert(int_basis_error<Q>() < 1e-13, "mode basis is not scale x integers");
+};
+
+// Entries as variable templates: always compile-time constants in kernels.
+template <int Q, int K, int I>
+inline constexpr int kIB = IntModes<Q>::B.I[K][I];
+template <int Q, int K>
+inline constexpr double kSB = IntModes<Q>::B.scale[K];
+
+// Compile-time loop: f(std::integral_constant<int, 0>{}) ... f(<N-1>).
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).

@@ -1,10 +1,18 @@
 // lbl_kernels.hpp -- gfx950 kernels of the coupled FLBE + SMOL step.
 //
 // Storage type S is double (FP64 path) or float (FP32-deviation path, where
-// populations hold fbar_i - w_i rho0).  Arithmetic runs in S.  One thread
-// updates one site; neighbour values come through L1/L2.  Populations are
-// structure-of-arrays: f[i*N + s].  The stored population buffer holds the
-// post-collision values f*^{n-1}; step n pulls fbar^n(x) = f*^{n-1}(x - c_i).
+// populations hold fbar_i - w_i rho0).  Arithmetic runs in S.
+//
+// Per step (full coupling):
+//   k_mu        mu(psi^n)                                    one thread/site
+//   k_lb        pull-stream, force -psi grad mu, MRT collision with noise,
+//               writes f*^n and u^n                          one thread/site
+//   k_noise_*   SMOL noise N^n, each site's normals drawn once, neighbours
+//               shared through LDS (z-marching tiles)
+//   k_stage_*   one Runge-Kutta stage: phi -> mu(phi) -> fluxes -> divergence,
+//               all in LDS (z-marching tiles)
+// Populations are structure-of-arrays f[i*N + s]; the stored buffer holds the
+// post-collision values f*^{n-1} and step n pulls fbar^n(x) = f*^{n-1}(x - c_i).
 #pragma once
 
 #include "lbl_device.hpp"
@@ -18,14 +26,56 @@ struct Coef {
   S a, b, kappa, M;
 };
 
+// Thread-block shape of the per-site kernels: 64 sites along x (one
+// wavefront, contiguous in memory) by 4 rows.
+constexpr int kBX = 64, kBY = 4;
+// Tile of the z-marching stencil kernels.
+constexpr int kTX = 32, kTY = 8;
+
+// Periodic neighbourhood of one site: wrapped coordinates and row offsets.
+struct Nbr {
+  int xs[3];
+  int rows[3][3];  // rows[dy+1][dz+1] = nx * (y+dy + ny * (z+dz))
+  __device__ __forceinline__ Nbr(const Geom& g, int x, int y, int z) {
+    xs[0] = x == 0 ? g.nx - 1 : x - 1;
+    xs[1] = x;
+    xs[2] = x == g.nx - 1 ? 0 : x + 1;
+    const int ys[3] = {y == 0 ? g.ny - 1 : y - 1, y, y == g.ny - 1 ? 0 : y + 1};
+    const int zs[3] = {z == 0 ? g.nz - 1 : z - 1, z, z == g.nz - 1 ? 0 : z + 1};
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int zr = g.ny * zs[b];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) rows[a][b] = g.nx * (ys[a] + zr);
+    }
+  }
+  __device__ __forceinline__ int at(int dx, int dy, int dz) const {
+    return xs[dx + 1] + rows[dy + 1][dz + 1];
+  }
+};
+
+__device__ __forceinline__ int wrap_any(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// Periodic wrap of a tile-region coordinate v in [-halo, start + tile + halo):
+// one conditional add or subtract when the side n is at least tile + halo
+// (`near`, uniform per launch), a modulo otherwise.
+__device__ __forceinline__ int wrap_r(int v, int n, bool near) {
+  if (near) return v < 0 ? v + n : (v >= n ? v - n : v);
+  return wrap_any(v, n);
+}
+
 // ---------------------------------------------------------------------------
 // Chemical potential mu = A phi + B phi^3 - K L_SO phi  (Sec. II.A; the
 // Shinozaki-Oono Laplacian of Eq. (solap) in 3-D, its 2-D analogue in 2-D).
+// `at(dx,dy,dz)` returns phi at the offset.
 // ---------------------------------------------------------------------------
-template <typename S, int Q>
-__device__ __forceinline__ S lap_so(const S* __restrict__ f, const Geom& g, int x, int y, int z) {
+template <typename S, int D, class At>
+__device__ __forceinline__ S lap_so(At&& at) {
   S s1 = 0, s2 = 0, s3 = 0;
-  if constexpr (Q == 19) {
+  if constexpr (D == 3) {
 #pragma unroll
     for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
@@ -34,13 +84,13 @@ __device__ __forceinline__ S lap_so(const S* __restrict__ f, const Geom& g, int 
         for (int dx = -1; dx <= 1; ++dx) {
           const int r2 = dx * dx + dy * dy + dz * dz;
           if (r2 == 0) continue;
-          const S v = f[g.nb(x, y, z, dx, dy, dz)];
+          const S v = at(dx, dy, dz);
           if (r2 == 1) s1 += v;
           else if (r2 == 2) s2 += v;
           else s3 += v;
         }
     return S(6.0 / 22.0) * s1 + S(3.0 / 22.0) * s2 + S(1.0 / 22.0) * s3 -
-           S(80.0 / 22.0) * f[g.idx(x, y, z)];
+           S(80.0 / 22.0) * at(0, 0, 0);
   } else {
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy)
@@ -48,47 +98,29 @@ __device__ __forceinline__ S lap_so(const S* __restrict__ f, const Geom& g, int 
       for (int dx = -1; dx <= 1; ++dx) {
         const int r2 = dx * dx + dy * dy;
         if (r2 == 0) continue;
-        const S v = f[g.nb(x, y, 0, dx, dy, 0)];
+        const S v = at(dx, dy, 0);
         if (r2 == 1) s1 += v;
         else s2 += v;
       }
-    return S(0.5) * s1 + S(0.25) * s2 - S(3.0) * f[g.idx(x, y, 0)];
+    return S(0.5) * s1 + S(0.25) * s2 - S(3.0) * at(0, 0, 0);
   }
+}
+
+template <typename S, int D, class At>
+__device__ __forceinline__ S chem_pot(const Coef<S>& c, At&& at) {
+  const S p = at(0, 0, 0);
+  return c.a * p + c.b * p * p * p - c.kappa * lap_so<S, D>(at);
 }
 
 template <typename S, int Q>
-__global__ __launch_bounds__(256) void k_mu(Geom g, Coef<S> c, const S* __restrict__ phi,
-                                            S* __restrict__ mu) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.N) return;
-  const int x = s % g.nx, y = (s / g.nx) % g.ny, z = s / (g.nx * g.ny);
-  const S p = phi[s];
-  mu[s] = c.a * p + c.b * p * p * p - c.kappa * lap_so<S, Q>(phi, g, x, y, z);
-}
-
-// Gradient of a scalar at (x,y,z): FD central difference (Sec. IV) or the FV
-// Gamma operator (1/c_s^2) sum_i w_i c_i v(x + c_i)  (Eq. fvgrad).
-template <typename S, int Q, int SMOL>
-__device__ __forceinline__ void grad(const S* __restrict__ v, const Geom& g, int x, int y, int z,
-                                     S out[3]) {
-  using L = Lat<Q>;
-  if constexpr (SMOL == kFD) {
-    out[0] = S(0.5) * (v[g.nb(x, y, z, 1, 0, 0)] - v[g.nb(x, y, z, -1, 0, 0)]);
-    out[1] = S(0.5) * (v[g.nb(x, y, z, 0, 1, 0)] - v[g.nb(x, y, z, 0, -1, 0)]);
-    out[2] = L::D == 3 ? S(0.5) * (v[g.nb(x, y, z, 0, 0, 1)] - v[g.nb(x, y, z, 0, 0, -1)]) : S(0);
-  } else {
-    S gx = 0, gy = 0, gz = 0;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const S t = S(L::w[i]) * v[g.nb(x, y, z, L::cx[i], L::cy[i], L::cz[i])];
-      if (L::cx[i]) gx += L::cx[i] * t;
-      if (L::cy[i]) gy += L::cy[i] * t;
-      if (L::cz[i]) gz += L::cz[i] * t;
-    }
-    out[0] = S(3) * gx;
-    out[1] = S(3) * gy;
-    out[2] = S(3) * gz;
-  }
+__global__ __launch_bounds__(kBX* kBY) void k_mu(Geom g, Coef<S> c, const S* __restrict__ phi,
+                                                 S* __restrict__ mu) {
+  const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const Nbr nb(g, x, y, z);
+  mu[nb.at(0, 0, 0)] =
+      chem_pot<S, Lat<Q>::D>(c, [&](int dx, int dy, int dz) { return phi[nb.at(dx, dy, dz)]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -108,34 +140,75 @@ struct LBArgs {
   uint32_t k0, k1, step;
   int force;  // 0: F = 0 (LB_ONLY)
   int noise;  // 0: kT == 0
-  int collide;  // 0: only compute u (observe)
 };
 
-template <typename S, bool DEV, int Q, int SMOL>
-__global__ __launch_bounds__(256) void k_lb(LBArgs<S> a) {
+// GHOST: the ghost modes keep gamma_g m_g (omega_ghost != 1).
+// COLLIDE: false computes only u (observable).
+template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool COLLIDE>
+__global__ __launch_bounds__(kBX* kBY) void k_lb(LBArgs<S> a) {
   using L = Lat<Q>;
   constexpr int D = L::D;
   constexpr int NR = Q - D - 1;
   constexpr int NB = (NR + 3) / 4;
   const Geom& g = a.g;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.N) return;
-  const int x = s % g.nx, y = (s / g.nx) % g.ny, z = s / (g.nx * g.ny);
+  const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const Nbr nb(g, x, y, z);
+  const int s = nb.at(0, 0, 0);
 
+  // Noise of the non-conserved modes, drawn first: n_k = sigma_k z_k, with
+  // sigma_k^2 = (1 - gamma_k^2) rho0 kT / c_s^2 per mode class.
+  S nk[NB * 4];
+#pragma unroll
+  for (int k = 0; k < NB * 4; ++k) nk[k] = 0;
+  if (COLLIDE && a.noise) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      S z4[4];
+      Normal4<S>::gen(static_cast<uint32_t>(s), a.step, b, kTagLB, a.k0, a.k1, z4);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const int k = 4 * b + l;
+        if (k >= NR) continue;
+        const S sig = k == 0 ? a.sigma_b : (k < L::NSTRESS ? a.sigma_s : a.sigma_g);
+        nk[k] = sig * z4[l];
+      }
+    }
+  }
+
+  // Force density F = -psi grad mu: FD central difference (Sec. IV) or the FV
+  // gradient (1/c_s^2) sum_i w_i c_i mu(x + c_i) (Eq. fvgrad).
   S F[3] = {0, 0, 0};
   if (a.force) {
-    S gm[3];
-    grad<S, Q, SMOL>(a.mu, g, x, y, z, gm);
+    const S* __restrict__ mu = a.mu;
+    S gx = 0, gy = 0, gz = 0;
+    if constexpr (SMOL == kFD) {
+      gx = S(0.5) * (mu[nb.at(1, 0, 0)] - mu[nb.at(-1, 0, 0)]);
+      gy = S(0.5) * (mu[nb.at(0, 1, 0)] - mu[nb.at(0, -1, 0)]);
+      if (D == 3) gz = S(0.5) * (mu[nb.at(0, 0, 1)] - mu[nb.at(0, 0, -1)]);
+    } else {
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const S t = S(L::w[i]) * mu[nb.at(L::cx[i], L::cy[i], L::cz[i])];
+        if (L::cx[i]) gx += L::cx[i] * t;
+        if (L::cy[i]) gy += L::cy[i] * t;
+        if (L::cz[i]) gz += L::cz[i] * t;
+      }
+      gx *= S(3);
+      gy *= S(3);
+      gz *= S(3);
+    }
     const S ps = a.psi[s];
-    F[0] = -ps * gm[0];
-    F[1] = -ps * gm[1];
-    F[2] = -ps * gm[2];
+    F[0] = -ps * gx;
+    F[1] = -ps * gy;
+    F[2] = -ps * gz;
   }
 
   S fv[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    fv[i] = a.f_in[static_cast<size_t>(i) * g.N + g.nb(x, y, z, -L::cx[i], -L::cy[i], -L::cz[i])];
+    fv[i] = a.f_in[static_cast<size_t>(i) * g.N + nb.at(-L::cx[i], -L::cy[i], -L::cz[i])];
 
   S S0 = 0, jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
 #pragma unroll
@@ -162,7 +235,24 @@ __global__ __launch_bounds__(256) void k_lb(LBArgs<S> a) {
     a.u_out[g.N + s] = uy;
     if (D == 3) a.u_out[2 * g.N + s] = uz;
   }
-  if (!a.collide) return;
+  if constexpr (!COLLIDE) return;
+
+  // Ghost moments scaled by their integer basis: m_k / scale_k.
+  S ghost[NR > 0 ? NR : 1];
+  if constexpr (GHOST) {
+    static_for<NR>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      if constexpr (k >= L::NSTRESS) {
+        S m = 0;
+        static_for<Q>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+          constexpr int c = kIB<Q, D + 1 + k, i>;
+          if constexpr (c != 0) m += S(c) * fv[i];
+        });
+        ghost[k] = m;
+      }
+    });
+  }
 
   // Stress Pi = sum fbar Q = sum fbar c c - c_s^2 S0 I, its non-equilibrium part
   // and the Guo source T = uF + Fu, split into isotropic (bulk) and deviatoric
@@ -176,7 +266,7 @@ __global__ __launch_bounds__(256) void k_lb(LBArgs<S> a) {
   const S nyz = D == 3 ? pyz - rho * uy * uz : S(0);
   const S txx = S(2) * ux * F[0], tyy = S(2) * uy * F[1], tzz = S(2) * uz * F[2];
   const S txy = ux * F[1] + F[0] * uy, txz = ux * F[2] + F[0] * uz, tyz = uy * F[2] + F[1] * uz;
-  const S invD = S(1) / S(D);
+  constexpr S invD = S(1.0 / D);
   const S ntr = (nxx + nyy + nzz) * invD;
   const S ttr = (txx + tyy + tzz) * invD;
   const S hs = S(0.5) * (S(1) + a.gamma_s), hb = S(0.5) * (S(1) + a.gamma_b);
@@ -190,194 +280,464 @@ __global__ __launch_bounds__(256) void k_lb(LBArgs<S> a) {
   const S qtr = qxx + qyy + qzz;
   const S jsx = jx + F[0], jsy = jy + F[1], jsz = jz + F[2];
 
-  // Amplitudes n_k of the non-conserved modes k = D+1 .. Q-1: noise, plus the
-  // surviving ghost part gamma_g m_g.
-  constexpr auto& E = Modes<Q>::B.e;
-  S nk[NB * 4];
-#pragma unroll
-  for (int k = 0; k < NB * 4; ++k) nk[k] = 0;
-  if (a.noise) {
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      S z4[4];
-      Normal4<S>::gen(static_cast<uint32_t>(s), a.step, b, kTagLB, a.k0, a.k1, z4);
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        const int k = 4 * b + l;
-        const S sig = k == 0 ? a.sigma_b : (k < L::NSTRESS ? a.sigma_s : a.sigma_g);
-        nk[k] = sig * z4[l];
-      }
-    }
-  }
-  if (a.gamma_g != S(0)) {
-#pragma unroll
-    for (int k = L::NSTRESS; k < NR; ++k) {
-      S m = 0;
-#pragma unroll
-      for (int i = 0; i < Q; ++i)
-        if (E[D + 1 + k][i] != 0.0) m += S(E[D + 1 + k][i]) * fv[i];
-      nk[k] += a.gamma_g * m;
-    }
-  }
+  // Scale the amplitudes into integer-basis units (and add gamma_g m_g).
+  static_for<NR>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    constexpr double sc = kSB<Q, D + 1 + k>;
+    if constexpr (GHOST && k >= L::NSTRESS)
+      nk[k] = S(sc) * (nk[k] + a.gamma_g * (S(sc) * ghost[k]));
+    else
+      nk[k] = S(sc) * nk[k];
+  });
 
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
+  static_for<Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
     S cj = 0;
-    if (cx) cj += cx * jsx;
-    if (cy) cj += cy * jsy;
-    if (cz) cj += cz * jsz;
+    if constexpr (cx != 0) cj += S(cx) * jsx;
+    if constexpr (cy != 0) cj += S(cy) * jsy;
+    if constexpr (cz != 0) cj += S(cz) * jsz;
     S pq = -S(kCs2) * qtr;
-    if (cx) pq += qxx;
-    if (cy) pq += qyy;
-    if (cz) pq += qzz;
-    if (cx * cy) pq += S(2 * cx * cy) * qxy;
-    if (cx * cz) pq += S(2 * cx * cz) * qxz;
-    if (cy * cz) pq += S(2 * cy * cz) * qyz;
+    if constexpr (cx != 0) pq += qxx;
+    if constexpr (cy != 0) pq += qyy;
+    if constexpr (cz != 0) pq += qzz;
+    if constexpr (cx * cy != 0) pq += S(2 * cx * cy) * qxy;
+    if constexpr (cx * cz != 0) pq += S(2 * cx * cz) * qxz;
+    if constexpr (cy * cz != 0) pq += S(2 * cy * cz) * qyz;
     S nz = 0;
-#pragma unroll
-    for (int k = 0; k < NR; ++k)
-      if (E[D + 1 + k][i] != 0.0) nz += S(E[D + 1 + k][i]) * nk[k];
-    a.f_out[static_cast<size_t>(i) * g.N + s] = S(L::w[i]) * (S0 + S(3) * cj + S(4.5) * pq + nz);
-  }
+    static_for<NR>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      constexpr int c = kIB<Q, D + 1 + k, i>;
+      if constexpr (c != 0) nz += S(c) * nk[k];
+    });
+    a.f_out[static_cast<size_t>(i) * g.N + s] =
+        S(L::w[i]) * (S0 + S(3) * cj + S(4.5) * pq + nz);
+  });
 }
 
 // ---------------------------------------------------------------------------
-// SMOL noise term N^n, frozen over the Runge-Kutta stages (Sec. V).
-// FD: link fluxes, N(x) = sum_l A_l [zeta_l(x - c_l) - zeta_l(x)],
-//     A_l = sqrt(2 kT M lambda_l): the Gaussian law of Eq. (etafdt) built in
-//     real space.  FV: N = Gamma . xi, xi_a = sqrt(2 kT M) z_a (Eqs. fvdiff,
-//     noiseflux, fdt_orderpara).
+// z-marching tiles.  A block of kTX x kTY threads owns the columns
+// [x0, x0+kTX) x [y0, y0+kTY) and the planes [z0, z1); plane-sized regions
+// with an xy halo live in LDS rings indexed by plane.  Every global access
+// is to a wrapped (periodic) coordinate.
 // ---------------------------------------------------------------------------
-template <typename S, int Q, int SMOL>
-__global__ __launch_bounds__(256) void k_smol_noise(Geom g, S amp, uint32_t k0, uint32_t k1,
-                                                    uint32_t step, S* __restrict__ out) {
+template <int W, int H>
+struct Region {
+  static constexpr int size = W * H;
+};
+
+__device__ __forceinline__ int ring(int p, int n) { return ((p % n) + n) % n; }
+
+// ---------------------------------------------------------------------------
+// Per-step preparation, z-marching: the SMOL noise N^n (Sec. V), frozen over
+// the Runge-Kutta stages, and the chemical potential mu(psi^n) that the LB
+// force needs.  Either part can be switched off (noise when kT = 0, mu when
+// the fluid is not forced).
+// ---------------------------------------------------------------------------
+template <typename S>
+struct PrepArgs {
+  Geom g;
+  Coef<S> c;
+  S amp;           // sqrt(2 kT M)
+  uint32_t k0, k1, step;
+  int zc;
+  const S* psi;    // psi^n
+  S* noise;        // N^n, or nullptr
+  S* mu;           // mu(psi^n), or nullptr
+};
+
+// psi ring for mu: region with halo 1, 4 planes.
+template <typename S, int D>
+struct PsiRing {
+  static constexpr int W = kTX + 2, H = kTY + 2, RS = W * H;
+  static constexpr int NRING = D == 3 ? 4 : 1;
+  S v[NRING][RS];
+};
+
+template <typename S, int D>
+__device__ __forceinline__ void prep_load_psi(PsiRing<S, D>& r, const PrepArgs<S>& a, int p,
+                                              int x0, int y0, bool near, int tid) {
+  using R = PsiRing<S, D>;
+  const Geom& g = a.g;
+  const int slot = ring(p, R::NRING), pz = wrap_any(p, g.nz);
+  for (int e = tid; e < R::RS; e += kTX * kTY) {
+    const int i = e % R::W, j = e / R::W;
+    const int gx = wrap_r(x0 - 1 + i, g.nx, near), gy = wrap_r(y0 - 1 + j, g.ny, near);
+    r.v[slot][e] = a.psi[gx + g.nx * (gy + g.ny * pz)];
+  }
+}
+
+template <typename S, int D>
+__device__ __forceinline__ void prep_mu(const PsiRing<S, D>& r, const PrepArgs<S>& a, int t,
+                                        int x0, int y0, int tx, int ty) {
+  using R = PsiRing<S, D>;
+  const Geom& g = a.g;
+  const int x = x0 + tx, y = y0 + ty;
+  if (x >= g.nx || y >= g.ny) return;
+  a.mu[x + g.nx * (y + g.ny * t)] = chem_pot<S, D>(a.c, [&](int dx, int dy, int dz) {
+    return r.v[ring(t + dz, R::NRING)][(tx + 1 + dx) + R::W * (ty + 1 + dy)];
+  });
+}
+
+// FV noise (Eqs. fvdiff, noiseflux, fdt_orderpara): node noise xi_a = amp z_a
+// and N = Gamma . xi with Gamma = (1/c_s^2) sum_i w_i c_i.
+template <typename S, int Q>
+__global__ __launch_bounds__(kTX* kTY) void k_prep_fv(PrepArgs<S> a) {
   using L = Lat<Q>;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.N) return;
-  const int x = s % g.nx, y = (s / g.nx) % g.ny, z = s / (g.nx * g.ny);
-  S acc = 0;
-  if constexpr (SMOL == kFD) {
-    constexpr int NL = L::NLINKS;
-    constexpr int NB = (NL + 3) / 4;
-    S own[NB * 4];
+  constexpr int D = L::D;
+  constexpr int W = kTX + 2, H = kTY + 2, RS = W * H;
+  constexpr int NRING = D == 3 ? 4 : 1;
+  __shared__ S xi[NRING][D][RS];
+  __shared__ PsiRing<S, D> pr;
+  const Geom& g = a.g;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
+  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
+  const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
+  const int z0 = D == 3 ? blockIdx.z * a.zc : 0, z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
+  auto gen = [&](int p) {  // xi on plane p, region with halo 1
+    const int slot = ring(p, NRING), pz = wrap_any(p, g.nz);
+    for (int e = tid; e < RS; e += kTX * kTY) {
+      const int i = e % W, j = e / W;
+      const int gx = wrap_r(x0 - 1 + i, g.nx, near), gy = wrap_r(y0 - 1 + j, g.ny, near);
+      const uint32_t site = static_cast<uint32_t>(gx + g.nx * (gy + g.ny * pz));
+      S zz[4];
+      if constexpr (D == 2)
+        Normal4<S>::gen2(site, a.step, 0, kTagSMOL, a.k0, a.k1, zz);
+      else
+        Normal4<S>::gen(site, a.step, 0, kTagSMOL, a.k0, a.k1, zz);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) Normal4<S>::gen(s, step, b, kTagSMOL, k0, k1, own + 4 * b);
-#pragma unroll
-    for (int l = 0; l < NL; ++l) {
-      const int back = g.nb(x, y, z, -L::lx[l], -L::ly[l], -L::lz[l]);
-      const S zb = normal_slot<S>(static_cast<uint32_t>(back), step, l, kTagSMOL, k0, k1);
-      acc += amp * sqrt(S(L::lw[l])) * (zb - own[l]);
+      for (int c = 0; c < D; ++c) xi[slot][c][e] = zz[c];
     }
-  } else {
-    S gx = 0, gy = 0, gz = 0;
+  };
+  auto div = [&](int t) {
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= g.nx || y >= g.ny) return;
+    S acc = 0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const int t = g.nb(x, y, z, L::cx[i], L::cy[i], L::cz[i]);
-      S xi[4];
-      if constexpr (L::D == 2) {
-        Normal4<S>::gen2(t, step, 0, kTagSMOL, k0, k1, xi);
-      } else {
-        Normal4<S>::gen(t, step, 0, kTagSMOL, k0, k1, xi);
-      }
-      if (L::cx[i]) gx += S(L::w[i] * L::cx[i]) * xi[0];
-      if (L::cy[i]) gy += S(L::w[i] * L::cy[i]) * xi[1];
-      if (L::D == 3 && L::cz[i]) gz += S(L::w[i] * L::cz[i]) * xi[2];
+      const int slot = ring(t + L::cz[i], NRING);
+      const int e = (tx + 1 + L::cx[i]) + W * (ty + 1 + L::cy[i]);
+      S v = 0;
+      if (L::cx[i]) v += L::cx[i] * xi[slot][0][e];
+      if (L::cy[i]) v += L::cy[i] * xi[slot][1][e];
+      if (D == 3 && L::cz[i]) v += L::cz[i] * xi[slot][D - 1][e];
+      acc += S(L::w[i]) * v;
     }
-    acc = S(3) * amp * (gx + gy + gz);
+    a.noise[x + g.nx * (y + g.ny * t)] = S(3) * a.amp * acc;
+  };
+  if constexpr (D == 2) {
+    if (a.noise) gen(0);
+    if (a.mu) prep_load_psi<S, D>(pr, a, 0, x0, y0, near, tid);
+    __syncthreads();
+    if (a.noise) div(0);
+    if (a.mu) prep_mu<S, D>(pr, a, 0, x0, y0, tx, ty);
+  } else {
+    for (int t = z0 - 2; t < z1; ++t) {
+      if (a.noise) gen(t + 1);
+      if (a.mu) prep_load_psi<S, D>(pr, a, t + 1, x0, y0, near, tid);
+      __syncthreads();
+      if (t >= z0) {
+        if (a.noise) div(t);
+        if (a.mu) prep_mu<S, D>(pr, a, t, x0, y0, tx, ty);
+      }
+    }
   }
-  out[s] = acc;
 }
 
-// FV: g = Gamma mu on every site (needed at neighbours by the diffusion term).
+// FD noise (Sec. V.A, reading): one flux zeta_l per undirected Laplacian link,
+// amplitude A_l = amp sqrt(lambda_l), N(x) = sum_l A_l [zeta_l(x - c_l) - zeta_l(x)].
+// Each plane's link normals are drawn once into LDS; every thread accumulates
+// its site's sums for planes p-1, p, p+1 in registers.
 template <typename S, int Q>
-__global__ __launch_bounds__(256) void k_grad_fv(Geom g, const S* __restrict__ mu,
-                                                 S* __restrict__ out) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.N) return;
-  const int x = s % g.nx, y = (s / g.nx) % g.ny, z = s / (g.nx * g.ny);
-  S v[3];
-  grad<S, Q, kFV>(mu, g, x, y, z, v);
-  out[s] = v[0];
-  out[g.N + s] = v[1];
-  if (Lat<Q>::D == 3) out[2 * g.N + s] = v[2];
+__global__ __launch_bounds__(kTX* kTY) void k_prep_fd(PrepArgs<S> a) {
+  using L = Lat<Q>;
+  constexpr int D = L::D;
+  constexpr int NL = L::NLINKS;
+  constexpr int NB = (NL + 3) / 4;
+  constexpr int W = kTX + 1, H = kTY + 2, RS = W * H;  // x in [x0-1, x0+kTX), y in [y0-1, y0+kTY]
+  __shared__ S zeta[NL][RS];
+  __shared__ PsiRing<S, D> pr;
+  const Geom& g = a.g;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
+  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
+  const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
+  const int z0 = D == 3 ? blockIdx.z * a.zc : 0, z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool live = x < g.nx && y < g.ny;
+  S A[NL];
+  static_for<NL>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    constexpr double r = ce_sqrt(L::lw[l]);
+    A[l] = a.amp * S(r);
+  });
+  S nm = 0, n0 = 0, np = 0;  // partial N for planes p-1, p, p+1
+  const int pbeg = D == 3 ? z0 - 1 : 0, pend = D == 3 ? z1 : 0;
+  for (int p = pbeg; p <= pend; ++p) {
+    const int pz = wrap_any(p, g.nz);
+    if (a.noise) {
+      for (int e = tid; e < RS; e += kTX * kTY) {
+        const int i = e % W, j = e / W;
+        const int gx = wrap_r(x0 - 1 + i, g.nx, near), gy = wrap_r(y0 - 1 + j, g.ny, near);
+        const uint32_t site = static_cast<uint32_t>(gx + g.nx * (gy + g.ny * pz));
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          S zz[4];
+          Normal4<S>::gen(site, a.step, b, kTagSMOL, a.k0, a.k1, zz);
+#pragma unroll
+          for (int l = 0; l < 4; ++l)
+            if (4 * b + l < NL) zeta[4 * b + l][e] = zz[l];
+        }
+      }
+    }
+    if (a.mu) prep_load_psi<S, D>(pr, a, p, x0, y0, near, tid);
+    __syncthreads();
+    if (a.mu && (D == 2 || (p - 1 >= z0 && p - 1 < z1)))
+      prep_mu<S, D>(pr, a, D == 2 ? 0 : p - 1, x0, y0, tx, ty);
+    if (live && a.noise) {
+      const int own = (tx + 1) + W * (ty + 1);
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        n0 -= A[l] * zeta[l][own];
+        const S in = A[l] * zeta[l][(tx + 1 - L::lx[l]) + W * (ty + 1 - L::ly[l])];
+        if (L::lz[l] == 0) n0 += in;
+        else if (L::lz[l] > 0) np += in;
+        else nm += in;
+      }
+      if (D == 2) {
+        a.noise[x + g.nx * y] = n0;
+      } else {
+        if (p - 1 >= z0 && p - 1 < z1) a.noise[x + g.nx * (y + g.ny * (p - 1))] = nm;
+        nm = n0;
+        n0 = np;
+        np = 0;
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
-// One Runge-Kutta stage of SMOL with frozen u and N (Sec. V):
-//   G(phi) = -Div(u phi) + M L_out mu(phi) + N,
-// FD: Div central, L_out = L_SO.  FV: Div = Gamma., L_out mu = Gamma.(Gamma mu).
-// Then  next = psi^n + cnext G,  acc = (first ? 0 : acc) + cacc G,
-// and on the last stage out = psi^n + acc_prev + cacc G.
+// One SMOL Runge-Kutta stage with frozen u^n and N^n (Sec. V):
+//   G(phi) = -Div(u phi) + M L_out mu(phi) + N.
+// Combination: mode kComb: out = psi_n + cnext G (and acc update when
+// acc != nullptr: acc = (first ? 0 : acc) + cacc G, or on the last stage
+// out = psi_n + acc + cacc G); mode kHeun2: out = (psi_n + phi + G) / 2.
 // ---------------------------------------------------------------------------
+enum : int { kComb = 0, kHeun2 = 1 };
+
 template <typename S>
 struct StageArgs {
   Geom g;
   Coef<S> c;
   const S* phi;    // stage input
-  const S* mu;     // mu(phi)
-  const S* gmu;    // FV: Gamma mu(phi) (d*N)
-  const S* u;      // u^n (d*N) or nullptr when const_u
+  const S* u;      // u^n (d*N) or nullptr when the flow is uniform
   S u0, u1, u2;    // uniform imposed flow (SMOL_ONLY)
   const S* noise;  // N^n
   const S* psi_n;
-  S* next;         // next stage input (or the new psi on the last stage)
+  S* out;
   S* acc;
   S cnext, cacc;
-  int first, last;
+  int mode, first, last;
+  int zc;
 };
 
-template <typename S, int Q, int SMOL>
-__global__ __launch_bounds__(256) void k_smol_stage(StageArgs<S> a) {
-  using L = Lat<Q>;
-  const Geom& g = a.g;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.N) return;
-  const int x = s % g.nx, y = (s / g.nx) % g.ny, z = s / (g.nx * g.ny);
-  const S* __restrict__ phi = a.phi;
-  auto uval = [&](int comp, int t) -> S {
-    if (a.u) return a.u[static_cast<size_t>(comp) * g.N + t];
-    return comp == 0 ? a.u0 : (comp == 1 ? a.u1 : a.u2);
-  };
-  S adv = 0, lap = 0;
-  if constexpr (SMOL == kFD) {
-    const int xp = g.nb(x, y, z, 1, 0, 0), xm = g.nb(x, y, z, -1, 0, 0);
-    const int yp = g.nb(x, y, z, 0, 1, 0), ym = g.nb(x, y, z, 0, -1, 0);
-    adv = S(0.5) * (uval(0, xp) * phi[xp] - uval(0, xm) * phi[xm]) +
-          S(0.5) * (uval(1, yp) * phi[yp] - uval(1, ym) * phi[ym]);
-    if (L::D == 3) {
-      const int zp = g.nb(x, y, z, 0, 0, 1), zm = g.nb(x, y, z, 0, 0, -1);
-      adv += S(0.5) * (uval(2, zp) * phi[zp] - uval(2, zm) * phi[zm]);
-    }
-    lap = lap_so<S, Q>(a.mu, g, x, y, z);
-  } else {
-    S av = 0, dv = 0;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const int t = g.nb(x, y, z, L::cx[i], L::cy[i], L::cz[i]);
-      const S p = phi[t];
-      S ca = 0, cd = 0;
-      if (L::cx[i]) { ca += L::cx[i] * uval(0, t); cd += L::cx[i] * a.gmu[t]; }
-      if (L::cy[i]) { ca += L::cy[i] * uval(1, t); cd += L::cy[i] * a.gmu[g.N + t]; }
-      if (L::cz[i]) { ca += L::cz[i] * uval(2, t); cd += L::cz[i] * a.gmu[2 * g.N + t]; }
-      av += S(L::w[i]) * ca * p;
-      dv += S(L::w[i]) * cd;
-    }
-    adv = S(3) * av;
-    lap = S(3) * dv;
+template <typename S>
+__device__ __forceinline__ void combine(const StageArgs<S>& a, int s, S G) {
+  if (a.mode == kHeun2) {
+    a.out[s] = S(0.5) * (a.psi_n[s] + a.phi[s] + G);
+    return;
   }
-  const S G = -adv + a.c.M * lap + a.noise[s];
+  if (a.acc == nullptr) {
+    a.out[s] = a.psi_n[s] + a.cnext * G;
+    return;
+  }
   const S prev = a.first ? S(0) : a.acc[s];
   if (a.last) {
-    a.next[s] = a.psi_n[s] + prev + a.cacc * G;
+    a.out[s] = a.psi_n[s] + prev + a.cacc * G;
   } else {
-    a.next[s] = a.psi_n[s] + a.cnext * G;
+    a.out[s] = a.psi_n[s] + a.cnext * G;
     a.acc[s] = prev + a.cacc * G;
   }
 }
 
+template <typename S>
+__device__ __forceinline__ S uval(const StageArgs<S>& a, int comp, int site) {
+  if (a.u) return a.u[static_cast<size_t>(comp) * a.g.N + site];
+  return comp == 0 ? a.u0 : (comp == 1 ? a.u1 : a.u2);
+}
+
+// FV stage (Sec. V.B, Eq. fvft): G = Gamma . J + N with the node flux
+// J = -u phi + M Gamma mu(phi).  Rings: phi (halo 3), mu (halo 2), J (halo 1).
+template <typename S, int Q>
+__global__ __launch_bounds__(kTX* kTY) void k_stage_fv(StageArgs<S> a) {
+  using L = Lat<Q>;
+  constexpr int D = L::D;
+  constexpr int WP = kTX + 6, HP = kTY + 6;
+  constexpr int WM = kTX + 4, HM = kTY + 4;
+  constexpr int WJ = kTX + 2, HJ = kTY + 2;
+  constexpr int NR = D == 3 ? 3 : 1;
+  constexpr int NT = kTX * kTY;
+  __shared__ S sphi[NR][WP * HP];
+  __shared__ S smu[NR][WM * HM];
+  __shared__ S sJ[NR][D][WJ * HJ];
+  const Geom& g = a.g;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
+  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
+  const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
+  const int z0 = D == 3 ? blockIdx.z * a.zc : 0;
+  const int z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
+
+  auto load_phi = [&](int p) {
+    const int slot = ring(p, NR), pz = wrap_any(p, g.nz);
+    for (int e = tid; e < WP * HP; e += NT) {
+      const int i = e % WP, j = e / WP;
+      const int gx = wrap_r(x0 - 3 + i, g.nx, near), gy = wrap_r(y0 - 3 + j, g.ny, near);
+      sphi[slot][e] = a.phi[gx + g.nx * (gy + g.ny * pz)];
+    }
+  };
+  auto comp_mu = [&](int p) {
+    const int slot = ring(p, NR);
+    for (int e = tid; e < WM * HM; e += NT) {
+      const int i = e % WM, j = e / WM;
+      smu[slot][e] = chem_pot<S, D>(a.c, [&](int dx, int dy, int dz) {
+        return sphi[ring(p + dz, NR)][(i + 1 + dx) + WP * (j + 1 + dy)];
+      });
+    }
+  };
+  auto comp_J = [&](int p) {
+    const int slot = ring(p, NR), pz = wrap_any(p, g.nz);
+    for (int e = tid; e < WJ * HJ; e += NT) {
+      const int i = e % WJ, j = e / WJ;
+      S gm[3] = {0, 0, 0};
+#pragma unroll
+      for (int q = 1; q < Q; ++q) {
+        const S t = S(L::w[q]) * smu[ring(p + L::cz[q], NR)][(i + 1 + L::cx[q]) + WM * (j + 1 + L::cy[q])];
+        if (L::cx[q]) gm[0] += L::cx[q] * t;
+        if (L::cy[q]) gm[1] += L::cy[q] * t;
+        if (L::cz[q]) gm[2] += L::cz[q] * t;
+      }
+      const S ph = sphi[slot][(i + 2) + WP * (j + 2)];
+      const int gx = wrap_r(x0 - 1 + i, g.nx, near), gy = wrap_r(y0 - 1 + j, g.ny, near);
+      const int site = gx + g.nx * (gy + g.ny * pz);
+#pragma unroll
+      for (int c = 0; c < D; ++c) sJ[slot][c][e] = -uval(a, c, site) * ph + a.c.M * (S(3) * gm[c]);
+    }
+  };
+  auto comp_G = [&](int t) {
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= g.nx || y >= g.ny) return;
+    S acc = 0;
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+      const int slot = ring(t + L::cz[q], NR);
+      const int e = (tx + 1 + L::cx[q]) + WJ * (ty + 1 + L::cy[q]);
+      S v = 0;
+      if (L::cx[q]) v += L::cx[q] * sJ[slot][0][e];
+      if (L::cy[q]) v += L::cy[q] * sJ[slot][1][e];
+      if (D == 3 && L::cz[q]) v += L::cz[q] * sJ[slot][D - 1][e];
+      acc += S(L::w[q]) * v;
+    }
+    const int s = x + g.nx * (y + g.ny * t);
+    combine(a, s, S(3) * acc + a.noise[s]);
+  };
+
+  if constexpr (D == 2) {
+    load_phi(0);
+    __syncthreads();
+    comp_mu(0);
+    __syncthreads();
+    comp_J(0);
+    __syncthreads();
+    comp_G(0);
+  } else {
+    for (int t = z0 - 6; t < z1; ++t) {
+      load_phi(t + 3);
+      __syncthreads();
+      if (t + 2 >= z0 - 2) comp_mu(t + 2);
+      __syncthreads();
+      if (t + 1 >= z0 - 1) comp_J(t + 1);
+      __syncthreads();
+      if (t >= z0) comp_G(t);
+    }
+  }
+}
+
+// FD stage (Sec. V.A): G = -D.(u phi) + M L_SO mu(phi) + N with the central
+// divergence D.  Rings: phi (halo 2, 5 planes), mu (halo 1, 3 planes).
+template <typename S, int Q>
+__global__ __launch_bounds__(kTX* kTY) void k_stage_fd(StageArgs<S> a) {
+  using L = Lat<Q>;
+  constexpr int D = L::D;
+  constexpr int WP = kTX + 4, HP = kTY + 4;
+  constexpr int WM = kTX + 2, HM = kTY + 2;
+  constexpr int NP = D == 3 ? 5 : 1, NM = D == 3 ? 3 : 1;
+  constexpr int NT = kTX * kTY;
+  __shared__ S sphi[NP][WP * HP];
+  __shared__ S smu[NM][WM * HM];
+  const Geom& g = a.g;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
+  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
+  const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
+  const int z0 = D == 3 ? blockIdx.z * a.zc : 0;
+  const int z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
+
+  auto load_phi = [&](int p) {
+    const int slot = ring(p, NP), pz = wrap_any(p, g.nz);
+    for (int e = tid; e < WP * HP; e += NT) {
+      const int i = e % WP, j = e / WP;
+      const int gx = wrap_r(x0 - 2 + i, g.nx, near), gy = wrap_r(y0 - 2 + j, g.ny, near);
+      sphi[slot][e] = a.phi[gx + g.nx * (gy + g.ny * pz)];
+    }
+  };
+  auto comp_mu = [&](int p) {
+    const int slot = ring(p, NM);
+    for (int e = tid; e < WM * HM; e += NT) {
+      const int i = e % WM, j = e / WM;
+      smu[slot][e] = chem_pot<S, D>(a.c, [&](int dx, int dy, int dz) {
+        return sphi[ring(p + dz, NP)][(i + 1 + dx) + WP * (j + 1 + dy)];
+      });
+    }
+  };
+  auto comp_G = [&](int t) {
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= g.nx || y >= g.ny) return;
+    const Nbr nb(g, x, y, t);
+    auto ph = [&](int dx, int dy, int dz) {
+      return sphi[ring(t + dz, NP)][(tx + 2 + dx) + WP * (ty + 2 + dy)];
+    };
+    S adv = S(0.5) * (uval(a, 0, nb.at(1, 0, 0)) * ph(1, 0, 0) -
+                      uval(a, 0, nb.at(-1, 0, 0)) * ph(-1, 0, 0)) +
+            S(0.5) * (uval(a, 1, nb.at(0, 1, 0)) * ph(0, 1, 0) -
+                      uval(a, 1, nb.at(0, -1, 0)) * ph(0, -1, 0));
+    if (D == 3)
+      adv += S(0.5) * (uval(a, 2, nb.at(0, 0, 1)) * ph(0, 0, 1) -
+                       uval(a, 2, nb.at(0, 0, -1)) * ph(0, 0, -1));
+    const S lap = lap_so<S, D>([&](int dx, int dy, int dz) {
+      return smu[ring(t + dz, NM)][(tx + 1 + dx) + WM * (ty + 1 + dy)];
+    });
+    const int s = nb.at(0, 0, 0);
+    combine(a, s, -adv + a.c.M * lap + a.noise[s]);
+  };
+
+  if constexpr (D == 2) {
+    load_phi(0);
+    __syncthreads();
+    comp_mu(0);
+    __syncthreads();
+    comp_G(0);
+  } else {
+    for (int t = z0 - 4; t < z1; ++t) {
+      load_phi(t + 2);
+      __syncthreads();
+      if (t + 1 >= z0 - 1) comp_mu(t + 1);
+      __syncthreads();
+      if (t >= z0) comp_G(t);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Initial state and observables.
+// Initial state and observables (one thread per site, 1-D grid).
 // ---------------------------------------------------------------------------
 template <typename S, bool DEV, int Q>
 __global__ __launch_bounds__(256) void k_init_uniform(Geom g, double rho0, double ux, double uy,
@@ -422,9 +782,10 @@ __global__ __launch_bounds__(256) void k_scatter_user(Geom g, double rho0,
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.N) return;
   const int x = s % g.nx, y = (s / g.nx) % g.ny, z = s / (g.nx * g.ny);
+  const Nbr nb(g, x, y, z);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double v = fin[static_cast<size_t>(i) * g.N + g.nb(x, y, z, L::cx[i], L::cy[i], L::cz[i])];
+    const double v = fin[static_cast<size_t>(i) * g.N + nb.at(L::cx[i], L::cy[i], L::cz[i])];
     f[static_cast<size_t>(i) * g.N + s] = static_cast<S>(DEV ? v - L::w[i] * rho0 : v);
   }
 }
@@ -438,11 +799,12 @@ __global__ __launch_bounds__(256) void k_gather(Geom g, double rho0, const S* __
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.N) return;
   const int x = s % g.nx, y = (s / g.nx) % g.ny, z = s / (g.nx * g.ny);
+  const Nbr nb(g, x, y, z);
   double r = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     double v = static_cast<double>(
-        f[static_cast<size_t>(i) * g.N + g.nb(x, y, z, -L::cx[i], -L::cy[i], -L::cz[i])]);
+        f[static_cast<size_t>(i) * g.N + nb.at(-L::cx[i], -L::cy[i], -L::cz[i])]);
     if (DEV) v += L::w[i] * rho0;
     if (pop) pop[static_cast<size_t>(i) * g.N + s] = v;
     r += v;
@@ -478,11 +840,12 @@ __global__ __launch_bounds__(kTotBlock) void k_totals_partial(Geom g, double rho
   double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.N; s += gridDim.x * blockDim.x) {
     const int x = s % g.nx, y = (s / g.nx) % g.ny, z = s / (g.nx * g.ny);
+    const Nbr nb(g, x, y, z);
     double r = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       double v = static_cast<double>(
-          f[static_cast<size_t>(i) * g.N + g.nb(x, y, z, -L::cx[i], -L::cy[i], -L::cz[i])]);
+          f[static_cast<size_t>(i) * g.N + nb.at(-L::cx[i], -L::cy[i], -L::cz[i])]);
       if (DEV) v += L::w[i] * rho0;
       r += v;
       if (L::cx[i]) jx += L::cx[i] * v;

@@ -52,6 +52,11 @@ class lbl_init(ctypes.Structure):
     ]
 
 
+class lbl_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -91,6 +96,11 @@ def library():
         L.lbl_strerror.restype = ctypes.c_char_p
         L.lbl_last_error.argtypes = [ctypes.c_void_p]
         L.lbl_last_error.restype = ctypes.c_char_p
+        L.lbl_timing_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.lbl_timing_enable.restype = ctypes.c_int
+        L.lbl_timing_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(lbl_kernel_time),
+                                      ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.lbl_timing_read.restype = ctypes.c_int
         L.lbl_abi_version.argtypes = []
         L.lbl_abi_version.restype = ctypes.c_int
         _lib = L
@@ -136,6 +146,18 @@ def lbl_observable_bytes(sim, what):
 
 def lbl_destroy(sim):
     return library().lbl_destroy(sim)
+
+
+def lbl_timing_enable(sim, enable):
+    return library().lbl_timing_enable(sim, int(enable))
+
+
+def lbl_timing_read(sim, max_entries=32):
+    buf = (lbl_kernel_time * max_entries)()
+    n = ctypes.c_int()
+    rc = library().lbl_timing_read(sim, buf, max_entries, ctypes.byref(n))
+    return rc, [(buf[k].name.decode(), int(buf[k].launches), float(buf[k].total_ms))
+                for k in range(min(n.value, max_entries))]
 
 
 def make_params(lattice=LBL_D2Q9, smol=LBL_SMOL_FD, precision=LBL_FP64, coupling=LBL_FULL,
@@ -256,6 +278,18 @@ class Sim:
         if rc != LBL_OK:
             raise LblError(rc, lbl_last_error(self.handle))
         return tensor
+
+    def timing(self, enable=True):
+        rc = lbl_timing_enable(self.handle, enable)
+        if rc != LBL_OK:
+            raise LblError(rc, lbl_last_error(self.handle))
+
+    def kernel_times(self):
+        """[(kernel name, launches, total ms)] since timing was enabled."""
+        rc, rows = lbl_timing_read(self.handle)
+        if rc != LBL_OK:
+            raise LblError(rc, lbl_last_error(self.handle))
+        return rows
 
     def close(self):
         if getattr(self, "handle", None):
