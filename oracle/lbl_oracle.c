@@ -648,31 +648,46 @@ int orc_step(const orc_params *p, double *f, double *psi, uint32_t step) {
     free(fn);
   }
 
-  /* 7: SMOL Runge-Kutta with the noise and the velocity frozen over the step
-   * (Sec. V, Wilkie's scheme).  Reading: the default is Heun's two-stage
-   * method; Euler and classical RK4 are selectable. */
+  /* 7: SMOL Runge-Kutta with the noise held constant through the step (Sec. V,
+   * Wilkie's scheme).  Reading: only the noise is frozen; each stage sees the
+   * advecting velocity of its own time level: u^n at t_n, and at t_{n+1} the
+   * velocity of the streamed populations, (jbar^{n+1} + F^n/2)/rho^{n+1} (the
+   * time-n force is the only one known before psi^{n+1}); RK4's mid stages use
+   * the average of the two.  Freezing u^n over both stages instead leaves the
+   * longitudinal momentum at the axis Nyquist wave number, which streaming flips
+   * each step and collision never damps, driving the interfaces with one sign
+   * through the whole step: two-phase runs then diverge after ~10^3 steps.
+   * Default stages: Heun; Euler and classical RK4 are selectable. */
   if (p->coupling != ORC_LB_ONLY) {
     double *noise = (double *)malloc(sizeof(double) * N);
     double *k1 = (double *)malloc(sizeof(double) * N);
     double *k2 = (double *)malloc(sizeof(double) * N);
     double *tmp = (double *)malloc(sizeof(double) * N);
+    double *u1 = (double *)malloc(sizeof(double) * N * d);
+    double *uh = (double *)malloc(sizeof(double) * N * d);
+    if (p->coupling == ORC_FULL) {
+      orc_velocity(p, f, F, u1); /* f now holds fbar^{n+1} */
+    } else {
+      memcpy(u1, u, sizeof(double) * N * d); /* imposed uniform flow */
+    }
+    for (int64_t k = 0; k < N * d; k++) uh[k] = 0.5 * (u[k] + u1[k]);
     orc_smol_noise(p, step, noise);
     orc_smol_rhs(p, psi, u, noise, k1);
     if (p->rk_stages == 1) {
       for (int64_t s = 0; s < N; s++) psi[s] = psi[s] + k1[s];
     } else if (p->rk_stages == 2) {
       for (int64_t s = 0; s < N; s++) tmp[s] = psi[s] + k1[s];
-      orc_smol_rhs(p, tmp, u, noise, k2);
+      orc_smol_rhs(p, tmp, u1, noise, k2);
       for (int64_t s = 0; s < N; s++) psi[s] = psi[s] + 0.5 * (k1[s] + k2[s]);
     } else {
       double *k3 = (double *)malloc(sizeof(double) * N);
       double *k4 = (double *)malloc(sizeof(double) * N);
       for (int64_t s = 0; s < N; s++) tmp[s] = psi[s] + 0.5 * k1[s];
-      orc_smol_rhs(p, tmp, u, noise, k2);
+      orc_smol_rhs(p, tmp, uh, noise, k2);
       for (int64_t s = 0; s < N; s++) tmp[s] = psi[s] + 0.5 * k2[s];
-      orc_smol_rhs(p, tmp, u, noise, k3);
+      orc_smol_rhs(p, tmp, uh, noise, k3);
       for (int64_t s = 0; s < N; s++) tmp[s] = psi[s] + k3[s];
-      orc_smol_rhs(p, tmp, u, noise, k4);
+      orc_smol_rhs(p, tmp, u1, noise, k4);
       for (int64_t s = 0; s < N; s++)
         psi[s] = psi[s] + (k1[s] + 2.0 * k2[s] + 2.0 * k3[s] + k4[s]) / 6.0;
       free(k3);
@@ -682,6 +697,8 @@ int orc_step(const orc_params *p, double *f, double *psi, uint32_t step) {
     free(k1);
     free(k2);
     free(tmp);
+    free(u1);
+    free(uh);
   }
   free(F);
   free(u);
