@@ -84,7 +84,9 @@ enum lbl_coupling {
  *   rk_stages: 1 (Euler), 2 (Heun, default) or 4 (classical RK4);
  *   seed  : key of the Philox4x32-10 noise stream;
  *   sample_every: if > 0, the axis structure factors are accumulated on the
- *           device after every sample_every-th step (LBL_OBS_SK_AXES etc.). */
+ *           device after every sample_every-th step (LBL_OBS_SK_AXES etc.),
+ *           and the FP64 totals are checked for NaN/Inf at the same time (a
+ *           failure surfaces as LBL_E_NONFINITE from the next lbl_observe). */
 typedef struct lbl_params {
   int32_t lattice;   /* enum lbl_lattice */
   int32_t smol;      /* enum lbl_smol */
@@ -162,11 +164,16 @@ enum lbl_observable {
                            with j = sum_i fbar_i c_i; reduced in FP64 */
   LBL_OBS_SK_AXES = 5,  /* d*Lmax FP64, Lmax = max(nx,ny,nz): mean over samples of
                            |sum_x psi e^{-i k x_alpha}|^2 / N at k = 2 pi m / L_alpha,
-                           element [alpha*Lmax + m] (0 beyond L_alpha) */
+                           element [alpha*Lmax + m] (0 beyond L_alpha).  A sample
+                           is taken after every sample_every-th step, on the new psi */
   LBL_OBS_UK_AXES = 6,  /* d*d*Lmax FP64: the same for each velocity component beta,
-                           element [(alpha*d + beta)*Lmax + m] */
+                           element [(alpha*d + beta)*Lmax + m]; the velocity sampled
+                           is u^n, the one the sampled step computed (zero for
+                           SMOL_ONLY, whose flow is imposed) */
   LBL_OBS_STEP = 7,     /* 1 int64: steps taken */
-  LBL_OBS_NSAMPLES = 8  /* 1 int64: samples accumulated into SK/UK */
+  LBL_OBS_NSAMPLES = 8, /* 1 int64: samples accumulated into SK/UK */
+  LBL_OBS_PSIK_AXES = 9 /* 2*d*Lmax FP64: the current sum_x psi e^{-i k x_alpha} at
+                           k = 2 pi m / L_alpha, element [(alpha*Lmax + m)*2 + {0: re, 1: im}] */
 };
 
 /* Copy an observable of the current state into dst (host memory, or device
@@ -196,6 +203,96 @@ typedef struct lbl_kernel_time {
 } lbl_kernel_time;
 int lbl_timing_enable(lbl_sim *sim, int enable);
 int lbl_timing_read(lbl_sim *sim, lbl_kernel_time *out, int max_entries, int *n_entries);
+
+/* ------------------------------------------------------------------------
+ * Pool: independent simulations batched on one device (the library's own
+ * serving and ensemble layer, not the paper's).  Requests are admitted in
+ * arrival order while their device memory fits the budget; every running
+ * request of the same kind (storage, lattice, variant, stages, ghost rate)
+ * advances together: each phase of a step is one launch over a work table of
+ * (request, tile) items, and a tick of several steps is captured and replayed
+ * as one graph.  A request's arithmetic, noise stream and results do not
+ * depend on what else is resident.  Finished requests release their device
+ * memory; their results stay until lbl_pool_release.
+ * ------------------------------------------------------------------------ */
+typedef struct lbl_pool lbl_pool;
+
+enum lbl_request_state {
+  LBL_REQ_QUEUED = 0,
+  LBL_REQ_RUNNING = 1,
+  LBL_REQ_DONE = 2,
+  LBL_REQ_FAILED = 3
+};
+
+enum lbl_submit_flags {
+  LBL_KEEP_PSI = 1 /* keep the final psi field as a result */
+};
+
+enum lbl_pool_result {
+  LBL_RES_SK_AXES = 0, /* d*Lmax FP64: |sum_x psi e^{-i k x_alpha}|^2 / N of the final
+                          state at k = 2 pi m / L_alpha, element [alpha*Lmax + m] */
+  LBL_RES_TOTALS = 1,  /* 20 FP64: LBL_OBS_TOTALS at admission, then at completion */
+  LBL_RES_TIMES = 2,   /* 3 FP64: submit, start, completion times in seconds of the
+                          host's monotonic clock */
+  LBL_RES_PSI = 3      /* N FP64: final psi (requests submitted with LBL_KEEP_PSI) */
+};
+
+typedef struct lbl_pool_info {
+  uint64_t budget_bytes, used_bytes;
+  int64_t queued, running, done, failed;
+  int64_t ticks, site_updates; /* lattice-site updates executed so far */
+} lbl_pool_info;
+
+/* Create a pool with a device-memory budget.  env gives the device and the
+ * allocator as for lbl_create; the pool runs all its work on a stream of its
+ * own (default priority, created here) so that ticks can be captured as
+ * graphs; env->stream is not used.  Errors: LBL_E_INVAL, LBL_E_DEVICE. */
+int lbl_pool_create(uint64_t budget_bytes, const lbl_env *env, lbl_pool **out);
+
+/* Queue one simulation of nsteps steps; never blocks.  *request receives its
+ * id.  The parameters are validated now (LBL_E_INVAL); a request whose
+ * device memory exceeds the whole budget gives LBL_E_NOMEM.  USER initial
+ * states are copied at submission. */
+int lbl_pool_submit(lbl_pool *pool, const lbl_params *params, const lbl_init *init,
+                    int64_t nsteps, int32_t flags, int64_t *request);
+
+/* One tick: admit what fits, advance every running request by up to
+ * max_steps steps (each stops at its own step count), retire the finished
+ * ones.  Synchronises the pool's stream.  *pending (may be NULL) receives the
+ * number of queued plus running requests afterwards. */
+int lbl_pool_run(lbl_pool *pool, int64_t max_steps, int64_t *pending);
+
+/* State and completed steps of a request.  LBL_E_INVAL for an unknown id. */
+int lbl_pool_poll(const lbl_pool *pool, int64_t request, int32_t *state, int64_t *steps_done);
+
+/* Copy a result of a finished request into host memory dst.  Errors:
+ * LBL_E_INVAL (unknown id or kind, not finished), LBL_E_BUFSIZE,
+ * LBL_E_UNSUPPORTED (psi not kept). */
+int lbl_pool_result(const lbl_pool *pool, int64_t request, int32_t what, void *dst,
+                    size_t bytes);
+
+/* Size in bytes of a result (0 if unknown). */
+size_t lbl_pool_result_bytes(const lbl_pool *pool, int64_t request, int32_t what);
+
+/* Forget a request: drops its results, or cancels it if queued or running
+ * (freeing its device memory). */
+int lbl_pool_release(lbl_pool *pool, int64_t request);
+
+int lbl_pool_stats(const lbl_pool *pool, lbl_pool_info *out);
+
+/* Work-table schedule of the batched launches: xcd_swizzle != 0 maps
+ * consecutive tiles of a request to the same XCD (L2); zc > 0 overrides the
+ * planes per tile of the 3-D kernels (0 = automatic). */
+int lbl_pool_set_schedule(lbl_pool *pool, int32_t xcd_swizzle, int32_t zc);
+
+/* Device memory one simulation with these parameters needs (0 if invalid). */
+uint64_t lbl_sim_bytes(const lbl_params *params);
+
+/* Text of the pool's last error ("" if none). */
+const char *lbl_pool_last_error(const lbl_pool *pool);
+
+/* Release the pool, cancelling what is still queued or running. */
+int lbl_pool_destroy(lbl_pool *pool);
 
 /* Static text for a status code. */
 const char *lbl_strerror(int status);

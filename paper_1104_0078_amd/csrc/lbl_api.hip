@@ -3,7 +3,11 @@
 // launch sequence of the coupled FLBE + SMOL sweep.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <deque>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <exception>
@@ -13,6 +17,8 @@
 
 #include "lbl.h"
 #include "lbl_kernels.hpp"
+#include "lbl_observe.hpp"
+#include "lbl_batch.hpp"
 
 using namespace lbl;
 
@@ -42,10 +48,16 @@ struct lbl_sim {
   void* acc = nullptr;
   void* mu = nullptr;
   void* u = nullptr;
+  void* u_end = nullptr;  // velocity of the streamed populations (stages at t_{n+1})
   void* noise = nullptr;
   double* part = nullptr;
   int nparts = 0;
   double* tot = nullptr;
+  bool tot_pending = false;
+  double* planes = nullptr;  // [kMaxFields][3][Lmax] plane sums
+  double* col = nullptr;     // [kMaxFields][nz][nx] column sums
+  double* sk = nullptr;      // [d][Lmax] accumulated S_a(k)
+  double* uk = nullptr;      // [d][d][Lmax] accumulated U_ab(k)
   int64_t step = 0;
   int64_t nsamples = 0;
   uint32_t k0 = 0, k1 = 0;
@@ -386,9 +398,17 @@ struct Impl {
       if (rc) return rc;
     }
     if (cpl != LBL_SMOL_ONLY) {
-      const LBArgs<S> a = lb_args(s, fin, fout, psin, cpl == LBL_FULL ? u : nullptr,
-                                  cpl == LBL_FULL, n);
+      const LBArgs<S> a = lb_args(s, fin, fout, psin, u, cpl == LBL_FULL, n);
       if (int rc = launch_lb(s, a, true)) return rc;
+    }
+    if (cpl == LBL_FULL && s->p.rk_stages > 1) {
+      // Velocity of the streamed populations for the stages at t_{n+1}.
+      const LBArgs<S> a = lb_args(s, fout, nullptr, psin, static_cast<S*>(s->u_end), 1, n);
+      const dim3 grid = site_grid(s), block(kBX, kBY);
+      if (int rc = launch(s, "k_uend", [&] {
+            k_lb<S, DEV, Q, SMOL, false, false><<<grid, block, 0, s->stream>>>(a);
+          }))
+        return rc;
     }
     if (cpl != LBL_LB_ONLY) {
       const int ns = s->p.rk_stages;
@@ -401,6 +421,8 @@ struct Impl {
         a.c = coef(s);
         a.phi = phi;
         a.u = cpl == LBL_FULL ? u : nullptr;
+        a.u_end = static_cast<const S*>(s->u_end);
+        a.utime = st == 0 ? kAtN : (st == ns - 1 ? kAtN1 : kAtMid);
         a.u0 = S(s->p.u_imposed[0]);
         a.u1 = S(s->p.u_imposed[1]);
         a.u2 = S(Lat<Q>::D == 3 ? s->p.u_imposed[2] : 0.0);
@@ -434,12 +456,154 @@ struct Impl {
     }
     if (cpl != LBL_SMOL_ONLY) s->cur = 1 - s->cur;
     s->step += 1;
+    if (s->p.sample_every > 0 && s->step % s->p.sample_every == 0) {
+      if (int rc = sample(s, true, nullptr)) return rc;
+      if (int rc = totals(s, s->tot)) return rc;
+      s->tot_pending = true;
+      s->nsamples += 1;
+    }
     return LBL_OK;
+  }
+
+  // Plane sums and axis DFTs of psi (and u when accumulating): adds
+  // |X|^2/N into sk/uk when `accumulate`, writes psi's complex X into `cur`.
+  static int sample(lbl_sim* s, bool accumulate, double* cur) {
+    const Geom g = geom(s);
+    const int D = Lat<Q>::D;
+    FieldSet<S> fs{};
+    fs.f[0] = static_cast<const S*>(s->psi[s->pcur]);
+    fs.nf = 1;
+    if (accumulate && s->p.coupling != LBL_SMOL_ONLY) {
+      for (int b = 0; b < D; ++b) fs.f[1 + b] = static_cast<const S*>(s->u) + static_cast<size_t>(b) * s->N;
+      fs.nf = 1 + D;
+    }
+    const int Lmax = s->Lmax;
+    const int last = D - 1, Llast = D == 3 ? s->p.nz : s->p.ny;
+    double* planes = s->planes;
+    double* col = s->col;
+    if (int rc = launch(s, "k_sample", [&] {
+          k_plane_last<S><<<Llast, kRedBlock, 0, s->stream>>>(g, fs, last, Lmax, planes);
+        }))
+      return rc;
+    if (D == 3)
+      if (int rc = launch(s, "k_sample", [&] {
+            k_plane_y<S><<<s->p.ny, kRedBlock, 0, s->stream>>>(g, fs, Lmax, planes);
+          }))
+        return rc;
+    const dim3 gx1((s->p.nx + kRedBlock - 1) / kRedBlock, s->p.nz);
+    if (int rc = launch(s, "k_sample",
+                        [&] { k_plane_x1<S><<<gx1, kRedBlock, 0, s->stream>>>(g, fs, col); }))
+      return rc;
+    const int nf = fs.nf;
+    if (int rc = launch(s, "k_sample", [&] {
+          k_plane_x2<<<(s->p.nx + kRedBlock - 1) / kRedBlock, kRedBlock, 0, s->stream>>>(
+              g, nf, col, Lmax, planes);
+        }))
+      return rc;
+    const int nthreads = nf * D * Lmax;
+    double* sk = accumulate ? s->sk : nullptr;
+    double* uk = accumulate ? s->uk : nullptr;
+    return launch(s, "k_sample", [&] {
+      k_axis_dft<<<(nthreads + kRedBlock - 1) / kRedBlock, kRedBlock, 0, s->stream>>>(
+          g, D, nf, Lmax, planes, sk, uk, cur);
+    });
+  }
+
+  static int totals(lbl_sim* s, double* dst) {
+    const Geom g = geom(s);
+    const S* f = static_cast<const S*>(s->f[s->cur]);
+    const S* psi = static_cast<const S*>(s->psi[s->pcur]);
+    k_totals_partial<S, DEV, Q><<<s->nparts, kTotBlock, 0, s->stream>>>(g, s->p.rho, f, psi,
+                                                                       s->part);
+    if (int rc = launched(s, "k_totals_partial")) return rc;
+    k_totals_final<<<1, 64, 0, s->stream>>>(s->nparts, s->part, dst);
+    return launched(s, "k_totals_final");
   }
 
   static int steps(lbl_sim* s, int64_t nsteps) {
     for (int64_t k = 0; k < nsteps; ++k)
       if (int rc = one_step(s)) return rc;
+    return LBL_OK;
+  }
+
+  // Descriptor of a simulation for the batched kernels.
+  static Replica<S> replica(const lbl_sim* s, int zc) {
+    Replica<S> r;
+    r.g = geom(s);
+    r.c = coef(s);
+    r.zc = zc;
+    r.coupling = s->p.coupling;
+    r.noise_on = s->p.kT > 0;
+    for (int k = 0; k < 2; ++k) {
+      r.f[k] = static_cast<S*>(s->f[k]);
+      r.psi[k] = static_cast<S*>(s->psi[k]);
+      r.phi[k] = static_cast<S*>(s->phi[k]);
+    }
+    r.acc = static_cast<S*>(s->acc);
+    r.mu = static_cast<S*>(s->mu);
+    r.u = static_cast<S*>(s->u);
+    r.u_end = static_cast<S*>(s->u_end);
+    r.noise = static_cast<S*>(s->noise);
+    r.rho0 = S(s->p.rho);
+    r.gamma_s = S(s->gamma_s);
+    r.gamma_b = S(s->gamma_b);
+    r.gamma_g = S(s->gamma_g);
+    r.sigma_s = S(s->sigma_s);
+    r.sigma_b = S(s->sigma_b);
+    r.sigma_g = S(s->sigma_g);
+    r.amp = S(std::sqrt(2.0 * s->p.kT * s->p.M));
+    r.u0 = S(s->p.u_imposed[0]);
+    r.u1 = S(s->p.u_imposed[1]);
+    r.u2 = S(Lat<Q>::D == 3 ? s->p.u_imposed[2] : 0.0);
+    r.k0 = s->k0;
+    r.k1 = s->k1;
+    return r;
+  }
+
+  static size_t replica_bytes() { return sizeof(Replica<S>); }
+
+  // Fill the descriptor array for `sims` (host memory, replica_bytes() each)
+  // and the two work tables.
+  static void tables(const std::vector<lbl_sim*>& sims, int zc_override, void* reps_host,
+                     std::vector<Work>& wlb, std::vector<Work>& wtile) {
+    Replica<S>* reps = static_cast<Replica<S>*>(reps_host);
+    wlb.clear();
+    wtile.clear();
+    for (size_t i = 0; i < sims.size(); ++i) {
+      const lbl_sim* s = sims[i];
+      const int zc = (Lat<Q>::D == 3 && zc_override > 0) ? std::min(zc_override, s->p.nz) : s->zc;
+      reps[i] = replica(s, zc);
+      const int rep = static_cast<int>(i);
+      for (int bz = 0; bz < s->p.nz; ++bz)
+        for (int by = 0; by < (s->p.ny + kBY - 1) / kBY; ++by)
+          for (int bx = 0; bx < (s->p.nx + kBX - 1) / kBX; ++bx) wlb.push_back(Work{rep, bx, by, bz});
+      const int nzc = Lat<Q>::D == 3 ? (s->p.nz + zc - 1) / zc : 1;
+      for (int bz = 0; bz < nzc; ++bz)
+        for (int by = 0; by < (s->p.ny + kTY - 1) / kTY; ++by)
+          for (int bx = 0; bx < (s->p.nx + kTX - 1) / kTX; ++bx) wtile.push_back(Work{rep, bx, by, bz});
+    }
+  }
+
+  // Enqueue `nsteps` batched steps of a group on `stream` (captured by the
+  // caller into a graph).
+  static int enqueue_group(hipStream_t stream, const void* reps_dev, RepState* states, int nrep,
+                           const Work* wlb, int nlb, const Work* wtile, int ntile, int rk,
+                           bool ghost, int64_t nsteps) {
+    const Replica<S>* reps = static_cast<const Replica<S>*>(reps_dev);
+    const dim3 bsite(kBX, kBY), btile(kTX, kTY);
+    for (int64_t k = 0; k < nsteps; ++k) {
+      kb_prep<S, Q, SMOL><<<ntile, btile, 0, stream>>>(reps, states, wtile);
+      if (ghost)
+        kb_lb<S, DEV, Q, SMOL, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb);
+      else
+        kb_lb<S, DEV, Q, SMOL, false><<<nlb, bsite, 0, stream>>>(reps, states, wlb);
+      if (rk > 1) kb_uend<S, DEV, Q, SMOL><<<nlb, bsite, 0, stream>>>(reps, states, wlb, rk);
+      for (int st = 0; st < rk; ++st)
+        kb_stage<S, Q, SMOL><<<ntile, btile, 0, stream>>>(reps, states, wtile, st, rk);
+      kb_advance<S><<<(nrep + 255) / 256, 256, 0, stream>>>(reps, states, nrep);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return LBL_E_DEVICE;
+    }
     return LBL_OK;
   }
 
@@ -470,12 +634,17 @@ struct Impl {
         k_to_f64<S><<<grid_for(s->d * s->N), kBlock, 0, s->stream>>>(s->d * s->N, ubuf, dst);
         return launched(s, "k_to_f64");
       }
-      case LBL_OBS_TOTALS: {
-        k_totals_partial<S, DEV, Q><<<s->nparts, kTotBlock, 0, s->stream>>>(g, s->p.rho, f, psi,
-                                                                           s->part);
-        if (int rc = launched(s, "k_totals_partial")) return rc;
-        k_totals_final<<<1, 64, 0, s->stream>>>(s->nparts, s->part, dst);
-        return launched(s, "k_totals_final");
+      case LBL_OBS_TOTALS:
+        return totals(s, dst);
+      case LBL_OBS_PSIK_AXES:
+        return sample(s, false, dst);
+      case LBL_OBS_SK_AXES:
+      case LBL_OBS_UK_AXES: {
+        const double inv = 1.0 / static_cast<double>(s->nsamples > 0 ? s->nsamples : 1);
+        const double* src = what == LBL_OBS_SK_AXES ? s->sk : s->uk;
+        const int n = static_cast<int>((what == LBL_OBS_SK_AXES ? 1 : s->d) * s->d * s->Lmax);
+        k_scale<<<grid_for(n), kBlock, 0, s->stream>>>(n, inv, src, dst);
+        return launched(s, "k_scale");
       }
       default:
         return LBL_E_UNSUPPORTED;
@@ -487,16 +656,24 @@ using StepFn = int (*)(lbl_sim*, int64_t);
 using InitFn = int (*)(lbl_sim*, const lbl_init*);
 using ObsFn = int (*)(lbl_sim*, int, double*);
 
+using TablesFn = void (*)(const std::vector<lbl_sim*>&, int, void*, std::vector<Work>&,
+                          std::vector<Work>&);
+using EnqueueFn = int (*)(hipStream_t, const void*, RepState*, int, const Work*, int, const Work*,
+                          int, int, bool, int64_t);
+
 struct Table {
   StepFn step;
   InitFn init;
   ObsFn observe;
+  TablesFn tables;
+  EnqueueFn enqueue;
+  size_t replica_bytes;
 };
 
 template <typename S, bool DEV, int Q, int SMOL>
 Table table_for() {
-  return Table{&Impl<S, DEV, Q, SMOL>::steps, &Impl<S, DEV, Q, SMOL>::init,
-               &Impl<S, DEV, Q, SMOL>::observe};
+  using I = Impl<S, DEV, Q, SMOL>;
+  return Table{&I::steps, &I::init, &I::observe, &I::tables, &I::enqueue_group, I::replica_bytes()};
 }
 
 Table select(const lbl_params& p) {
@@ -509,6 +686,20 @@ Table select(const lbl_params& p) {
   }
   if (!d3) return fv ? table_for<float, true, 9, kFV>() : table_for<float, true, 9, kFD>();
   return fv ? table_for<float, true, 19, kFV>() : table_for<float, true, 19, kFD>();
+}
+
+// Device allocations of one simulation, in creation order.
+std::vector<size_t> alloc_plan(const lbl_params& p) {
+  const int q = p.lattice, d = p.lattice == LBL_D2Q9 ? 2 : 3;
+  const size_t N = static_cast<size_t>(p.nx) * p.ny * p.nz;
+  const size_t sz = p.precision == LBL_FP64 ? 8 : 4;
+  const int Lmax = std::max(p.nx, std::max(p.ny, p.nz));
+  const int nparts = std::min(1024, std::max(1, static_cast<int>((N + kBlock - 1) / kBlock)));
+  return {sz * N * q, sz * N * q, sz * N, sz * N, sz * N, sz * N, sz * N, sz * N,
+          sz * N * d, sz * N, sizeof(double) * 10 * nparts, sizeof(double) * 16,
+          sizeof(double) * kMaxFields * 3 * Lmax,
+          sizeof(double) * kMaxFields * static_cast<size_t>(p.nz) * p.nx,
+          sizeof(double) * d * Lmax, sizeof(double) * d * d * Lmax, sz * N * d};
 }
 
 size_t obs_bytes(const lbl_sim* s, int what) {
@@ -527,6 +718,8 @@ size_t obs_bytes(const lbl_sim* s, int what) {
       return 8 * static_cast<size_t>(s->d) * s->Lmax;
     case LBL_OBS_UK_AXES:
       return 8 * static_cast<size_t>(s->d) * s->d * s->Lmax;
+    case LBL_OBS_PSIK_AXES:
+      return 8 * 2 * static_cast<size_t>(s->d) * s->Lmax;
     case LBL_OBS_STEP:
     case LBL_OBS_NSAMPLES:
       return 8;
@@ -579,22 +772,6 @@ int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* e
 
   const size_t N = static_cast<size_t>(s->N);
   const size_t sz = s->ssize;
-  bool ok = true;
-  auto A = [&](size_t bytes) {
-    void* ptr = dev_alloc(s, bytes);
-    ok = ok && ptr;
-    return ptr;
-  };
-  s->f[0] = A(sz * N * s->q);
-  s->f[1] = A(sz * N * s->q);
-  s->psi[0] = A(sz * N);
-  s->psi[1] = A(sz * N);
-  s->phi[0] = A(sz * N);
-  s->phi[1] = A(sz * N);
-  s->acc = A(sz * N);
-  s->mu = A(sz * N);
-  s->u = A(sz * N * s->d);
-  s->noise = A(sz * N);
   // z-chunk of the tiled SMOL kernels: at least ~2048 blocks when possible.
   {
     const int bxy = ((params->nx + kTX - 1) / kTX) * ((params->ny + kTY - 1) / kTY);
@@ -603,8 +780,33 @@ int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* e
     s->zc = std::max(1, zc);
   }
   s->nparts = std::min(1024, std::max(1, grid_for(s->N)));
-  s->part = static_cast<double*>(A(sizeof(double) * 10 * s->nparts));
-  s->tot = static_cast<double*>(A(sizeof(double) * 16));
+  const std::vector<size_t> plan = alloc_plan(*params);
+  std::vector<void*> bufs;
+  bool ok = true;
+  for (size_t b : plan) {
+    void* ptr = dev_alloc(s, b);
+    ok = ok && ptr;
+    bufs.push_back(ptr);
+  }
+  if (ok) {
+    s->f[0] = bufs[0];
+    s->f[1] = bufs[1];
+    s->psi[0] = bufs[2];
+    s->psi[1] = bufs[3];
+    s->phi[0] = bufs[4];
+    s->phi[1] = bufs[5];
+    s->acc = bufs[6];
+    s->mu = bufs[7];
+    s->u = bufs[8];
+    s->noise = bufs[9];
+    s->part = static_cast<double*>(bufs[10]);
+    s->tot = static_cast<double*>(bufs[11]);
+    s->planes = static_cast<double*>(bufs[12]);
+    s->col = static_cast<double*>(bufs[13]);
+    s->sk = static_cast<double*>(bufs[14]);
+    s->uk = static_cast<double*>(bufs[15]);
+    s->u_end = bufs[16];
+  }
   if (!ok) {
     std::string msg = "device allocation failed";
     release_all(s);
@@ -612,6 +814,13 @@ int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* e
     return fail(nullptr, LBL_E_NOMEM, msg);
   }
   rc = hip_check(s, hipMemsetAsync(s->noise, 0, sz * N, s->stream), "clear noise");
+  if (!rc)
+    rc = hip_check(s, hipMemsetAsync(s->sk, 0, sizeof(double) * s->d * s->Lmax, s->stream),
+                   "clear sk");
+  if (!rc)
+    rc = hip_check(s, hipMemsetAsync(s->uk, 0, sizeof(double) * s->d * s->d * s->Lmax, s->stream),
+                   "clear uk");
+  if (!rc) rc = hip_check(s, hipMemsetAsync(s->u, 0, sz * N * s->d, s->stream), "clear u");
   if (!rc) rc = select(s->p).init(s, init);
   if (!rc) rc = hip_check(s, hipStreamSynchronize(s->stream), "create sync");
   if (rc) {
@@ -622,6 +831,341 @@ int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* e
   }
   *out = s;
   return LBL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Pool.
+// ---------------------------------------------------------------------------
+double now_seconds() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct PoolReq {
+  int64_t id = 0;
+  lbl_params p{};
+  lbl_init init{};
+  std::vector<double> user_f, user_psi;
+  int64_t nsteps = 0, done_steps = 0;
+  int32_t flags = 0;
+  int state = LBL_REQ_QUEUED;
+  lbl_sim* sim = nullptr;
+  uint64_t bytes = 0;
+  double t_submit = 0, t_start = 0, t_done = 0;
+  std::vector<double> totals, sk, psi;
+  std::string err;
+};
+
+struct GroupKey {
+  int precision, lattice, smol, rk, ghost;
+  bool operator<(const GroupKey& o) const {
+    if (precision != o.precision) return precision < o.precision;
+    if (lattice != o.lattice) return lattice < o.lattice;
+    if (smol != o.smol) return smol < o.smol;
+    if (rk != o.rk) return rk < o.rk;
+    return ghost < o.ghost;
+  }
+};
+
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t cap = 0;
+};
+
+struct Group {
+  GroupKey key{};
+  std::vector<int64_t> members;
+  DevBuf reps, states, wlb, wtile;
+  int nlb = 0, ntile = 0;
+  bool dirty = true;
+  hipGraphExec_t exec = nullptr;
+  int64_t exec_steps = 0;
+};
+
+GroupKey key_of(const lbl_params& p) {
+  return GroupKey{p.precision, p.lattice, p.smol, p.rk_stages, p.omega_ghost != 1.0 ? 1 : 0};
+}
+
+}  // namespace
+
+struct lbl_pool {
+  uint64_t budget = 0, used = 0;
+  lbl_env env{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::deque<int64_t> queue;
+  std::map<int64_t, PoolReq> reqs;
+  int64_t next_id = 1;
+  std::map<GroupKey, Group> groups;
+  int xcd_swizzle = 1;
+  int zc_override = 0;
+  int64_t ticks = 0, site_updates = 0;
+  std::string err;
+};
+
+namespace {
+
+void* pool_alloc(lbl_pool* pl, size_t bytes) {
+  void* ptr = nullptr;
+  if (pl->env.alloc) return pl->env.alloc(pl->env.ctx, bytes, pl->stream);
+  return hipMalloc(&ptr, bytes) == hipSuccess ? ptr : nullptr;
+}
+
+void pool_free(lbl_pool* pl, void* ptr) {
+  if (!ptr) return;
+  if (pl->env.free)
+    pl->env.free(pl->env.ctx, ptr, pl->stream);
+  else
+    (void)hipFree(ptr);
+}
+
+bool ensure(lbl_pool* pl, DevBuf& b, size_t bytes) {
+  if (b.cap >= bytes && b.ptr) return true;
+  pool_free(pl, b.ptr);
+  b.cap = std::max<size_t>(bytes, 256);
+  b.ptr = pool_alloc(pl, b.cap);
+  if (!b.ptr) b.cap = 0;
+  return b.ptr != nullptr;
+}
+
+void drop_graph(Group& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g.exec = nullptr;
+  g.exec_steps = 0;
+}
+
+// Block b of the launch runs on XCD (b mod 8); give each XCD a contiguous
+// range of the work table so that neighbouring tiles share its L2.
+void xcd_order(std::vector<Work>& w) {
+  const size_t n = w.size();
+  if (n < 16) return;
+  const size_t q = n / 8, r = n % 8;
+  size_t start[8];
+  size_t acc = 0;
+  for (size_t x = 0; x < 8; ++x) {
+    start[x] = acc;
+    acc += q + (x < r ? 1 : 0);
+  }
+  std::vector<Work> out(n);
+  for (size_t i = 0; i < n; ++i) out[i] = w[start[i % 8] + i / 8];
+  w.swap(out);
+}
+
+int pool_fail(lbl_pool* pl, int code, const std::string& msg) {
+  pl->err = msg;
+  return code;
+}
+
+void finish_request(lbl_pool* pl, PoolReq& r, int state) {
+  if (r.sim) {
+    (void)lbl_destroy(r.sim);
+    r.sim = nullptr;
+    pl->used -= r.bytes;
+  }
+  r.state = state;
+  r.t_done = now_seconds();
+}
+
+// Collect the results of a request that has finished its steps.
+void retire(lbl_pool* pl, PoolReq& r) {
+  lbl_sim* s = r.sim;
+  double t[10];
+  int rc = lbl_observe(s, LBL_OBS_TOTALS, t, sizeof(t), 0);
+  if (!rc) r.totals.insert(r.totals.end(), t, t + 10);
+  std::vector<double> cur(2 * static_cast<size_t>(s->d) * s->Lmax);
+  if (!rc) rc = lbl_observe(s, LBL_OBS_PSIK_AXES, cur.data(), cur.size() * 8, 0);
+  if (!rc) {
+    r.sk.assign(static_cast<size_t>(s->d) * s->Lmax, 0.0);
+    for (size_t k = 0; k < r.sk.size(); ++k)
+      r.sk[k] = (cur[2 * k] * cur[2 * k] + cur[2 * k + 1] * cur[2 * k + 1]) / s->N;
+  }
+  if (!rc && (r.flags & LBL_KEEP_PSI)) {
+    r.psi.resize(static_cast<size_t>(s->N));
+    rc = lbl_observe(s, LBL_OBS_PSI, r.psi.data(), r.psi.size() * 8, 0);
+  }
+  if (rc) r.err = s->err;
+  finish_request(pl, r, rc ? LBL_REQ_FAILED : LBL_REQ_DONE);
+}
+
+int admit(lbl_pool* pl) {
+  while (!pl->queue.empty()) {
+    PoolReq& r = pl->reqs[pl->queue.front()];
+    if (pl->used + r.bytes > pl->budget) break;
+    pl->queue.pop_front();
+    lbl_init ini = r.init;
+    if (ini.kind == LBL_INIT_USER) {
+      ini.f0 = r.user_f.data();
+      ini.psi0 = r.user_psi.data();
+      ini.user_on_device = 0;
+    }
+    lbl_sim* s = nullptr;
+    const int rc = create_impl(&r.p, &ini, &pl->env, &s);
+    if (rc) {
+      r.err = g_create_error;
+      r.state = LBL_REQ_FAILED;
+      r.t_done = now_seconds();
+      continue;
+    }
+    r.sim = s;
+    pl->used += r.bytes;
+    r.state = LBL_REQ_RUNNING;
+    r.t_start = now_seconds();
+    r.user_f.clear();
+    r.user_f.shrink_to_fit();
+    r.user_psi.clear();
+    r.user_psi.shrink_to_fit();
+    double t[10];
+    if (lbl_observe(s, LBL_OBS_TOTALS, t, sizeof(t), 0) == LBL_OK)
+      r.totals.assign(t, t + 10);
+    Group& g = pl->groups[key_of(r.p)];
+    g.key = key_of(r.p);
+    g.members.push_back(r.id);
+    g.dirty = true;
+    if (r.nsteps == 0) {
+      retire(pl, r);
+      g.members.pop_back();
+    }
+  }
+  return LBL_OK;
+}
+
+int run_group(lbl_pool* pl, Group& g, int64_t max_steps) {
+  if (g.members.empty()) return LBL_OK;
+  lbl_sim* first = pl->reqs[g.members.front()].sim;
+  const Table t = select(first->p);
+  const int n = static_cast<int>(g.members.size());
+  if (g.dirty) {
+    drop_graph(g);
+    std::vector<lbl_sim*> sims;
+    std::vector<RepState> st;
+    for (int64_t id : g.members) {
+      PoolReq& r = pl->reqs[id];
+      sims.push_back(r.sim);
+      st.push_back(RepState{r.sim->cur, r.sim->pcur, static_cast<uint32_t>(r.sim->step),
+                            static_cast<int>(r.nsteps - r.done_steps)});
+    }
+    std::vector<unsigned char> reps(t.replica_bytes * n);
+    std::vector<Work> wlb, wtile;
+    t.tables(sims, pl->zc_override, reps.data(), wlb, wtile);
+    if (pl->xcd_swizzle) {
+      xcd_order(wlb);
+      xcd_order(wtile);
+    }
+    if (!ensure(pl, g.reps, reps.size()) || !ensure(pl, g.states, sizeof(RepState) * n) ||
+        !ensure(pl, g.wlb, sizeof(Work) * wlb.size()) ||
+        !ensure(pl, g.wtile, sizeof(Work) * wtile.size()))
+      return pool_fail(pl, LBL_E_NOMEM, "pool tables: device allocation failed");
+    hipError_t e = hipMemcpyAsync(g.reps.ptr, reps.data(), reps.size(), hipMemcpyHostToDevice,
+                                  pl->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(g.states.ptr, st.data(), sizeof(RepState) * n, hipMemcpyHostToDevice,
+                         pl->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(g.wlb.ptr, wlb.data(), sizeof(Work) * wlb.size(), hipMemcpyHostToDevice,
+                         pl->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(g.wtile.ptr, wtile.data(), sizeof(Work) * wtile.size(),
+                         hipMemcpyHostToDevice, pl->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+    if (e != hipSuccess)
+      return pool_fail(pl, LBL_E_DEVICE, std::string("pool tables: ") + hipGetErrorString(e));
+    g.nlb = static_cast<int>(wlb.size());
+    g.ntile = static_cast<int>(wtile.size());
+    g.dirty = false;
+  }
+  int64_t steps = 0;
+  for (int64_t id : g.members) {
+    const PoolReq& r = pl->reqs[id];
+    steps = std::max(steps, r.nsteps - r.done_steps);
+  }
+  steps = std::min(steps, max_steps);
+  if (steps <= 0) return LBL_OK;
+  if (!g.exec || g.exec_steps != steps) {
+    drop_graph(g);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+      return pool_fail(pl, LBL_E_DEVICE, std::string("begin capture: ") + hipGetErrorString(e));
+    const int rc = t.enqueue(pl->stream, g.reps.ptr, static_cast<RepState*>(g.states.ptr), n,
+                             static_cast<const Work*>(g.wlb.ptr), g.nlb,
+                             static_cast<const Work*>(g.wtile.ptr), g.ntile, g.key.rk,
+                             g.key.ghost != 0, steps);
+    e = hipStreamEndCapture(pl->stream, &graph);
+    if (rc || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return pool_fail(pl, LBL_E_DEVICE, "graph capture of the batched step failed");
+    }
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      g.exec = nullptr;
+      return pool_fail(pl, LBL_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    g.exec_steps = steps;
+  }
+  const hipError_t e = hipGraphLaunch(g.exec, pl->stream);
+  if (e != hipSuccess)
+    return pool_fail(pl, LBL_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+  return LBL_OK;
+}
+
+// After the tick's graphs have run: copy the device states back into the
+// simulations, count the work, retire what is finished.
+int settle_group(lbl_pool* pl, Group& g) {
+  const int n = static_cast<int>(g.members.size());
+  if (n == 0) return LBL_OK;
+  std::vector<RepState> st(n);
+  hipError_t e = hipMemcpyAsync(st.data(), g.states.ptr, sizeof(RepState) * n,
+                                hipMemcpyDeviceToHost, pl->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+  if (e != hipSuccess)
+    return pool_fail(pl, LBL_E_DEVICE, std::string("pool states: ") + hipGetErrorString(e));
+  std::vector<int64_t> keep;
+  for (int i = 0; i < n; ++i) {
+    PoolReq& r = pl->reqs[g.members[i]];
+    const int64_t done = r.nsteps - st[i].remaining;
+    pl->site_updates += (done - r.done_steps) * static_cast<int64_t>(r.sim->N);
+    r.done_steps = done;
+    r.sim->cur = st[i].cur;
+    r.sim->pcur = st[i].pcur;
+    r.sim->step = st[i].step;
+    if (st[i].remaining <= 0) {
+      retire(pl, r);
+      g.dirty = true;
+    } else {
+      keep.push_back(r.id);
+    }
+  }
+  g.members.swap(keep);
+  return LBL_OK;
+}
+
+int pool_run_impl(lbl_pool* pl, int64_t max_steps, int64_t* pending) {
+  if (int rc = hip_check(nullptr, hipSetDevice(pl->device), "hipSetDevice"))
+    return pool_fail(pl, rc, g_create_error);
+  admit(pl);
+  for (auto& kv : pl->groups)
+    if (int rc = run_group(pl, kv.second, max_steps)) return rc;
+  for (auto& kv : pl->groups)
+    if (int rc = settle_group(pl, kv.second)) return rc;
+  pl->ticks += 1;
+  if (pending) {
+    int64_t n = static_cast<int64_t>(pl->queue.size());
+    for (auto& kv : pl->groups) n += static_cast<int64_t>(kv.second.members.size());
+    *pending = n;
+  }
+  return LBL_OK;
+}
+
+size_t result_bytes(const PoolReq& r, int what) {
+  const int d = r.p.lattice == LBL_D2Q9 ? 2 : 3;
+  const int Lmax = std::max(r.p.nx, std::max(r.p.ny, r.p.nz));
+  switch (what) {
+    case LBL_RES_SK_AXES: return 8 * static_cast<size_t>(d) * Lmax;
+    case LBL_RES_TOTALS: return 8 * 20;
+    case LBL_RES_TIMES: return 8 * 3;
+    case LBL_RES_PSI: return 8 * static_cast<size_t>(r.p.nx) * r.p.ny * r.p.nz;
+    default: return 0;
+  }
 }
 
 }  // namespace
@@ -680,6 +1224,18 @@ int lbl_observe(lbl_sim* sim, int what, void* dst, size_t bytes, int dst_is_devi
   if (bytes < need) return fail(sim, LBL_E_BUFSIZE, "destination buffer too small");
   try {
     if (int rc = hip_check(sim, hipSetDevice(sim->device), "hipSetDevice")) return rc;
+    if (sim->tot_pending) {
+      double t[10];
+      sim->tot_pending = false;
+      int rc = hip_check(sim, hipMemcpyAsync(t, sim->tot, sizeof(t), hipMemcpyDeviceToHost,
+                                             sim->stream),
+                         "copy sampled totals");
+      if (!rc) rc = hip_check(sim, hipStreamSynchronize(sim->stream), "observe sync");
+      if (rc) return rc;
+      for (int k = 0; k < 10; ++k)
+        if (!std::isfinite(t[k]))
+          return fail(sim, LBL_E_NONFINITE, "a sampled conserved total is NaN or infinite");
+    }
     if (sim->deferred) {
       const int rc = sim->deferred;
       sim->deferred = LBL_OK;
@@ -753,5 +1309,193 @@ int lbl_destroy(lbl_sim* sim) {
   delete sim;
   return LBL_OK;
 }
+
+uint64_t lbl_sim_bytes(const lbl_params* params) {
+  lbl_init ini{};
+  if (!params || validate(params, &ini) != LBL_OK) return 0;
+  uint64_t total = 0;
+  for (size_t b : alloc_plan(*params)) total += b;
+  return total;
+}
+
+int lbl_pool_create(uint64_t budget_bytes, const lbl_env* env, lbl_pool** out) {
+  if (!out) return LBL_E_INVAL;
+  *out = nullptr;
+  if (budget_bytes == 0) return fail(nullptr, LBL_E_INVAL, "budget must be > 0");
+  if (env && ((env->alloc == nullptr) != (env->free == nullptr)))
+    return fail(nullptr, LBL_E_INVAL, "alloc and free must both be set or both NULL");
+  lbl_pool* pl = new (std::nothrow) lbl_pool();
+  if (!pl) return LBL_E_NOMEM;
+  pl->budget = budget_bytes;
+  if (env) {
+    pl->env = *env;
+    pl->device = env->device;
+  }
+  hipStream_t st = nullptr;
+  if (hipSetDevice(pl->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    delete pl;
+    return fail(nullptr, LBL_E_DEVICE, "pool stream creation failed");
+  }
+  pl->stream = st;
+  pl->env.stream = st;
+  *out = pl;
+  return LBL_OK;
+}
+
+int lbl_pool_submit(lbl_pool* pl, const lbl_params* params, const lbl_init* init, int64_t nsteps,
+                    int32_t flags, int64_t* request) {
+  if (!pl || !request) return LBL_E_INVAL;
+  if (nsteps < 0) return pool_fail(pl, LBL_E_INVAL, "nsteps must be >= 0");
+  if (int rc = validate(params, init)) return pool_fail(pl, rc, g_create_error);
+  if (params->sample_every != 0)
+    return pool_fail(pl, LBL_E_INVAL, "pool requests report the final state (sample_every 0)");
+  PoolReq r;
+  r.id = pl->next_id++;
+  r.p = *params;
+  r.init = *init;
+  r.nsteps = nsteps;
+  r.flags = flags;
+  r.t_submit = now_seconds();
+  uint64_t bytes = 0;
+  for (size_t b : alloc_plan(*params)) bytes += b;
+  r.bytes = bytes;
+  if (bytes > pl->budget) return pool_fail(pl, LBL_E_NOMEM, "request exceeds the pool budget");
+  if (init->kind == LBL_INIT_USER) {
+    if (init->user_on_device) return pool_fail(pl, LBL_E_INVAL, "pool USER init must be host data");
+    const size_t N = static_cast<size_t>(params->nx) * params->ny * params->nz;
+    r.user_f.assign(init->f0, init->f0 + N * params->lattice);
+    r.user_psi.assign(init->psi0, init->psi0 + N);
+  }
+  r.init.f0 = nullptr;
+  r.init.psi0 = nullptr;
+  *request = r.id;
+  pl->queue.push_back(r.id);
+  pl->reqs.emplace(r.id, std::move(r));
+  return LBL_OK;
+}
+
+int lbl_pool_run(lbl_pool* pl, int64_t max_steps, int64_t* pending) {
+  if (!pl || max_steps <= 0) return LBL_E_INVAL;
+  try {
+    return pool_run_impl(pl, max_steps, pending);
+  } catch (...) {
+    return pool_fail(pl, LBL_E_DEVICE, "unexpected exception in lbl_pool_run");
+  }
+}
+
+int lbl_pool_poll(const lbl_pool* pl, int64_t request, int32_t* state, int64_t* steps_done) {
+  if (!pl) return LBL_E_INVAL;
+  auto it = pl->reqs.find(request);
+  if (it == pl->reqs.end()) return LBL_E_INVAL;
+  if (state) *state = it->second.state;
+  if (steps_done) *steps_done = it->second.done_steps;
+  return LBL_OK;
+}
+
+size_t lbl_pool_result_bytes(const lbl_pool* pl, int64_t request, int32_t what) {
+  if (!pl) return 0;
+  auto it = pl->reqs.find(request);
+  return it == pl->reqs.end() ? 0 : result_bytes(it->second, what);
+}
+
+int lbl_pool_result(const lbl_pool* pl, int64_t request, int32_t what, void* dst, size_t bytes) {
+  if (!pl || !dst) return LBL_E_INVAL;
+  auto it = pl->reqs.find(request);
+  if (it == pl->reqs.end()) return LBL_E_INVAL;
+  const PoolReq& r = it->second;
+  const size_t need = result_bytes(r, what);
+  if (need == 0) return LBL_E_INVAL;
+  if (r.state != LBL_REQ_DONE) return LBL_E_INVAL;
+  if (bytes < need) return LBL_E_BUFSIZE;
+  double* out = static_cast<double*>(dst);
+  switch (what) {
+    case LBL_RES_SK_AXES:
+      std::copy(r.sk.begin(), r.sk.end(), out);
+      return LBL_OK;
+    case LBL_RES_TOTALS:
+      if (r.totals.size() != 20) return LBL_E_UNSUPPORTED;
+      std::copy(r.totals.begin(), r.totals.end(), out);
+      return LBL_OK;
+    case LBL_RES_TIMES:
+      out[0] = r.t_submit;
+      out[1] = r.t_start;
+      out[2] = r.t_done;
+      return LBL_OK;
+    case LBL_RES_PSI:
+      if (r.psi.empty()) return LBL_E_UNSUPPORTED;
+      std::copy(r.psi.begin(), r.psi.end(), out);
+      return LBL_OK;
+    default:
+      return LBL_E_INVAL;
+  }
+}
+
+int lbl_pool_release(lbl_pool* pl, int64_t request) {
+  if (!pl) return LBL_E_INVAL;
+  auto it = pl->reqs.find(request);
+  if (it == pl->reqs.end()) return LBL_E_INVAL;
+  PoolReq& r = it->second;
+  if (r.state == LBL_REQ_QUEUED)
+    pl->queue.erase(std::remove(pl->queue.begin(), pl->queue.end(), request), pl->queue.end());
+  if (r.state == LBL_REQ_RUNNING) {
+    Group& g = pl->groups[key_of(r.p)];
+    g.members.erase(std::remove(g.members.begin(), g.members.end(), request), g.members.end());
+    g.dirty = true;
+    drop_graph(g);
+    (void)hipStreamSynchronize(pl->stream);
+    finish_request(pl, r, LBL_REQ_FAILED);
+  }
+  pl->reqs.erase(it);
+  return LBL_OK;
+}
+
+int lbl_pool_stats(const lbl_pool* pl, lbl_pool_info* out) {
+  if (!pl || !out) return LBL_E_INVAL;
+  *out = lbl_pool_info{};
+  out->budget_bytes = pl->budget;
+  out->used_bytes = pl->used;
+  for (const auto& kv : pl->reqs) {
+    const int st = kv.second.state;
+    out->queued += st == LBL_REQ_QUEUED;
+    out->running += st == LBL_REQ_RUNNING;
+    out->done += st == LBL_REQ_DONE;
+    out->failed += st == LBL_REQ_FAILED;
+  }
+  out->ticks = pl->ticks;
+  out->site_updates = pl->site_updates;
+  return LBL_OK;
+}
+
+int lbl_pool_set_schedule(lbl_pool* pl, int32_t xcd_swizzle, int32_t zc) {
+  if (!pl || zc < 0) return LBL_E_INVAL;
+  pl->xcd_swizzle = xcd_swizzle != 0;
+  pl->zc_override = zc;
+  for (auto& kv : pl->groups) {
+    kv.second.dirty = true;
+    drop_graph(kv.second);
+  }
+  return LBL_OK;
+}
+
+int lbl_pool_destroy(lbl_pool* pl) {
+  if (!pl) return LBL_OK;
+  (void)hipSetDevice(pl->device);
+  (void)hipStreamSynchronize(pl->stream);
+  for (auto& kv : pl->reqs)
+    if (kv.second.sim) finish_request(pl, kv.second, LBL_REQ_FAILED);
+  for (auto& kv : pl->groups) {
+    drop_graph(kv.second);
+    pool_free(pl, kv.second.reps.ptr);
+    pool_free(pl, kv.second.states.ptr);
+    pool_free(pl, kv.second.wlb.ptr);
+    pool_free(pl, kv.second.wtile.ptr);
+  }
+  (void)hipStreamDestroy(pl->stream);
+  delete pl;
+  return LBL_OK;
+}
+
+const char* lbl_pool_last_error(const lbl_pool* pl) { return pl ? pl->err.c_str() : ""; }
 
 }  // extern "C"

@@ -1,0 +1,187 @@
+// lbl_batch.hpp -- batched launches: many independent replicas of one kind
+// (storage, lattice, variant) advance together.  Each launch walks a work
+// table of (replica, block) items; the replica's buffers and parameters come
+// from a descriptor array and its step counter and buffer parity from a
+// device-side state array, so a graph can capture any number of steps.  The
+// per-block arithmetic is the same device code as the single-simulation
+// kernels (lb_body, prep_*_body, stage_*_body).
+#pragma once
+
+#include "lbl_kernels.hpp"
+
+namespace lbl {
+
+enum : int { kCplFull = 0, kCplSmolOnly = 1, kCplLbOnly = 2 };
+
+template <typename S>
+struct Replica {
+  Geom g;
+  Coef<S> c;
+  int zc;
+  int coupling;
+  int noise_on;  // kT > 0
+  S* f[2];
+  S* psi[2];
+  S* phi[2];
+  S* acc;
+  S* mu;
+  S* u;
+  S* u_end;
+  S* noise;
+  S rho0, gamma_s, gamma_b, gamma_g, sigma_s, sigma_b, sigma_g, amp;
+  S u0, u1, u2;
+  uint32_t k0, k1;
+};
+
+// Device-side state of one replica; it is advanced while remaining > 0.
+struct RepState {
+  int cur;    // population buffer holding f*
+  int pcur;   // psi buffer holding psi^n
+  uint32_t step;
+  int remaining;
+};
+
+struct Work {
+  int rep;
+  int bx, by, bz;
+};
+
+template <typename S, int Q, int SMOL>
+__global__ __launch_bounds__(kTX* kTY) void kb_prep(const Replica<S>* __restrict__ reps,
+                                                   const RepState* __restrict__ st,
+                                                   const Work* __restrict__ work) {
+  const Work w = work[blockIdx.x];
+  const RepState rs = st[w.rep];
+  if (rs.remaining <= 0) return;
+  const Replica<S>& r = reps[w.rep];
+  PrepArgs<S> a;
+  a.g = r.g;
+  a.c = r.c;
+  a.amp = r.amp;
+  a.k0 = r.k0;
+  a.k1 = r.k1;
+  a.step = rs.step;
+  a.zc = r.zc;
+  a.psi = r.psi[rs.pcur];
+  a.noise = (r.coupling != kCplLbOnly && r.noise_on) ? r.noise : nullptr;
+  a.mu = r.coupling == kCplFull ? r.mu : nullptr;
+  if (!a.noise && !a.mu) return;
+  if constexpr (SMOL == kFV)
+    prep_fv_body<S, Q>(a, w.bx, w.by, w.bz);
+  else
+    prep_fd_body<S, Q>(a, w.bx, w.by, w.bz);
+}
+
+template <typename S, bool DEV, int Q, int SMOL, bool GHOST>
+__global__ __launch_bounds__(kBX* kBY) void kb_lb(const Replica<S>* __restrict__ reps,
+                                                 const RepState* __restrict__ st,
+                                                 const Work* __restrict__ work) {
+  const Work w = work[blockIdx.x];
+  const RepState rs = st[w.rep];
+  const Replica<S>& r = reps[w.rep];
+  if (rs.remaining <= 0 || r.coupling == kCplSmolOnly) return;
+  LBArgs<S> a;
+  a.g = r.g;
+  a.f_in = r.f[rs.cur];
+  a.f_out = r.f[1 - rs.cur];
+  a.psi = r.psi[rs.pcur];
+  a.mu = r.mu;
+  a.u_out = r.u;
+  a.rho0 = r.rho0;
+  a.gamma_s = r.gamma_s;
+  a.gamma_b = r.gamma_b;
+  a.gamma_g = r.gamma_g;
+  a.sigma_s = r.sigma_s;
+  a.sigma_b = r.sigma_b;
+  a.sigma_g = r.sigma_g;
+  a.k0 = r.k0;
+  a.k1 = r.k1;
+  a.step = rs.step;
+  a.force = r.coupling == kCplFull;
+  a.noise = r.noise_on;
+  lb_body<S, DEV, Q, SMOL, GHOST, true>(a, w.bx, w.by, w.bz);
+}
+
+// Velocity of the streamed populations, (jbar^{n+1} + F^n/2)/rho^{n+1}, for
+// the Runge-Kutta stages at t_{n+1}: the LB body without collision, pulling
+// the populations the step just wrote.
+template <typename S, bool DEV, int Q, int SMOL>
+__global__ __launch_bounds__(kBX* kBY) void kb_uend(const Replica<S>* __restrict__ reps,
+                                                   const RepState* __restrict__ st,
+                                                   const Work* __restrict__ work, int rk) {
+  const Work w = work[blockIdx.x];
+  const RepState rs = st[w.rep];
+  const Replica<S>& r = reps[w.rep];
+  if (rs.remaining <= 0 || r.coupling != kCplFull || rk < 2) return;
+  LBArgs<S> a;
+  a.g = r.g;
+  a.f_in = r.f[1 - rs.cur];
+  a.f_out = nullptr;
+  a.psi = r.psi[rs.pcur];
+  a.mu = r.mu;
+  a.u_out = r.u_end;
+  a.rho0 = r.rho0;
+  a.force = 1;
+  a.noise = 0;
+  lb_body<S, DEV, Q, SMOL, false, false>(a, w.bx, w.by, w.bz);
+}
+
+// Stage `st` of `ns` (ns = 1, 2 or 4), with the same combinations as the
+// single-simulation path.
+template <typename S, int Q, int SMOL>
+__global__ __launch_bounds__(kTX* kTY) void kb_stage(const Replica<S>* __restrict__ reps,
+                                                    const RepState* __restrict__ state,
+                                                    const Work* __restrict__ work, int st,
+                                                    int ns) {
+  const Work w = work[blockIdx.x];
+  const RepState rs = state[w.rep];
+  const Replica<S>& r = reps[w.rep];
+  if (rs.remaining <= 0 || r.coupling == kCplLbOnly) return;
+  StageArgs<S> a;
+  a.g = r.g;
+  a.c = r.c;
+  a.phi = st == 0 ? r.psi[rs.pcur] : r.phi[(st - 1) & 1];
+  a.u = r.coupling == kCplFull ? r.u : nullptr;
+  a.u_end = r.u_end;
+  a.utime = st == 0 ? kAtN : (st == ns - 1 ? kAtN1 : kAtMid);
+  a.u0 = r.u0;
+  a.u1 = r.u1;
+  a.u2 = r.u2;
+  a.noise = r.noise;
+  a.psi_n = r.psi[rs.pcur];
+  a.first = st == 0;
+  a.last = st == ns - 1;
+  a.zc = r.zc;
+  a.acc = nullptr;
+  a.cacc = S(0);
+  a.cnext = S(1);
+  a.mode = kComb;
+  if (ns == 2 && st == 1) a.mode = kHeun2;
+  if (ns == 4) {
+    a.acc = r.acc;
+    a.cnext = st == 2 ? S(1) : S(0.5);
+    a.cacc = (st == 0 || st == 3) ? S(1.0 / 6.0) : S(1.0 / 3.0);
+  }
+  a.out = a.last ? r.psi[1 - rs.pcur] : r.phi[st & 1];
+  if constexpr (SMOL == kFV)
+    stage_fv_body<S, Q>(a, w.bx, w.by, w.bz);
+  else
+    stage_fd_body<S, Q>(a, w.bx, w.by, w.bz);
+}
+
+// End of a step: flip the buffers the step wrote, count it.
+template <typename S>
+__global__ void kb_advance(const Replica<S>* __restrict__ reps, RepState* __restrict__ st, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  RepState s = st[i];
+  if (s.remaining <= 0) return;
+  const int cpl = reps[i].coupling;
+  if (cpl != kCplSmolOnly) s.cur = 1 - s.cur;
+  if (cpl != kCplLbOnly) s.pcur = 1 - s.pcur;
+  s.step += 1;
+  s.remaining -= 1;
+  st[i] = s;
+}
+
+}  // namespace lbl

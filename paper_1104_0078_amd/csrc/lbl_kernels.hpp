@@ -145,14 +145,14 @@ struct LBArgs {
 // GHOST: the ghost modes keep gamma_g m_g (omega_ghost != 1).
 // COLLIDE: false computes only u (observable).
 template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool COLLIDE>
-__global__ __launch_bounds__(kBX* kBY) void k_lb(LBArgs<S> a) {
+__device__ __forceinline__ void lb_body(const LBArgs<S>& a, int bx, int by, int bz) {
   using L = Lat<Q>;
   constexpr int D = L::D;
   constexpr int NR = Q - D - 1;
   constexpr int NB = (NR + 3) / 4;
   const Geom& g = a.g;
-  const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
-  const int z = blockIdx.z;
+  const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
+  const int z = bz;
   if (x >= g.nx || y >= g.ny) return;
   const Nbr nb(g, x, y, z);
   const int s = nb.at(0, 0, 0);
@@ -315,6 +315,11 @@ __global__ __launch_bounds__(kBX* kBY) void k_lb(LBArgs<S> a) {
   });
 }
 
+template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool COLLIDE>
+__global__ __launch_bounds__(kBX* kBY) void k_lb(LBArgs<S> a) {
+  lb_body<S, DEV, Q, SMOL, GHOST, COLLIDE>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // ---------------------------------------------------------------------------
 // z-marching tiles.  A block of kTX x kTY threads owns the columns
 // [x0, x0+kTX) x [y0, y0+kTY) and the planes [z0, z1); plane-sized regions
@@ -382,7 +387,7 @@ __device__ __forceinline__ void prep_mu(const PsiRing<S, D>& r, const PrepArgs<S
 // FV noise (Eqs. fvdiff, noiseflux, fdt_orderpara): node noise xi_a = amp z_a
 // and N = Gamma . xi with Gamma = (1/c_s^2) sum_i w_i c_i.
 template <typename S, int Q>
-__global__ __launch_bounds__(kTX* kTY) void k_prep_fv(PrepArgs<S> a) {
+__device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int by, int bz) {
   using L = Lat<Q>;
   constexpr int D = L::D;
   constexpr int W = kTX + 2, H = kTY + 2, RS = W * H;
@@ -391,9 +396,9 @@ __global__ __launch_bounds__(kTX* kTY) void k_prep_fv(PrepArgs<S> a) {
   __shared__ PsiRing<S, D> pr;
   const Geom& g = a.g;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
-  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
+  const int x0 = bx * kTX, y0 = by * kTY;
   const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
-  const int z0 = D == 3 ? blockIdx.z * a.zc : 0, z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
+  const int z0 = D == 3 ? bz * a.zc : 0, z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
   auto gen = [&](int p) {  // xi on plane p, region with halo 1
     const int slot = ring(p, NRING), pz = wrap_any(p, g.nz);
     for (int e = tid; e < RS; e += kTX * kTY) {
@@ -444,12 +449,17 @@ __global__ __launch_bounds__(kTX* kTY) void k_prep_fv(PrepArgs<S> a) {
   }
 }
 
+template <typename S, int Q>
+__global__ __launch_bounds__(kTX* kTY) void k_prep_fv(PrepArgs<S> a) {
+  prep_fv_body<S, Q>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // FD noise (Sec. V.A, reading): one flux zeta_l per undirected Laplacian link,
 // amplitude A_l = amp sqrt(lambda_l), N(x) = sum_l A_l [zeta_l(x - c_l) - zeta_l(x)].
 // Each plane's link normals are drawn once into LDS; every thread accumulates
 // its site's sums for planes p-1, p, p+1 in registers.
 template <typename S, int Q>
-__global__ __launch_bounds__(kTX* kTY) void k_prep_fd(PrepArgs<S> a) {
+__device__ __forceinline__ void prep_fd_body(const PrepArgs<S>& a, int bx, int by, int bz) {
   using L = Lat<Q>;
   constexpr int D = L::D;
   constexpr int NL = L::NLINKS;
@@ -459,9 +469,9 @@ __global__ __launch_bounds__(kTX* kTY) void k_prep_fd(PrepArgs<S> a) {
   __shared__ PsiRing<S, D> pr;
   const Geom& g = a.g;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
-  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
+  const int x0 = bx * kTX, y0 = by * kTY;
   const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
-  const int z0 = D == 3 ? blockIdx.z * a.zc : 0, z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
+  const int z0 = D == 3 ? bz * a.zc : 0, z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
   const int x = x0 + tx, y = y0 + ty;
   const bool live = x < g.nx && y < g.ny;
   S A[NL];
@@ -516,6 +526,11 @@ __global__ __launch_bounds__(kTX* kTY) void k_prep_fd(PrepArgs<S> a) {
   }
 }
 
+template <typename S, int Q>
+__global__ __launch_bounds__(kTX* kTY) void k_prep_fd(PrepArgs<S> a) {
+  prep_fd_body<S, Q>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // ---------------------------------------------------------------------------
 // One SMOL Runge-Kutta stage with frozen u^n and N^n (Sec. V):
 //   G(phi) = -Div(u phi) + M L_out mu(phi) + N.
@@ -524,6 +539,7 @@ __global__ __launch_bounds__(kTX* kTY) void k_prep_fd(PrepArgs<S> a) {
 // out = psi_n + acc + cacc G); mode kHeun2: out = (psi_n + phi + G) / 2.
 // ---------------------------------------------------------------------------
 enum : int { kComb = 0, kHeun2 = 1 };
+enum : int { kAtN = 0, kAtN1 = 1, kAtMid = 2 };
 
 template <typename S>
 struct StageArgs {
@@ -531,6 +547,8 @@ struct StageArgs {
   Coef<S> c;
   const S* phi;    // stage input
   const S* u;      // u^n (d*N) or nullptr when the flow is uniform
+  const S* u_end;  // velocity of the streamed populations at t_{n+1} (d*N)
+  int utime;       // stage time level: kAtN (u), kAtN1 (u_end), kAtMid (their mean)
   S u0, u1, u2;    // uniform imposed flow (SMOL_ONLY)
   const S* noise;  // N^n
   const S* psi_n;
@@ -560,16 +578,21 @@ __device__ __forceinline__ void combine(const StageArgs<S>& a, int s, S G) {
   }
 }
 
+// Advecting velocity of the stage: each Runge-Kutta stage sees the velocity
+// of its own time level (only the noise is frozen over the step).
 template <typename S>
 __device__ __forceinline__ S uval(const StageArgs<S>& a, int comp, int site) {
-  if (a.u) return a.u[static_cast<size_t>(comp) * a.g.N + site];
-  return comp == 0 ? a.u0 : (comp == 1 ? a.u1 : a.u2);
+  if (!a.u) return comp == 0 ? a.u0 : (comp == 1 ? a.u1 : a.u2);
+  const size_t k = static_cast<size_t>(comp) * a.g.N + site;
+  if (a.utime == kAtN) return a.u[k];
+  if (a.utime == kAtN1) return a.u_end[k];
+  return S(0.5) * (a.u[k] + a.u_end[k]);
 }
 
 // FV stage (Sec. V.B, Eq. fvft): G = Gamma . J + N with the node flux
 // J = -u phi + M Gamma mu(phi).  Rings: phi (halo 3), mu (halo 2), J (halo 1).
 template <typename S, int Q>
-__global__ __launch_bounds__(kTX* kTY) void k_stage_fv(StageArgs<S> a) {
+__device__ __forceinline__ void stage_fv_body(const StageArgs<S>& a, int bx, int by, int bz) {
   using L = Lat<Q>;
   constexpr int D = L::D;
   constexpr int WP = kTX + 6, HP = kTY + 6;
@@ -582,9 +605,9 @@ __global__ __launch_bounds__(kTX* kTY) void k_stage_fv(StageArgs<S> a) {
   __shared__ S sJ[NR][D][WJ * HJ];
   const Geom& g = a.g;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
-  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
+  const int x0 = bx * kTX, y0 = by * kTY;
   const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
-  const int z0 = D == 3 ? blockIdx.z * a.zc : 0;
+  const int z0 = D == 3 ? bz * a.zc : 0;
   const int z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
 
   auto load_phi = [&](int p) {
@@ -662,10 +685,15 @@ __global__ __launch_bounds__(kTX* kTY) void k_stage_fv(StageArgs<S> a) {
   }
 }
 
+template <typename S, int Q>
+__global__ __launch_bounds__(kTX* kTY) void k_stage_fv(StageArgs<S> a) {
+  stage_fv_body<S, Q>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // FD stage (Sec. V.A): G = -D.(u phi) + M L_SO mu(phi) + N with the central
 // divergence D.  Rings: phi (halo 2, 5 planes), mu (halo 1, 3 planes).
 template <typename S, int Q>
-__global__ __launch_bounds__(kTX* kTY) void k_stage_fd(StageArgs<S> a) {
+__device__ __forceinline__ void stage_fd_body(const StageArgs<S>& a, int bx, int by, int bz) {
   using L = Lat<Q>;
   constexpr int D = L::D;
   constexpr int WP = kTX + 4, HP = kTY + 4;
@@ -676,9 +704,9 @@ __global__ __launch_bounds__(kTX* kTY) void k_stage_fd(StageArgs<S> a) {
   __shared__ S smu[NM][WM * HM];
   const Geom& g = a.g;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
-  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
+  const int x0 = bx * kTX, y0 = by * kTY;
   const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
-  const int z0 = D == 3 ? blockIdx.z * a.zc : 0;
+  const int z0 = D == 3 ? bz * a.zc : 0;
   const int z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
 
   auto load_phi = [&](int p) {
@@ -734,6 +762,11 @@ __global__ __launch_bounds__(kTX* kTY) void k_stage_fd(StageArgs<S> a) {
       if (t >= z0) comp_G(t);
     }
   }
+}
+
+template <typename S, int Q>
+__global__ __launch_bounds__(kTX* kTY) void k_stage_fd(StageArgs<S> a) {
+  stage_fd_body<S, Q>(a, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ---------------------------------------------------------------------------

@@ -27,7 +27,7 @@ LBL_FP64, LBL_FP32DEV = 0, 1
 LBL_FULL, LBL_SMOL_ONLY, LBL_LB_ONLY = 0, 1, 2
 LBL_INIT_REST, LBL_INIT_TANH_2IF, LBL_INIT_USER = 0, 1, 2
 (LBL_OBS_PSI, LBL_OBS_RHO, LBL_OBS_U, LBL_OBS_POP, LBL_OBS_TOTALS, LBL_OBS_SK_AXES,
- LBL_OBS_UK_AXES, LBL_OBS_STEP, LBL_OBS_NSAMPLES) = range(9)
+ LBL_OBS_UK_AXES, LBL_OBS_STEP, LBL_OBS_NSAMPLES, LBL_OBS_PSIK_AXES) = range(10)
 
 
 class lbl_params(ctypes.Structure):
@@ -56,6 +56,17 @@ class lbl_kernel_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double)]
 
+
+class lbl_pool_info(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("used_bytes", ctypes.c_uint64),
+                ("queued", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("done", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("ticks", ctypes.c_int64), ("site_updates", ctypes.c_int64)]
+
+
+LBL_REQ_QUEUED, LBL_REQ_RUNNING, LBL_REQ_DONE, LBL_REQ_FAILED = 0, 1, 2, 3
+LBL_KEEP_PSI = 1
+LBL_RES_SK_AXES, LBL_RES_TOTALS, LBL_RES_TIMES, LBL_RES_PSI = 0, 1, 2, 3
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -101,6 +112,26 @@ def library():
         L.lbl_timing_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(lbl_kernel_time),
                                       ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.lbl_timing_read.restype = ctypes.c_int
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.lbl_sim_bytes.argtypes = [P(lbl_params)]
+        L.lbl_sim_bytes.restype = ctypes.c_uint64
+        L.lbl_pool_create.argtypes = [ctypes.c_uint64, P(lbl_env), P(vp)]
+        L.lbl_pool_submit.argtypes = [vp, P(lbl_params), P(lbl_init), i64, i32, P(i64)]
+        L.lbl_pool_run.argtypes = [vp, i64, P(i64)]
+        L.lbl_pool_poll.argtypes = [vp, i64, P(i32), P(i64)]
+        L.lbl_pool_result.argtypes = [vp, i64, i32, vp, ctypes.c_size_t]
+        L.lbl_pool_result_bytes.argtypes = [vp, i64, i32]
+        L.lbl_pool_result_bytes.restype = ctypes.c_size_t
+        L.lbl_pool_release.argtypes = [vp, i64]
+        L.lbl_pool_stats.argtypes = [vp, P(lbl_pool_info)]
+        L.lbl_pool_set_schedule.argtypes = [vp, i32, i32]
+        L.lbl_pool_destroy.argtypes = [vp]
+        L.lbl_pool_last_error.argtypes = [vp]
+        L.lbl_pool_last_error.restype = ctypes.c_char_p
+        for n in ("lbl_pool_create", "lbl_pool_submit", "lbl_pool_run", "lbl_pool_poll",
+                  "lbl_pool_result", "lbl_pool_release", "lbl_pool_stats",
+                  "lbl_pool_set_schedule", "lbl_pool_destroy"):
+            getattr(L, n).restype = ctypes.c_int
         L.lbl_abi_version.argtypes = []
         L.lbl_abi_version.restype = ctypes.c_int
         _lib = L
@@ -266,6 +297,14 @@ class Sim:
             return out.reshape(self.d, self.N)
         if what in (LBL_OBS_STEP, LBL_OBS_NSAMPLES):
             return int(out[0])
+        L = max(self.params.nx, self.params.ny, self.params.nz)
+        if what == LBL_OBS_SK_AXES:
+            return out.reshape(self.d, L)
+        if what == LBL_OBS_UK_AXES:
+            return out.reshape(self.d, self.d, L)
+        if what == LBL_OBS_PSIK_AXES:
+            o = out.reshape(self.d, L, 2)
+            return o[..., 0] + 1j * o[..., 1]
         return out
 
     def observe_into(self, what, tensor):
@@ -294,6 +333,88 @@ class Sim:
     def close(self):
         if getattr(self, "handle", None):
             lbl_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def lbl_sim_bytes(params):
+    return int(library().lbl_sim_bytes(ctypes.byref(params)))
+
+
+class Pool:
+    """Many independent simulations batched on one GPU (lbl_pool_* entry points)."""
+
+    def __init__(self, budget_bytes, device=0, stream=None, memory=None):
+        self.memory = memory if memory is not None else TorchMemory(device, stream)
+        self.env = self.memory.env()
+        h = ctypes.c_void_p()
+        rc = library().lbl_pool_create(int(budget_bytes), ctypes.byref(self.env), ctypes.byref(h))
+        if rc != LBL_OK:
+            raise LblError(rc, lbl_last_error(None))
+        self.handle = h
+        self.params = {}
+
+    def _check(self, rc):
+        if rc != LBL_OK:
+            raise LblError(rc, library().lbl_pool_last_error(self.handle).decode())
+
+    def submit(self, params, init=None, nsteps=0, keep_psi=False):
+        init = init if init is not None else make_init()
+        rid = ctypes.c_int64()
+        rc = library().lbl_pool_submit(self.handle, ctypes.byref(params), ctypes.byref(init),
+                                       int(nsteps), LBL_KEEP_PSI if keep_psi else 0,
+                                       ctypes.byref(rid))
+        self._check(rc)
+        self.params[rid.value] = params
+        return rid.value
+
+    def run(self, max_steps):
+        pending = ctypes.c_int64()
+        self._check(library().lbl_pool_run(self.handle, int(max_steps), ctypes.byref(pending)))
+        return pending.value
+
+    def poll(self, rid):
+        st, done = ctypes.c_int32(), ctypes.c_int64()
+        self._check(library().lbl_pool_poll(self.handle, rid, ctypes.byref(st),
+                                            ctypes.byref(done)))
+        return st.value, done.value
+
+    def result(self, rid, what):
+        n = library().lbl_pool_result_bytes(self.handle, rid, what)
+        out = np.zeros(max(1, n // 8))
+        self._check(library().lbl_pool_result(self.handle, rid, what, out.ctypes.data, n))
+        p = self.params.get(rid)
+        if what == LBL_RES_SK_AXES and p is not None:
+            d = 2 if p.lattice == LBL_D2Q9 else 3
+            return out.reshape(d, max(p.nx, p.ny, p.nz))
+        return out
+
+    def release(self, rid):
+        self._check(library().lbl_pool_release(self.handle, rid))
+        self.params.pop(rid, None)
+
+    def stats(self):
+        info = lbl_pool_info()
+        self._check(library().lbl_pool_stats(self.handle, ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in lbl_pool_info._fields_}
+
+    def set_schedule(self, xcd_swizzle=True, zc=0):
+        self._check(library().lbl_pool_set_schedule(self.handle, int(bool(xcd_swizzle)), int(zc)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            library().lbl_pool_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

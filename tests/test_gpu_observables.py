@@ -1,0 +1,66 @@
+"""GPU parity of the on-device Fourier observables and of the non-finite
+trap: the sampled axis structure factors S_a(k) and velocity spectra
+U_ab(k) against the oracle's axis spectra of the same trajectory, the
+instantaneous psi(k) against numpy's FFT of the oracle's field."""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests import harness as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("lattice,shape,smol", [(H.D2Q9, (40, 28, 1), H.FD),
+                                                (H.D3Q19, (20, 12, 10), H.FV)])
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
+def test_sampled_spectra_match_oracle(lattice, shape, smol, precision):
+    from paper_1104_0078_amd import lbl
+    c = H.config(lattice=lattice, smol=smol, precision=precision, shape=shape, kT=1e-4)
+    print("sampling case", c, flush=True)
+    every, nsteps = 2, 6
+    with lbl.Sim(H.lbl_params(c, sample_every=every), lbl.make_init(psi_std=1e-2)) as sim:
+        sim.step(nsteps)
+        sk = sim.observe(lbl.LBL_OBS_SK_AXES)
+        uk = sim.observe(lbl.LBL_OBS_UK_AXES)
+        assert sim.observe(lbl.LBL_OBS_NSAMPLES) == nsteps // every
+        psik = sim.observe(lbl.LBL_OBS_PSIK_AXES)
+    p = H.oracle_params(c)
+    f, psi = O.init(p, 0, 1e-2)
+    d = O.d_of(p)
+    L = max(shape)
+    sk_ref = np.zeros((d, L))
+    uk_ref = np.zeros((d, d, L))
+    for n in range(nsteps):
+        u = O.velocity(p, f, O.force(p, psi))
+        O.step(p, f, psi, n)
+        if (n + 1) % every == 0:
+            sk_ref += O.axis_spectrum(p, psi, L)
+            for b in range(d):
+                uk_ref[:, b, :] += O.axis_spectrum(p, u[b], L)
+    sk_ref /= nsteps // every
+    uk_ref /= nsteps // every
+    tol = 1e-11 if precision == H.FP64 else 2e-5
+    assert H.rel_err(sk, sk_ref) < tol
+    assert H.rel_err(uk, uk_ref) < tol
+    grid = psi.reshape(shape[::-1] if d == 3 else shape[1::-1])
+    F = np.fft.fftn(grid)  # axes (z,) y, x
+    ref = [F[0, :], F[:, 0]] if d == 2 else [F[0, 0, :], F[0, :, 0], F[:, 0, 0]]
+    for a in range(d):
+        n_a = len(ref[a])
+        np.testing.assert_allclose(psik[a][:n_a], ref[a],
+                                   atol=tol * 10 * np.abs(ref[a]).max())
+
+
+def test_nonfinite_state_is_reported():
+    from paper_1104_0078_amd import lbl
+    c = H.config(lattice=H.D2Q9, smol=H.FD, shape=(32, 32, 1))
+    p = H.oracle_params(c)
+    f0, psi0 = O.init(p, 0, 1e-3)
+    psi0[100] = np.nan
+    ini = lbl.make_init(kind=lbl.LBL_INIT_USER, f0=f0, psi0=psi0)
+    with lbl.Sim(H.lbl_params(c, sample_every=1), ini) as sim:
+        sim.step(2)
+        with pytest.raises(lbl.LblError) as e:
+            sim.observe(lbl.LBL_OBS_PSI)
+        assert e.value.code == lbl.LBL_E_NONFINITE

@@ -1,0 +1,241 @@
+"""Statistical and deterministic checks of the GPU sweep against what model H
+and the discrete scheme fix (closed forms in tests/theory.py):
+
+* equipartition <|u_k|^2> = kT/rho0 at every k (fluctuating LB, Secs. III, IV);
+* SMOL static structure factor against the exact discrete-time form, whose
+  dt -> 0 limit is the lattice Ornstein-Zernike law (Eq. test2 and after);
+* Galilean invariance under an imposed flow at Ma = 0.08 (Sec. VI.B);
+* deterministic decay of a single psi mode, R(z)^n (the dynamic structure
+  factor's decay rates, Eq. strf, for the discrete scheme);
+* shear-wave decay nu k^2;
+* coupled S(k) within a few per cent of the discrete form, and FP32 against
+  FP64 within 2% or 3 standard errors;
+* capillary spectrum <|h_q|^2>/L = kT/(gamma q^2) of two flat interfaces
+  in the paper's 2-D set-up (Eq. flucinterf), gamma from Eq. (st).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests import harness as H
+from tests import theory as T
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(c, sample_every=0, init=None):
+    from paper_1104_0078_amd import lbl
+    ini = init if init is not None else lbl.make_init(kind=c["init"], psi_std=c["psi_std"],
+                                                      boost=c["boost"])
+    return lbl.Sim(H.lbl_params(c, sample_every=sample_every), ini)
+
+
+@pytest.mark.parametrize("lattice,shape", [(H.D2Q9, (48, 40, 1)), (H.D3Q19, (20, 18, 16))])
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
+def test_equipartition(lattice, shape, precision):
+    from paper_1104_0078_amd import lbl
+    kT, rho0 = 1e-5, 1.0
+    c = H.config(lattice=lattice, smol=H.FV, precision=precision, coupling=H.LB_ONLY,
+                 shape=shape, kT=kT, rho=rho0, psi_std=0.0)
+    print("equipartition case", c, flush=True)
+    with _sim(c, sample_every=5) as sim:
+        sim.step(24000)
+        uk = sim.observe(lbl.LBL_OBS_UK_AXES)
+    d = 2 if lattice == H.D2Q9 else 3
+    ratios = []
+    for a in range(d):
+        L = shape[a]
+        for b in range(d):
+            for m in range(1, L):
+                if b == a and 2 * m == L:
+                    continue  # longitudinal momentum at the axis Nyquist is invariant
+                ratios.append(uk[a, b, m] / (kT / rho0))
+    ratios = np.array(ratios)
+    print("  <|u_k|^2>/(kT/rho) mean %.4f min %.3f max %.3f" % (ratios.mean(), ratios.min(),
+                                                               ratios.max()), flush=True)
+    # The run starts from rest; the slowest shear modes (nu k^2 >= 1.7e-3 per
+    # step) thermalise within a few hundred of the 24000 steps.
+    assert abs(ratios.mean() - 1) < 0.04
+    assert np.all(np.abs(ratios - 1) < 0.6)
+
+
+def _sk_theory(c, shape, U=(0, 0, 0)):
+    d = 2 if c["lattice"] == H.D2Q9 else 3
+    out = []
+    for a in range(d):
+        q = T.axis_q(shape[a], a, d)
+        out.append(T.smol_static_sk(q, c["lattice"], c["smol"], c["M"], c["a"], c["kappa"],
+                                    c["kT"], c["rk"], U))
+    return out
+
+
+def _sk_compare(sk, th, shape, d):
+    ratios = []
+    for a in range(d):
+        for m in range(1, shape[a]):
+            if np.isfinite(th[a][m]) and th[a][m] > 0:
+                ratios.append(sk[a, m] / th[a][m])
+    return np.array(ratios)
+
+
+@pytest.mark.parametrize("lattice,smol,shape", [(H.D2Q9, H.FD, (64, 48, 1)),
+                                                (H.D2Q9, H.FV, (64, 48, 1)),
+                                                (H.D3Q19, H.FV, (24, 20, 16)),
+                                                (H.D3Q19, H.FD, (24, 20, 16))])
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
+def test_smol_static_structure_factor(lattice, smol, shape, precision):
+    from paper_1104_0078_amd import lbl
+    c = H.config(lattice=lattice, smol=smol, precision=precision, coupling=H.SMOL_ONLY,
+                 shape=shape, kT=1e-4, a=0.5, b=0.0, kappa=0.1, M=0.2, psi_std=0.0)
+    print("S(k) case", c, flush=True)
+    with _sim(c, sample_every=3) as sim:
+        sim.step(30000)
+        sk = sim.observe(lbl.LBL_OBS_SK_AXES)
+    d = 2 if lattice == H.D2Q9 else 3
+    r = _sk_compare(sk, _sk_theory(c, shape), shape, d)
+    print("  S/S_theory mean %.4f min %.3f max %.3f (n=%d)" % (r.mean(), r.min(), r.max(), r.size),
+          flush=True)
+    assert abs(r.mean() - 1) < 0.03
+    assert np.all(np.abs(r - 1) < 0.25)
+
+
+@pytest.mark.parametrize("smol", [H.FD, H.FV])
+def test_galilean_invariance_ma008(smol):
+    from paper_1104_0078_amd import lbl
+    cs = np.sqrt(1 / 3)
+    U = 0.08 * cs / np.sqrt(2)
+    shape = (64, 64, 1)
+    out = {}
+    for tag, u in (("rest", (0, 0, 0)), ("moving", (U, U, 0))):
+        c = H.config(lattice=H.D2Q9, smol=smol, coupling=H.SMOL_ONLY, shape=shape, kT=1e-4,
+                     a=0.5, b=0.0, kappa=0.1, M=0.2, psi_std=0.0, u_imposed=u)
+        with _sim(c, sample_every=3) as sim:
+            sim.step(30000)
+            out[tag] = (c, sim.observe(lbl.LBL_OBS_SK_AXES))
+    c, sk_move = out["moving"]
+    # The exact discrete form with the advection phase, and the rest-frame form.
+    r_exact = _sk_compare(sk_move, _sk_theory(c, shape, U=c["u_imposed"]), shape, 2)
+    r_rest = _sk_compare(sk_move, _sk_theory(c, shape), shape, 2)
+    print("  moving S/S_exact mean %.4f; S/S_rest mean %.4f" % (r_exact.mean(), r_rest.mean()),
+          flush=True)
+    assert abs(r_exact.mean() - 1) < 0.03
+    assert abs(r_rest.mean() - 1) < 0.03
+
+
+@pytest.mark.parametrize("lattice,smol,shape", [(H.D2Q9, H.FD, (48, 40, 1)),
+                                                (H.D3Q19, H.FV, (24, 20, 16))])
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
+def test_mode_decay_rate(lattice, smol, shape, precision):
+    from paper_1104_0078_amd import lbl
+    c = H.config(lattice=lattice, smol=smol, precision=precision, coupling=H.SMOL_ONLY,
+                 shape=shape, kT=0.0, a=0.065, b=0.0, kappa=0.04, M=0.095)
+    p = H.oracle_params(c)
+    N = O.nsites(p)
+    x = np.arange(N) % shape[0]
+    m = 3
+    psi0 = 1e-2 * np.cos(2 * np.pi * m * x / shape[0])
+    f0 = np.zeros((lattice, N)) + O.velocities(lattice)[1][:, None]
+    ini = lbl.make_init(kind=lbl.LBL_INIT_USER, f0=f0, psi0=psi0)
+    d = 2 if lattice == H.D2Q9 else 3
+    q = np.zeros(3)
+    q[0] = 2 * np.pi * m / shape[0]
+    z, _, _ = T.smol_z(q, lattice, smol, c["M"], c["a"], c["kappa"])
+    R, _ = T.rk_poly(z, 2)
+    with _sim(c, init=ini) as sim:
+        a0 = sim.observe(lbl.LBL_OBS_PSIK_AXES)[0, m]
+        sim.step(200)
+        a1 = sim.observe(lbl.LBL_OBS_PSIK_AXES)[0, m]
+    got = (a1 / a0).real
+    tol = 1e-10 if precision == H.FP64 else 1e-5
+    print("  decay ratio %.12f expected %.12f (1/tau = %.4e)" % (got, R.real ** 200, -z.real))
+    assert abs(got - R.real ** 200) < tol
+
+
+@pytest.mark.parametrize("lattice,shape", [(H.D2Q9, (96, 4, 1)), (H.D3Q19, (64, 4, 4))])
+def test_shear_wave_decay(lattice, shape):
+    from paper_1104_0078_amd import lbl
+    eta = 0.1
+    c = H.config(lattice=lattice, smol=H.FV, coupling=H.LB_ONLY, shape=shape, kT=0.0, eta=eta)
+    cvec, w = O.velocities(lattice)
+    d = 2 if lattice == H.D2Q9 else 3
+    N = shape[0] * shape[1] * shape[2]
+    x = np.arange(N) % shape[0]
+    k = 2 * np.pi / shape[0]
+    u = np.zeros((d, N))
+    u[1] = 1e-4 * np.sin(k * x)
+    cu = cvec[:, :d].astype(float) @ u
+    f0 = w[:, None] * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * (u ** 2).sum(0))
+    ini = lbl.make_init(kind=lbl.LBL_INIT_USER, f0=f0, psi0=np.zeros(N))
+    amp = []
+    with _sim(c, init=ini) as sim:
+        sim.step(100)
+        for _ in range(2):
+            f = sim.observe(lbl.LBL_OBS_POP)
+            amp.append(2 * ((cvec[:, 1].astype(float) @ f) * np.sin(k * x)).sum() / N)
+            sim.step(800)
+    rate = -np.log(amp[1] / amp[0]) / 800
+    nu = (1 / (1 / (0.5 + 3 * eta)) - 0.5) / 3
+    assert abs(rate / (nu * k * k) - 1) < 0.01
+
+
+def test_coupled_structure_factor_fp32_vs_fp64():
+    from paper_1104_0078_amd import lbl
+    shape = (24, 20, 16)
+    res = {}
+    for prec in (H.FP64, H.FP32DEV):
+        c = H.config(lattice=H.D3Q19, smol=H.FV, precision=prec, shape=shape, kT=1e-4, a=0.5,
+                     b=0.0, kappa=0.1, M=0.2, psi_std=0.0)
+        with _sim(c, sample_every=3) as sim:
+            sim.step(30000)
+            res[prec] = sim.observe(lbl.LBL_OBS_SK_AXES)
+    th = _sk_theory(c, shape)
+    r64 = _sk_compare(res[H.FP64], th, shape, 3)
+    r32 = _sk_compare(res[H.FP32DEV], th, shape, 3)
+    print("  coupled S/S_theory FP64 %.4f FP32 %.4f" % (r64.mean(), r32.mean()), flush=True)
+    assert abs(r64.mean() - 1) < 0.04
+    assert abs(r32.mean() - 1) < 0.04
+    assert abs(r32.mean() / r64.mean() - 1) < 0.02
+
+
+def _interface_heights(psi, nx, ny, lo, hi):
+    """Zero crossing of psi along y between rows lo and hi, by linear
+    interpolation between the two sites that bracket it (Sec. VI.C); h(x)."""
+    g = psi.reshape(ny, nx)[lo:hi]
+    s = np.sign(g)
+    idx = np.argmax((s[:-1] * s[1:]) <= 0, axis=0)
+    z0 = g[idx, np.arange(nx)]
+    z1 = g[idx + 1, np.arange(nx)]
+    return lo + idx + z0 / (z0 - z1)
+
+
+@pytest.mark.parametrize("smol", [H.FD, H.FV])
+def test_capillary_spectrum(smol):
+    """The paper's capillary set-up (Sec. VI.C): a 1024 x 128 D2Q9 lattice with
+    two flat interfaces 64 sites apart, -A = B = 0.05, K = 0.2, M = 0.1,
+    kT = 1/3000, nu = c_s^2 tau with tau = 0.45.  The height spectrum of the
+    longest modes follows <|h_q|^2>/L = kT/(gamma q^2) (Eq. flucinterf) with
+    gamma from Eq. (st)."""
+    from paper_1104_0078_amd import lbl
+    nx, ny = 1024, 128
+    a, b, kappa, kT = -0.05, 0.05, 0.2, 1.0 / 3000
+    c = H.config(lattice=H.D2Q9, smol=smol, precision=H.FP64, shape=(nx, ny, 1), a=a, b=b,
+                 kappa=kappa, M=0.1, kT=kT, eta=0.15, init=1, psi_std=1e-3, seed=77)
+    print("capillary case", c, flush=True)
+    gamma = 2 * np.sqrt(2) / 3 * np.sqrt(kappa * abs(a) ** 3) / b
+    nsamp = 2000
+    acc = np.zeros(nx)
+    with _sim(c) as sim:
+        sim.step(20000)
+        for _ in range(nsamp):
+            sim.step(100)
+            psi = sim.observe(lbl.LBL_OBS_PSI)
+            for lo, hi in ((8, 56), (72, 120)):  # interfaces at y = 32 and 96
+                h = _interface_heights(psi, nx, ny, lo, hi)
+                acc += np.abs(np.fft.fft(h - h.mean())) ** 2 / nx / 2
+    S = acc / nsamp
+    m = np.arange(1, 17)
+    q = 2 * np.pi * m / nx
+    ratio = S[m] * gamma * q ** 2 / kT
+    print("  capillary <|h_q|^2> gamma q^2/(L kT), m = 1..16: mean %.3f" % ratio.mean(),
+          flush=True)
+    assert abs(ratio.mean() - 1) < 0.1

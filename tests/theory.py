@@ -1,0 +1,82 @@
+"""Closed forms used by the statistical and deterministic checks (test side).
+
+Lattice symbols: Shinozaki-Oono Laplacian (the paper's Eq. solapft in 3-D, its
+2-D analogue), FV Gamma and Gamma.Gamma for D2Q9/D3Q19, central difference.
+SMOL discrete-time response for frozen-noise Runge-Kutta: the stability
+polynomial R(z) and noise transfer phi(z), the static structure factor
+2 kT M (-L_out) |phi|^2 / (1 - |R|^2), whose dt -> 0 limit is kT/(A - K L_SO)
+(Eq. test2 and the text after it).
+"""
+import numpy as np
+
+D2Q9, D3Q19 = 9, 19
+FD, FV = 0, 1
+
+
+def so_symbol(q, lattice):
+    c = np.cos(q)
+    if lattice == D3Q19:
+        return (12 * (c[0] + c[1] + c[2]) + 12 * (c[0] * c[1] + c[0] * c[2] + c[1] * c[2])
+                + 8 * c[0] * c[1] * c[2] - 80) / 22
+    return c[0] + c[1] + c[0] * c[1] - 3
+
+
+def fv_gamma(q, lattice):
+    """Imaginary part of the FV gradient symbol Gamma(q) (Gamma = i * this)."""
+    s, c = np.sin(q), np.cos(q)
+    if lattice == D3Q19:
+        return np.array([s[0] * (1 + c[1] + c[2]), s[1] * (1 + c[0] + c[2]),
+                         s[2] * (1 + c[0] + c[1])]) / 3
+    return np.array([s[0] * (2 + c[1]), s[1] * (2 + c[0])]) / 3
+
+
+def l_out(q, lattice, smol):
+    if smol == FD:
+        return so_symbol(q, lattice)
+    g = fv_gamma(q, lattice)
+    return -(g * g).sum(axis=0)
+
+
+def advection_symbol(q, U, lattice, smol):
+    """theta with -Div(U psi) -> -i theta psi."""
+    d = 2 if lattice == D2Q9 else 3
+    U = np.asarray(U, dtype=float)[:d]
+    if smol == FD:
+        s = np.sin(q[:d])
+    else:
+        s = fv_gamma(q, lattice)
+    return np.tensordot(U, s, axes=(0, 0))
+
+
+def rk_poly(z, stages):
+    if stages == 1:
+        return 1 + z, np.ones_like(z)
+    if stages == 2:
+        return 1 + z + z * z / 2, 1 + z / 2
+    return (1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24,
+            1 + z / 2 + z ** 2 / 6 + z ** 3 / 24)
+
+
+def smol_z(q, lattice, smol, M, a, kappa, U=(0, 0, 0)):
+    lso = so_symbol(q, lattice)
+    lo = l_out(q, lattice, smol)
+    lam = M * (-lo) * (a - kappa * lso)
+    return -lam - 1j * advection_symbol(q, U, lattice, smol), lo, lso
+
+
+def smol_static_sk(q, lattice, smol, M, a, kappa, kT, stages=2, U=(0, 0, 0)):
+    z, lo, lso = smol_z(q, lattice, smol, M, a, kappa, U)
+    R, phi = rk_poly(z, stages)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return 2 * kT * M * (-lo) * np.abs(phi) ** 2 / (1 - np.abs(R) ** 2)
+
+
+def ornstein_zernike(q, lattice, a, kappa, kT):
+    return kT / (a - kappa * so_symbol(q, lattice))
+
+
+def axis_q(L, axis, d):
+    """Wave vectors 2 pi m / L along one axis, as a (3, L) array."""
+    q = np.zeros((3, L))
+    q[axis] = 2 * np.pi * np.arange(L) / L
+    return q
