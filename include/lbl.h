@@ -204,6 +204,23 @@ typedef struct lbl_kernel_time {
 int lbl_timing_enable(lbl_sim *sim, int enable);
 int lbl_timing_read(lbl_sim *sim, lbl_kernel_time *out, int max_entries, int *n_entries);
 
+/* Launch schedule of one simulation.  It changes only speed, never results.
+ * lb_width: sites along x per 256-thread block of the per-site LB kernels
+ * (32, 64, 128 or 256; a block covers 256 / lb_width rows of one plane);
+ * xcd_swizzle != 0: the blocks are ordered so that each of the 8 XCDs sweeps
+ * one contiguous eighth of the lattice (pulls across block edges then hit the
+ * same L2); zc: planes per block of the z-marching SMOL kernels of a 3-D
+ * lattice (0 keeps the current value, larger than nz is clamped).
+ * Errors: LBL_E_INVAL (NULL, unsupported width, zc < 0, reserved != 0). */
+typedef struct lbl_schedule {
+  int32_t lb_width;
+  int32_t xcd_swizzle;
+  int32_t zc;
+  int32_t reserved; /* must be 0 */
+} lbl_schedule;
+int lbl_set_schedule(lbl_sim *sim, const lbl_schedule *schedule);
+int lbl_get_schedule(const lbl_sim *sim, lbl_schedule *out);
+
 /* ------------------------------------------------------------------------
  * Pool: independent simulations batched on one device (the library's own
  * serving and ensemble layer, not the paper's).  Requests are admitted in

@@ -62,6 +62,8 @@ struct lbl_sim {
   int64_t nsamples = 0;
   uint32_t k0 = 0, k1 = 0;
   int zc = 1;  // planes per block of the z-marching kernels
+  int lb_lw = 6;       // log2 of the LB block width along x
+  int lb_swizzle = 0;  // XCD-contiguous block order of the LB kernels
   double gamma_s = 0, gamma_b = 0, gamma_g = 0, sigma_s = 0, sigma_b = 0, sigma_g = 0;
   int deferred = LBL_OK;
   std::string err;
@@ -341,19 +343,20 @@ struct Impl {
                 Lat<Q>::D == 3 ? (s->p.nz + s->zc - 1) / s->zc : 1);
   }
 
-  static int launch_lb(lbl_sim* s, const LBArgs<S>& a, bool collide) {
-    const dim3 grid = site_grid(s), block(kBX, kBY);
+  static int launch_lb(lbl_sim* s, const LBArgs<S>& a, bool collide, const char* name) {
+    const SiteMap m = make_site_map(s->p.nx, s->p.ny, s->p.nz, s->lb_lw, s->lb_swizzle != 0);
+    const dim3 grid(site_map_blocks(m)), block(kSiteBlock);
     const bool ghost = s->gamma_g != 0.0;
     if (!collide)
-      return launch(s, "k_lb_u", [&] {
-        k_lb<S, DEV, Q, SMOL, false, false><<<grid, block, 0, s->stream>>>(a);
+      return launch(s, name, [&] {
+        k_lb<S, DEV, Q, SMOL, false, false><<<grid, block, 0, s->stream>>>(a, m);
       });
     if (ghost)
-      return launch(s, "k_lb", [&] {
-        k_lb<S, DEV, Q, SMOL, true, true><<<grid, block, 0, s->stream>>>(a);
+      return launch(s, name, [&] {
+        k_lb<S, DEV, Q, SMOL, true, true><<<grid, block, 0, s->stream>>>(a, m);
       });
-    return launch(s, "k_lb", [&] {
-      k_lb<S, DEV, Q, SMOL, false, true><<<grid, block, 0, s->stream>>>(a);
+    return launch(s, name, [&] {
+      k_lb<S, DEV, Q, SMOL, false, true><<<grid, block, 0, s->stream>>>(a, m);
     });
   }
 
@@ -399,16 +402,12 @@ struct Impl {
     }
     if (cpl != LBL_SMOL_ONLY) {
       const LBArgs<S> a = lb_args(s, fin, fout, psin, u, cpl == LBL_FULL, n);
-      if (int rc = launch_lb(s, a, true)) return rc;
+      if (int rc = launch_lb(s, a, true, "k_lb")) return rc;
     }
     if (cpl == LBL_FULL && s->p.rk_stages > 1) {
       // Velocity of the streamed populations for the stages at t_{n+1}.
       const LBArgs<S> a = lb_args(s, fout, nullptr, psin, static_cast<S*>(s->u_end), 1, n);
-      const dim3 grid = site_grid(s), block(kBX, kBY);
-      if (int rc = launch(s, "k_uend", [&] {
-            k_lb<S, DEV, Q, SMOL, false, false><<<grid, block, 0, s->stream>>>(a);
-          }))
-        return rc;
+      if (int rc = launch_lb(s, a, false, "k_uend")) return rc;
     }
     if (cpl != LBL_LB_ONLY) {
       const int ns = s->p.rk_stages;
@@ -630,7 +629,7 @@ struct Impl {
         if (full)
           if (int rc = launch_mu(s, psi, static_cast<S*>(s->mu))) return rc;
         const LBArgs<S> a = lb_args(s, f, nullptr, psi, ubuf, full, 0);
-        if (int rc = launch_lb(s, a, false)) return rc;
+        if (int rc = launch_lb(s, a, false, "k_lb_u")) return rc;
         k_to_f64<S><<<grid_for(s->d * s->N), kBlock, 0, s->stream>>>(s->d * s->N, ubuf, dst);
         return launched(s, "k_to_f64");
       }
@@ -1275,6 +1274,29 @@ int lbl_observe(lbl_sim* sim, int what, void* dst, size_t bytes, int dst_is_devi
   } catch (...) {
     return fail(sim, LBL_E_DEVICE, "unexpected exception in lbl_observe");
   }
+}
+
+int lbl_set_schedule(lbl_sim* sim, const lbl_schedule* sch) {
+  if (!sim || !sch) return LBL_E_INVAL;
+  const int w = sch->lb_width;
+  int lw = -1;
+  for (int k = 5; k <= 8; ++k)
+    if (w == (1 << k)) lw = k;
+  if (lw < 0) return fail(sim, LBL_E_INVAL, "lb_width must be 32, 64, 128 or 256");
+  if (sch->zc < 0 || sch->reserved != 0) return fail(sim, LBL_E_INVAL, "zc < 0 or reserved != 0");
+  sim->lb_lw = lw;
+  sim->lb_swizzle = sch->xcd_swizzle != 0;
+  if (sch->zc > 0) sim->zc = std::min(sch->zc, sim->p.nz);
+  return LBL_OK;
+}
+
+int lbl_get_schedule(const lbl_sim* sim, lbl_schedule* out) {
+  if (!sim || !out) return LBL_E_INVAL;
+  out->lb_width = 1 << sim->lb_lw;
+  out->xcd_swizzle = sim->lb_swizzle;
+  out->zc = sim->zc;
+  out->reserved = 0;
+  return LBL_OK;
 }
 
 int lbl_timing_enable(lbl_sim* sim, int enable) {

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kTX* kTY) void kb_prep(const Replica<S>* __restrict
 }
 
 template <typename S, bool DEV, int Q, int SMOL, bool GHOST>
-__global__ __launch_bounds__(kBX* kBY) void kb_lb(const Replica<S>* __restrict__ reps,
+__global__ __launch_bounds__(kBX* kBY, 5) void kb_lb(const Replica<S>* __restrict__ reps,
                                                  const RepState* __restrict__ st,
                                                  const Work* __restrict__ work) {
   const Work w = work[blockIdx.x];
@@ -99,7 +99,8 @@ __global__ __launch_bounds__(kBX* kBY) void kb_lb(const Replica<S>* __restrict__
   a.step = rs.step;
   a.force = r.coupling == kCplFull;
   a.noise = r.noise_on;
-  lb_body<S, DEV, Q, SMOL, GHOST, true>(a, w.bx, w.by, w.bz);
+  const int x = w.bx * kBX + threadIdx.x, y = w.by * kBY + threadIdx.y;
+  if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, GHOST, true>(a, x, y, w.bz);
 }
 
 // Velocity of the streamed populations, (jbar^{n+1} + F^n/2)/rho^{n+1}, for
@@ -123,7 +124,8 @@ __global__ __launch_bounds__(kBX* kBY) void kb_uend(const Replica<S>* __restrict
   a.rho0 = r.rho0;
   a.force = 1;
   a.noise = 0;
-  lb_body<S, DEV, Q, SMOL, false, false>(a, w.bx, w.by, w.bz);
+  const int x = w.bx * kBX + threadIdx.x, y = w.by * kBY + threadIdx.y;
+  if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, false, false>(a, x, y, w.bz);
 }
 
 // Stage `st` of `ns` (ns = 1, 2 or 4), with the same combinations as the

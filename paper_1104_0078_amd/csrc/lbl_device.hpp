@@ -10,6 +10,8 @@
 #include <cstdint>
 #include <utility>
 
+#include "lbl_math.hpp"
+
 namespace lbl {
 
 constexpr double kCs2 = 1.0 / 3.0;  // c_s^2 for dx = dt = 1 (Sec. VI)
@@ -208,66 +210,56 @@ struct Normal4;
 
 template <>
 struct Normal4<double> {
+  // Box-Muller pair from two 32-bit outputs: sqrt(-2 ln u_a) (cos, sin)(2 pi u_b).
+  __device__ __forceinline__ static void pair(uint32_t ka, uint32_t kb, double& za, double& zb) {
+    const double r = sqrt(-2.0 * bm::log_unit(bm::unit(ka)));
+    double s, c;
+    bm::sincos_turn(kb, &s, &c);
+    za = r * c;
+    zb = r * s;
+  }
   __device__ __forceinline__ static void gen(uint32_t site, uint32_t step, uint32_t block,
                                              uint32_t tag, uint32_t k0, uint32_t k1,
                                              double z[4]) {
     const u32x4 r = philox4x32_10(u32x4{site, step, block, tag}, k0, k1);
-    const double u0 = (static_cast<double>(r.x) + 0.5) * 0x1p-32;
-    const double u1 = (static_cast<double>(r.y) + 0.5) * 0x1p-32;
-    const double u2 = (static_cast<double>(r.z) + 0.5) * 0x1p-32;
-    const double u3 = (static_cast<double>(r.w) + 0.5) * 0x1p-32;
-    const double ra = sqrt(-2.0 * log(u0));
-    const double rb = sqrt(-2.0 * log(u2));
-    double sa, ca, sb, cb;
-    sincospi(2.0 * u1, &sa, &ca);
-    sincospi(2.0 * u3, &sb, &cb);
-    z[0] = ra * ca;
-    z[1] = ra * sa;
-    z[2] = rb * cb;
-    z[3] = rb * sb;
+    pair(r.x, r.y, z[0], z[1]);
+    pair(r.z, r.w, z[2], z[3]);
   }
   // Only the first pair (slots 0, 1 of the block).
   __device__ __forceinline__ static void gen2(uint32_t site, uint32_t step, uint32_t block,
                                               uint32_t tag, uint32_t k0, uint32_t k1,
                                               double z[2]) {
     const u32x4 r = philox4x32_10(u32x4{site, step, block, tag}, k0, k1);
-    const double u0 = (static_cast<double>(r.x) + 0.5) * 0x1p-32;
-    const double u1 = (static_cast<double>(r.y) + 0.5) * 0x1p-32;
-    const double ra = sqrt(-2.0 * log(u0));
-    double sa, ca;
-    sincospi(2.0 * u1, &sa, &ca);
-    z[0] = ra * ca;
-    z[1] = ra * sa;
+    pair(r.x, r.y, z[0], z[1]);
   }
 };
 
+// FP32 storage: the transform in FP32 with the hardware transcendentals
+// (log2, and sine and cosine of an angle given in turns, which is what the
+// uniform already is).
 template <>
 struct Normal4<float> {
   __device__ __forceinline__ static float unif(uint32_t x) {
     return fmaf(static_cast<float>(x), 0x1p-32f, 0x1p-33f);
   }
+  __device__ __forceinline__ static void pair(uint32_t ka, uint32_t kb, float& za, float& zb) {
+    constexpr float kMinus2Ln2 = -1.38629436111989061883f;  // -2 ln 2
+    const float r = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(unif(ka)));
+    const float t = unif(kb);
+    za = r * __builtin_amdgcn_cosf(t);
+    zb = r * __builtin_amdgcn_sinf(t);
+  }
   __device__ __forceinline__ static void gen(uint32_t site, uint32_t step, uint32_t block,
                                              uint32_t tag, uint32_t k0, uint32_t k1, float z[4]) {
     const u32x4 r = philox4x32_10(u32x4{site, step, block, tag}, k0, k1);
-    const float ra = sqrtf(-2.0f * logf(unif(r.x)));
-    const float rb = sqrtf(-2.0f * logf(unif(r.z)));
-    float sa, ca, sb, cb;
-    sincospif(2.0f * unif(r.y), &sa, &ca);
-    sincospif(2.0f * unif(r.w), &sb, &cb);
-    z[0] = ra * ca;
-    z[1] = ra * sa;
-    z[2] = rb * cb;
-    z[3] = rb * sb;
+    pair(r.x, r.y, z[0], z[1]);
+    pair(r.z, r.w, z[2], z[3]);
   }
   __device__ __forceinline__ static void gen2(uint32_t site, uint32_t step, uint32_t block,
                                               uint32_t tag, uint32_t k0, uint32_t k1,
                                               float z[2]) {
     const u32x4 r = philox4x32_10(u32x4{site, step, block, tag}, k0, k1);
-    const float ra = sqrtf(-2.0f * logf(unif(r.x)));
-    float sa, ca;
-    sincospif(2.0f * unif(r.y), &sa, &ca);
-    z[0] = ra * ca;
-    z[1] = ra * sa;
+    pair(r.x, r.y, z[0], z[1]);
   }
 };
 

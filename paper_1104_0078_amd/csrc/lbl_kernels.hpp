@@ -26,9 +26,52 @@ struct Coef {
   S a, b, kappa, M;
 };
 
-// Thread-block shape of the per-site kernels: 64 sites along x (one
+// Thread-block shape of the batched per-site kernels: 64 sites along x (one
 // wavefront, contiguous in memory) by 4 rows.
 constexpr int kBX = 64, kBY = 4;
+constexpr int kSiteBlock = 256;  // threads per block of the per-site kernels
+
+// Schedule of the single-simulation per-site kernels: 256-thread blocks that
+// cover 2^lw sites along x by 256 / 2^lw rows of one z-plane, enumerated with
+// x fastest.  The hardware hands the blocks of a 1-D grid to the 8 XCDs
+// round-robin; with `per` > 0 block b takes virtual block (b % 8) per + b / 8,
+// so each XCD sweeps one contiguous eighth of the lattice and the rows that a
+// pull reads across block edges sit in the same L2.
+struct SiteMap {
+  int lw;        // log2 of the block width along x
+  int nbx, nby;  // blocks along x and y
+  int nb;        // blocks in total
+  int per;       // blocks per XCD when swizzled, else 0
+};
+
+__host__ inline SiteMap make_site_map(int nx, int ny, int nz, int lw, bool swizzle) {
+  SiteMap m;
+  m.lw = lw;
+  const int w = 1 << lw, h = kSiteBlock >> lw;
+  m.nbx = (nx + w - 1) / w;
+  m.nby = (ny + h - 1) / h;
+  m.nb = m.nbx * m.nby * nz;
+  m.per = swizzle ? (m.nb + 7) / 8 : 0;
+  return m;
+}
+
+__host__ inline int site_map_blocks(const SiteMap& m) { return m.per ? 8 * m.per : m.nb; }
+
+// Site of this thread; false when the block is padding or the site is off
+// the lattice.
+__device__ __forceinline__ bool site_of(const SiteMap& m, const Geom& g, int& x, int& y, int& z) {
+  int b = blockIdx.x;
+  if (m.per) {
+    b = (b & 7) * m.per + (b >> 3);
+    if (b >= m.nb) return false;
+  }
+  const int bx = b % m.nbx, r = b / m.nbx;
+  const int by = r % m.nby;
+  z = r / m.nby;
+  x = (bx << m.lw) + (threadIdx.x & ((1 << m.lw) - 1));
+  y = by * (kSiteBlock >> m.lw) + (threadIdx.x >> m.lw);
+  return x < g.nx && y < g.ny;
+}
 // Tile of the z-marching stencil kernels.
 constexpr int kTX = 32, kTY = 8;
 
@@ -144,16 +187,14 @@ struct LBArgs {
 
 // GHOST: the ghost modes keep gamma_g m_g (omega_ghost != 1).
 // COLLIDE: false computes only u (observable).
+// The caller passes a site on the lattice.
 template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool COLLIDE>
-__device__ __forceinline__ void lb_body(const LBArgs<S>& a, int bx, int by, int bz) {
+__device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z) {
   using L = Lat<Q>;
   constexpr int D = L::D;
   constexpr int NR = Q - D - 1;
   constexpr int NB = (NR + 3) / 4;
   const Geom& g = a.g;
-  const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
-  const int z = bz;
-  if (x >= g.nx || y >= g.ny) return;
   const Nbr nb(g, x, y, z);
   const int s = nb.at(0, 0, 0);
 
@@ -316,8 +357,9 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int bx, int by, int 
 }
 
 template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool COLLIDE>
-__global__ __launch_bounds__(kBX* kBY) void k_lb(LBArgs<S> a) {
-  lb_body<S, DEV, Q, SMOL, GHOST, COLLIDE>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+__global__ __launch_bounds__(kSiteBlock, 5) void k_lb(LBArgs<S> a, SiteMap m) {
+  int x, y, z;
+  if (site_of(m, a.g, x, y, z)) lb_body<S, DEV, Q, SMOL, GHOST, COLLIDE>(a, x, y, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -385,23 +427,28 @@ __device__ __forceinline__ void prep_mu(const PsiRing<S, D>& r, const PrepArgs<S
 }
 
 // FV noise (Eqs. fvdiff, noiseflux, fdt_orderpara): node noise xi_a = amp z_a
-// and N = Gamma . xi with Gamma = (1/c_s^2) sum_i w_i c_i.
+// and N = Gamma . xi with Gamma = (1/c_s^2) sum_i w_i c_i.  One plane of xi
+// (halo 1) lives in LDS at a time; each plane is folded into register partial
+// sums of N for the planes below, at and above it.  psi has a three-plane ring
+// for mu.
 template <typename S, int Q>
 __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int by, int bz) {
   using L = Lat<Q>;
   constexpr int D = L::D;
   constexpr int W = kTX + 2, H = kTY + 2, RS = W * H;
-  constexpr int NRING = D == 3 ? 4 : 1;
-  __shared__ S xi[NRING][D][RS];
-  __shared__ PsiRing<S, D> pr;
+  constexpr int NT = kTX * kTY;
+  __shared__ S xi[D][RS];
+  __shared__ S spsi[D == 3 ? 3 : 1][RS];
   const Geom& g = a.g;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
   const int x0 = bx * kTX, y0 = by * kTY;
   const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
   const int z0 = D == 3 ? bz * a.zc : 0, z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool live = x < g.nx && y < g.ny;
   auto gen = [&](int p) {  // xi on plane p, region with halo 1
-    const int slot = ring(p, NRING), pz = wrap_any(p, g.nz);
-    for (int e = tid; e < RS; e += kTX * kTY) {
+    const int pz = wrap_any(p, g.nz);
+    for (int e = tid; e < RS; e += NT) {
       const int i = e % W, j = e / W;
       const int gx = wrap_r(x0 - 1 + i, g.nx, near), gy = wrap_r(y0 - 1 + j, g.ny, near);
       const uint32_t site = static_cast<uint32_t>(gx + g.nx * (gy + g.ny * pz));
@@ -411,40 +458,60 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
       else
         Normal4<S>::gen(site, a.step, 0, kTagSMOL, a.k0, a.k1, zz);
 #pragma unroll
-      for (int c = 0; c < D; ++c) xi[slot][c][e] = zz[c];
+      for (int c = 0; c < D; ++c) xi[c][e] = zz[c];
     }
   };
-  auto div = [&](int t) {
-    const int x = x0 + tx, y = y0 + ty;
-    if (x >= g.nx || y >= g.ny) return;
-    S acc = 0;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const int slot = ring(t + L::cz[i], NRING);
-      const int e = (tx + 1 + L::cx[i]) + W * (ty + 1 + L::cy[i]);
-      S v = 0;
-      if (L::cx[i]) v += L::cx[i] * xi[slot][0][e];
-      if (L::cy[i]) v += L::cy[i] * xi[slot][1][e];
-      if (D == 3 && L::cz[i]) v += L::cz[i] * xi[slot][D - 1][e];
-      acc += S(L::w[i]) * v;
+  auto load_psi = [&](int p) {
+    const int slot = ring(p, D == 3 ? 3 : 1), pz = wrap_any(p, g.nz);
+    for (int e = tid; e < RS; e += NT) {
+      const int i = e % W, j = e / W;
+      const int gx = wrap_r(x0 - 1 + i, g.nx, near), gy = wrap_r(y0 - 1 + j, g.ny, near);
+      spsi[slot][e] = a.psi[gx + g.nx * (gy + g.ny * pz)];
     }
-    a.noise[x + g.nx * (y + g.ny * t)] = S(3) * a.amp * acc;
+  };
+  auto mu_at = [&](int t) {
+    if (!live) return;
+    a.mu[x + g.nx * (y + g.ny * t)] = chem_pot<S, D>(a.c, [&](int dx, int dy, int dz) {
+      return spsi[ring(t + dz, D == 3 ? 3 : 1)][(tx + 1 + dx) + W * (ty + 1 + dy)];
+    });
+  };
+  S npart[3] = {0, 0, 0};  // N(p-1), N(p), N(p+1)
+  auto fold = [&]() {
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+      const int e = (tx + 1 + L::cx[q]) + W * (ty + 1 + L::cy[q]);
+      S v = 0;
+      if (L::cx[q]) v += L::cx[q] * xi[0][e];
+      if (L::cy[q]) v += L::cy[q] * xi[1][e];
+      if (D == 3 && L::cz[q]) v += L::cz[q] * xi[D - 1][e];
+      npart[1 - L::cz[q]] += S(L::w[q]) * v;
+    }
   };
   if constexpr (D == 2) {
     if (a.noise) gen(0);
-    if (a.mu) prep_load_psi<S, D>(pr, a, 0, x0, y0, near, tid);
+    if (a.mu) load_psi(0);
     __syncthreads();
-    if (a.noise) div(0);
-    if (a.mu) prep_mu<S, D>(pr, a, 0, x0, y0, tx, ty);
+    if (a.noise) {
+      fold();
+      if (live) a.noise[x + g.nx * y] = S(3) * a.amp * npart[1];
+    }
+    if (a.mu) mu_at(0);
   } else {
-    for (int t = z0 - 2; t < z1; ++t) {
-      if (a.noise) gen(t + 1);
-      if (a.mu) prep_load_psi<S, D>(pr, a, t + 1, x0, y0, near, tid);
+    // Iteration p: xi(p) and psi(p) staged; N(p-1) and mu(p-1) emitted.
+    for (int p = z0 - 1; p <= z1; ++p) {
+      if (a.noise) gen(p);
+      if (a.mu) load_psi(p);
       __syncthreads();
-      if (t >= z0) {
-        if (a.noise) div(t);
-        if (a.mu) prep_mu<S, D>(pr, a, t, x0, y0, tx, ty);
+      const bool emit = p - 1 >= z0 && p - 1 < z1;
+      if (a.noise) {
+        fold();
+        if (emit && live) a.noise[x + g.nx * (y + g.ny * (p - 1))] = S(3) * a.amp * npart[0];
+        npart[0] = npart[1];
+        npart[1] = npart[2];
+        npart[2] = 0;
       }
+      if (a.mu && emit) mu_at(p - 1);
+      __syncthreads();
     }
   }
 }
@@ -589,8 +656,43 @@ __device__ __forceinline__ S uval(const StageArgs<S>& a, int comp, int site) {
   return S(0.5) * (a.u[k] + a.u_end[k]);
 }
 
+// Values of one site that the stage's combination reads, fetched early so the
+// loads overlap the stencil work of the same plane.
+template <typename S>
+struct SiteIn {
+  S noise, psi_n, phi, acc;
+};
+
+template <typename S>
+__device__ __forceinline__ SiteIn<S> fetch_site(const StageArgs<S>& a, int s) {
+  SiteIn<S> v;
+  v.noise = a.noise[s];
+  v.psi_n = a.psi_n[s];
+  v.phi = a.mode == kHeun2 ? a.phi[s] : S(0);
+  v.acc = (a.acc && !a.first) ? a.acc[s] : S(0);
+  return v;
+}
+
+template <typename S>
+__device__ __forceinline__ void combine_in(const StageArgs<S>& a, int s, S G, const SiteIn<S>& v) {
+  if (a.mode == kHeun2) {
+    a.out[s] = S(0.5) * (v.psi_n + v.phi + G);
+  } else if (a.acc == nullptr) {
+    a.out[s] = v.psi_n + a.cnext * G;
+  } else if (a.last) {
+    a.out[s] = v.psi_n + v.acc + a.cacc * G;
+  } else {
+    a.out[s] = v.psi_n + a.cnext * G;
+    a.acc[s] = v.acc + a.cacc * G;
+  }
+}
+
 // FV stage (Sec. V.B, Eq. fvft): G = Gamma . J + N with the node flux
-// J = -u phi + M Gamma mu(phi).  Rings: phi (halo 3), mu (halo 2), J (halo 1).
+// J = -u phi + M Gamma mu(phi).  z-marching with LDS rings for phi (halo 3,
+// three planes) and mu (halo 2, three planes) and one plane of J (halo 1):
+// each J plane is folded into register partial sums of G for the planes
+// below, at and above it, so J never needs a ring.  The next phi plane and the
+// site values of the current plane are fetched one step ahead.
 template <typename S, int Q>
 __device__ __forceinline__ void stage_fv_body(const StageArgs<S>& a, int bx, int by, int bz) {
   using L = Lat<Q>;
@@ -600,22 +702,56 @@ __device__ __forceinline__ void stage_fv_body(const StageArgs<S>& a, int bx, int
   constexpr int WJ = kTX + 2, HJ = kTY + 2;
   constexpr int NR = D == 3 ? 3 : 1;
   constexpr int NT = kTX * kTY;
+  constexpr int NPF = (WP * HP + NT - 1) / NT;  // phi elements per thread
+  constexpr int NJ = (WJ * HJ + NT - 1) / NT;   // J elements per thread
   __shared__ S sphi[NR][WP * HP];
   __shared__ S smu[NR][WM * HM];
-  __shared__ S sJ[NR][D][WJ * HJ];
+  __shared__ S sJ[D][WJ * HJ];
   const Geom& g = a.g;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
   const int x0 = bx * kTX, y0 = by * kTY;
   const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
   const int z0 = D == 3 ? bz * a.zc : 0;
   const int z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool live = x < g.nx && y < g.ny;
 
-  auto load_phi = [&](int p) {
-    const int slot = ring(p, NR), pz = wrap_any(p, g.nz);
-    for (int e = tid; e < WP * HP; e += NT) {
-      const int i = e % WP, j = e / WP;
-      const int gx = wrap_r(x0 - 3 + i, g.nx, near), gy = wrap_r(y0 - 3 + j, g.ny, near);
-      sphi[slot][e] = a.phi[gx + g.nx * (gy + g.ny * pz)];
+  // phi plane p -> registers (issued one iteration before it is stored).
+  S pf[NPF];
+  auto fetch_phi = [&](int p) {
+    const int pz = wrap_any(p, g.nz);
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+      const int e = tid + k * NT;
+      if (e < WP * HP) {
+        const int i = e % WP, j = e / WP;
+        const int gx = wrap_r(x0 - 3 + i, g.nx, near), gy = wrap_r(y0 - 3 + j, g.ny, near);
+        pf[k] = a.phi[gx + g.nx * (gy + g.ny * pz)];
+      }
+    }
+  };
+  auto store_phi = [&](int p) {
+    const int slot = ring(p, NR);
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+      const int e = tid + k * NT;
+      if (e < WP * HP) sphi[slot][e] = pf[k];
+    }
+  };
+  // Advecting velocity at the J elements of plane p.
+  S uv[NJ][D];
+  auto fetch_u = [&](int p) {
+    const int pz = wrap_any(p, g.nz);
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) {
+      const int e = tid + k * NT;
+      if (e < WJ * HJ) {
+        const int i = e % WJ, j = e / WJ;
+        const int gx = wrap_r(x0 - 1 + i, g.nx, near), gy = wrap_r(y0 - 1 + j, g.ny, near);
+        const int site = gx + g.nx * (gy + g.ny * pz);
+#pragma unroll
+        for (int c = 0; c < D; ++c) uv[k][c] = uval(a, c, site);
+      }
     }
   };
   auto comp_mu = [&](int p) {
@@ -628,59 +764,77 @@ __device__ __forceinline__ void stage_fv_body(const StageArgs<S>& a, int bx, int
     }
   };
   auto comp_J = [&](int p) {
-    const int slot = ring(p, NR), pz = wrap_any(p, g.nz);
-    for (int e = tid; e < WJ * HJ; e += NT) {
-      const int i = e % WJ, j = e / WJ;
-      S gm[3] = {0, 0, 0};
+    const int slot = ring(p, NR);
 #pragma unroll
-      for (int q = 1; q < Q; ++q) {
-        const S t = S(L::w[q]) * smu[ring(p + L::cz[q], NR)][(i + 1 + L::cx[q]) + WM * (j + 1 + L::cy[q])];
-        if (L::cx[q]) gm[0] += L::cx[q] * t;
-        if (L::cy[q]) gm[1] += L::cy[q] * t;
-        if (L::cz[q]) gm[2] += L::cz[q] * t;
+    for (int k = 0; k < NJ; ++k) {
+      const int e = tid + k * NT;
+      if (e < WJ * HJ) {
+        const int i = e % WJ, j = e / WJ;
+        S gm[3] = {0, 0, 0};
+#pragma unroll
+        for (int q = 1; q < Q; ++q) {
+          const S t = S(L::w[q]) * smu[ring(p + L::cz[q], NR)][(i + 1 + L::cx[q]) + WM * (j + 1 + L::cy[q])];
+          if (L::cx[q]) gm[0] += L::cx[q] * t;
+          if (L::cy[q]) gm[1] += L::cy[q] * t;
+          if (L::cz[q]) gm[2] += L::cz[q] * t;
+        }
+        const S ph = sphi[slot][(i + 2) + WP * (j + 2)];
+#pragma unroll
+        for (int c = 0; c < D; ++c) sJ[c][e] = -uv[k][c] * ph + a.c.M * (S(3) * gm[c]);
       }
-      const S ph = sphi[slot][(i + 2) + WP * (j + 2)];
-      const int gx = wrap_r(x0 - 1 + i, g.nx, near), gy = wrap_r(y0 - 1 + j, g.ny, near);
-      const int site = gx + g.nx * (gy + g.ny * pz);
-#pragma unroll
-      for (int c = 0; c < D; ++c) sJ[slot][c][e] = -uval(a, c, site) * ph + a.c.M * (S(3) * gm[c]);
     }
   };
-  auto comp_G = [&](int t) {
-    const int x = x0 + tx, y = y0 + ty;
-    if (x >= g.nx || y >= g.ny) return;
-    S acc = 0;
+  // Fold J of one plane into the partial sums of G for the planes at offsets
+  // -1, 0, +1 from it (a tap with z-velocity cz reaches G at plane p - cz).
+  S gpart[3] = {0, 0, 0};  // G(p-1), G(p), G(p+1)
+  auto fold_J = [&]() {
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
-      const int slot = ring(t + L::cz[q], NR);
       const int e = (tx + 1 + L::cx[q]) + WJ * (ty + 1 + L::cy[q]);
       S v = 0;
-      if (L::cx[q]) v += L::cx[q] * sJ[slot][0][e];
-      if (L::cy[q]) v += L::cy[q] * sJ[slot][1][e];
-      if (D == 3 && L::cz[q]) v += L::cz[q] * sJ[slot][D - 1][e];
-      acc += S(L::w[q]) * v;
+      if (L::cx[q]) v += L::cx[q] * sJ[0][e];
+      if (L::cy[q]) v += L::cy[q] * sJ[1][e];
+      if (D == 3 && L::cz[q]) v += L::cz[q] * sJ[D - 1][e];
+      gpart[1 - L::cz[q]] += S(L::w[q]) * v;
     }
-    const int s = x + g.nx * (y + g.ny * t);
-    combine(a, s, S(3) * acc + a.noise[s]);
   };
 
   if constexpr (D == 2) {
-    load_phi(0);
+    fetch_phi(0);
+    fetch_u(0);
+    SiteIn<S> sv{};
+    if (live) sv = fetch_site(a, x + g.nx * y);
+    store_phi(0);
     __syncthreads();
     comp_mu(0);
     __syncthreads();
     comp_J(0);
     __syncthreads();
-    comp_G(0);
+    fold_J();
+    if (live) combine_in(a, x + g.nx * y, S(3) * gpart[1] + sv.noise, sv);
   } else {
+    fetch_phi(z0 - 3);
     for (int t = z0 - 6; t < z1; ++t) {
-      load_phi(t + 3);
+      // Iteration t: phi(t+3) stored, mu(t+2), J(t+1) folded, G(t) emitted.
+      store_phi(t + 3);
+      if (t + 1 < z1) fetch_phi(t + 4);
+      const bool do_mu = t + 2 >= z0 - 2, do_J = t + 1 >= z0 - 1, do_G = t >= z0 && live;
+      if (do_J) fetch_u(t + 1);
+      const int s = x + g.nx * (y + g.ny * t);
+      SiteIn<S> sv{};
+      if (do_G) sv = fetch_site(a, s);
       __syncthreads();
-      if (t + 2 >= z0 - 2) comp_mu(t + 2);
+      if (do_mu) comp_mu(t + 2);
       __syncthreads();
-      if (t + 1 >= z0 - 1) comp_J(t + 1);
+      if (do_J) comp_J(t + 1);
       __syncthreads();
-      if (t >= z0) comp_G(t);
+      if (do_J) {
+        fold_J();  // J(t+1) -> G(t), G(t+1), G(t+2)
+        if (do_G) combine_in(a, s, S(3) * gpart[0] + sv.noise, sv);
+        gpart[0] = gpart[1];
+        gpart[1] = gpart[2];
+        gpart[2] = 0;
+      }
     }
   }
 }

@@ -57,6 +57,11 @@ class lbl_kernel_time(ctypes.Structure):
                 ("total_ms", ctypes.c_double)]
 
 
+class lbl_schedule(ctypes.Structure):
+    _fields_ = [("lb_width", ctypes.c_int32), ("xcd_swizzle", ctypes.c_int32),
+                ("zc", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class lbl_pool_info(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("used_bytes", ctypes.c_uint64),
                 ("queued", ctypes.c_int64), ("running", ctypes.c_int64),
@@ -113,6 +118,10 @@ def library():
                                       ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.lbl_timing_read.restype = ctypes.c_int
         vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.lbl_set_schedule.argtypes = [vp, P(lbl_schedule)]
+        L.lbl_set_schedule.restype = ctypes.c_int
+        L.lbl_get_schedule.argtypes = [vp, P(lbl_schedule)]
+        L.lbl_get_schedule.restype = ctypes.c_int
         L.lbl_sim_bytes.argtypes = [P(lbl_params)]
         L.lbl_sim_bytes.restype = ctypes.c_uint64
         L.lbl_pool_create.argtypes = [ctypes.c_uint64, P(lbl_env), P(vp)]
@@ -329,6 +338,24 @@ class Sim:
         if rc != LBL_OK:
             raise LblError(rc, lbl_last_error(self.handle))
         return rows
+
+    def set_schedule(self, lb_width=None, xcd_swizzle=None, zc=0):
+        """Launch schedule (speed only): LB block width along x (32..256),
+        XCD-contiguous block order, planes per SMOL tile (0 keeps)."""
+        cur = self.schedule()
+        sch = lbl_schedule(int(lb_width if lb_width is not None else cur["lb_width"]),
+                           int(bool(xcd_swizzle if xcd_swizzle is not None
+                                    else cur["xcd_swizzle"])), int(zc), 0)
+        rc = library().lbl_set_schedule(self.handle, ctypes.byref(sch))
+        if rc != LBL_OK:
+            raise LblError(rc, lbl_last_error(self.handle))
+
+    def schedule(self):
+        sch = lbl_schedule()
+        rc = library().lbl_get_schedule(self.handle, ctypes.byref(sch))
+        if rc != LBL_OK:
+            raise LblError(rc, lbl_last_error(self.handle))
+        return {"lb_width": sch.lb_width, "xcd_swizzle": sch.xcd_swizzle, "zc": sch.zc}
 
     def close(self):
         if getattr(self, "handle", None):
