@@ -1,17 +1,26 @@
 """Benchmark of the coupled FLBE + SMOL sweep on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                [--no-cpu-baseline] [--no-batched] [--no-served]
+                [--serve-rate R] [--serve-seconds T] [--no-tune]
 
 Prints ONE JSON line.  A "step" is one full coupled time step (LB collide and
 stream with noise, chemical potential, force, SMOL Runge-Kutta with noise) over
 the whole lattice, with the state already resident in HBM.  value = lattice
 sites x steps / wall time of the timed region (MLUPS, million lattice-site
-updates per second).  The kernel roofline figure is measured live with HIP
-events on the library's stream during the same timed region.
+updates per second) of the plain single-simulation FP64 run.  The kernel
+roofline figure is measured live with HIP events on the library's stream
+during the same timed region.
+
+Beside it the line carries the FP32-deviation run of the same lattice, the
+batched ensemble (96 uneven D2Q9 replicas in one pool, FP32 and FP64) and the
+served mix (Poisson arrivals into a pool with an HBM budget; p50/p99
+completion latency and aggregate MLUPS).
 """
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -118,13 +127,203 @@ def cpu_baseline(w, workload_name):
                 nsteps, workload_name, N, dt)}
 
 
+def make_sim_params(lbl, w, precision=None, seed=1234):
+    return lbl.make_params(lattice=w["lattice"], smol=w["smol"],
+                           precision=w["precision"] if precision is None else precision,
+                           shape=w["shape"], rho=1.0, eta=w["eta"], M=w["M"], a=w["a"],
+                           b=w["b"], kappa=w["kappa"], kT=w["kT"], seed=seed)
+
+
+def run_single(lbl, torch, w, wname, steps, warmup, tune, precision=None):
+    """Plain single-simulation run: warm-up, then `steps` timed steps."""
+    from paper_1104_0078_amd import autotune
+    params = make_sim_params(lbl, w, precision)
+    init = lbl.make_init(kind=w["init"], psi_std=w["psi_std"])
+    stream = torch.cuda.current_stream()
+    N = w["shape"][0] * w["shape"][1] * w["shape"][2]
+    with lbl.Sim(params, init, device=0, stream=stream) as sim:
+        tuned = autotune.tune_sim(sim, params) if tune else None
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        sim.timing(True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        sim.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_ms = ev0.elapsed_time(ev1)
+        ktimes = sim.kernel_times()
+        sim.timing(False)
+        tot = sim.observe(lbl.LBL_OBS_TOTALS)
+        schedule = sim.schedule()
+    seconds = max(wall, gpu_ms / 1e3)
+    return {"N": N, "seconds": seconds, "mlups": N * steps / seconds / 1e6,
+            "ms_per_step": seconds * 1e3 / steps, "ktimes": ktimes, "totals": tot,
+            "schedule": schedule, "tuned_from_cache": None if tuned is None else
+            tuned["from_cache"]}
+
+
+ENSEMBLE_SIDES = (32, 48, 64, 96, 128, 192, 256)
+
+
+def ensemble_requests(lbl, precision, nrep=96, seed=1234):
+    """96 independent D2Q9 + FD replicas: square sides drawn uniformly from
+    ENSEMBLE_SIDES, a_r ~ U[0.01, 0.1], b = 0.1, kappa = 0.05, M = 0.1,
+    kT = 1e-5, eta = 0.1, Philox seed 1234 + r, psi0 = N(0, 1e-3)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    sides = rng.choice(ENSEMBLE_SIDES, size=nrep)
+    avals = rng.uniform(0.01, 0.1, size=nrep)
+    out = []
+    for r in range(nrep):
+        L = int(sides[r])
+        p = lbl.make_params(lattice=lbl.LBL_D2Q9, smol=lbl.LBL_SMOL_FD, precision=precision,
+                            shape=(L, L, 1), rho=1.0, eta=0.1, M=0.1, a=float(avals[r]), b=0.1,
+                            kappa=0.05, kT=1e-5, seed=seed + r)
+        out.append((p, L * L))
+    return out
+
+
+def run_ensemble(lbl, torch, precision, nsteps, tune, tick=500):
+    """All replicas resident in one pool; each tick of `tick` steps of every
+    replica is one captured graph, replayed until all are done."""
+    from paper_1104_0078_amd import autotune
+    reqs = ensemble_requests(lbl, precision)
+    init = lbl.make_init(kind=0, psi_std=1e-3)
+    sites = sum(n for _, n in reqs)
+    res = {"replicas": len(reqs), "sites": sites, "steps": nsteps}
+    if tune:
+        # Tune on a short copy of the same ensemble (not timed).
+        with lbl.Pool(64 << 30) as pool:
+            for p, _ in reqs:
+                pool.submit(p, init, 1000)
+            pool.run(0)
+            t = autotune.tune_pool(pool, "ensemble96/D2Q9/FD/%s" % (
+                "fp32" if precision else "fp64"), steps=8)
+            res["schedule"] = t["schedule"]
+    with lbl.Pool(64 << 30) as pool:
+        if tune:
+            pool.set_schedule(**res["schedule"])
+        ids = [pool.submit(p, init, nsteps) for p, _ in reqs]
+        pool.run(0)  # admission: create and initialise every replica (not timed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pending = len(ids)
+        while pending:
+            pending = pool.run(tick)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        states = [pool.poll(i)[0] for i in ids]
+        drift = 0.0
+        for i in ids:
+            tot = pool.result(i, lbl.LBL_RES_TOTALS)
+            drift = max(drift, abs(tot[10] - tot[0]) / max(abs(tot[0]), 1e-300))
+        res["schedule"] = pool.schedule()
+    res.update({"seconds": round(dt, 4), "mlups": round(sites * nsteps / dt / 1e6, 1),
+                "all_done": all(st == lbl.LBL_REQ_DONE for st in states),
+                "max_mass_drift_rel": drift})
+    return res
+
+
+def served_mix(rate, seconds, seed=1234):
+    """Poisson arrivals: (arrival time, kind) with 70% D2Q9 (side 64-512) and
+    30% D3Q19 (side 64-192), one- or two-phase and FP32 or FP64 with
+    probability 1/2 each, steps log-uniform in [500, 20000]."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > seconds:
+            break
+        d3 = rng.random() < 0.3
+        side = int(rng.integers(64, 193)) if d3 else int(rng.integers(64, 513))
+        two_phase = rng.random() < 0.5
+        fp32 = rng.random() < 0.5
+        steps = int(round(math.exp(rng.uniform(math.log(500), math.log(20000)))))
+        out.append({"t": t, "d3": d3, "side": side, "two_phase": two_phase, "fp32": fp32,
+                    "steps": steps})
+    return out
+
+
+def run_served(lbl, torch, rate, seconds, budget_gb=200, tick=200, seed=1234):
+    """Real-time serving loop over a pool: requests are submitted when their
+    arrival time has passed, every tick advances all resident requests by up
+    to `tick` steps, finished ones return S(k) and totals and are released.
+    Latency = completion (end of the tick that finished it) - arrival."""
+    import numpy as np
+    mix = served_mix(rate, seconds, seed)
+    lat, lups, drift = [], 0.0, 0.0
+    with lbl.Pool(int(budget_gb * 1e9)) as pool:
+        live = {}
+        nxt = 0
+        t_start = time.monotonic()
+        while nxt < len(mix) or live:
+            now = time.monotonic() - t_start
+            while nxt < len(mix) and mix[nxt]["t"] <= now:
+                r = mix[nxt]
+                i = nxt
+                nxt += 1
+                if r["two_phase"]:
+                    a, b, init = -0.04, 0.04, lbl.make_init(kind=1, psi_std=1e-3)
+                else:
+                    a, b, init = 0.04, 0.1, lbl.make_init(kind=0, psi_std=1e-3)
+                shape = (r["side"],) * 3 if r["d3"] else (r["side"], r["side"], 1)
+                p = lbl.make_params(
+                    lattice=lbl.LBL_D3Q19 if r["d3"] else lbl.LBL_D2Q9,
+                    smol=lbl.LBL_SMOL_FV if r["d3"] else lbl.LBL_SMOL_FD,
+                    precision=1 if r["fp32"] else 0, shape=shape, rho=1.0, eta=0.1, M=0.1,
+                    a=a, b=b, kappa=0.05, kT=1e-5, seed=seed + i)
+                rid = pool.submit(p, init, r["steps"])
+                live[rid] = (r, shape[0] * shape[1] * shape[2])
+            if not live:
+                time.sleep(min(0.01, max(0.0, mix[nxt]["t"] - now)))
+                continue
+            pool.run(tick)
+            t_end = time.monotonic() - t_start
+            for rid in list(live):
+                st, _ = pool.poll(rid)
+                if st in (lbl.LBL_REQ_DONE, lbl.LBL_REQ_FAILED):
+                    r, n = live.pop(rid)
+                    if st == lbl.LBL_REQ_DONE:
+                        lat.append(t_end - r["t"])
+                        lups += n * r["steps"]
+                        pool.result(rid, lbl.LBL_RES_SK_AXES)
+                        tot = pool.result(rid, lbl.LBL_RES_TOTALS)
+                        drift = max(drift, abs(tot[10] - tot[0]) / max(abs(tot[0]), 1e-300))
+                    pool.release(rid)
+        t_total = time.monotonic() - t_start
+        info = pool.stats()
+    lat = np.array(lat) if lat else np.zeros(1)
+    return {"rate_per_s": rate, "window_s": seconds, "requests": len(mix),
+            "completed": int(len(lat)) if len(mix) else 0, "failed": int(info["failed"]),
+            "p50_s": round(float(np.percentile(lat, 50)), 3),
+            "p99_s": round(float(np.percentile(lat, 99)), 3),
+            "aggregate_mlups": round(lups / t_total / 1e6, 1), "wall_s": round(t_total, 2),
+            "budget_gb": budget_gb, "max_mass_drift_rel": drift,
+            "mix": "70% D2Q9+FD side U{64..512}, 30% D3Q19+FV side U{64..192}; one/two-phase, "
+                   "FP32/FP64 50/50; steps log-uniform [500, 20000]; S(k) and totals returned"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=5000)
+    ap.add_argument("--serve-rate", type=float, default=2.0,
+                    help="Poisson arrival rate (requests/s); the full mix is 20/s")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="arrival window (s); the full mix is 300 s")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 2 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -146,37 +345,15 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_each_way": n * 8, "launches": 5}))
         return
 
+    tune = not args.no_tune
     w = WORKLOADS[args.workload]
-    params = lbl.make_params(lattice=w["lattice"], smol=w["smol"], precision=w["precision"],
-                             shape=w["shape"], rho=1.0, eta=w["eta"], M=w["M"], a=w["a"],
-                             b=w["b"], kappa=w["kappa"], kT=w["kT"], seed=1234)
-    init = lbl.make_init(kind=w["init"], psi_std=w["psi_std"])
-    stream = torch.cuda.current_stream()
-    N = w["shape"][0] * w["shape"][1] * w["shape"][2]
-    with lbl.Sim(params, init, device=0, stream=stream) as sim:
-        sim.step(args.warmup)
-        torch.cuda.synchronize()
-        sim.timing(True)
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ev0.record(stream)
-        sim.step(args.steps)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        gpu_ms = ev0.elapsed_time(ev1)
-        ktimes = sim.kernel_times()
-        sim.timing(False)
-        tot = sim.observe(lbl.LBL_OBS_TOTALS)
-    seconds = max(wall, gpu_ms / 1e3)
-    ms_per_step = seconds * 1e3 / args.steps
-    mlups = N * args.steps / seconds / 1e6
+    r = run_single(lbl, torch, w, args.workload, args.steps, args.warmup, tune)
+    N = r["N"]
+    print("single run done: %.1f MLUPS" % r["mlups"], file=sys.stderr, flush=True)
     # Per-kernel HBM roofline from the event timings; the dominant kernel is
     # the one with the largest share of device time.
     per_kernel = {}
-    for kname, klaunch, kms in ktimes:
+    for kname, klaunch, kms in r["ktimes"]:
         avg_s = kms / klaunch / 1e3
         kb = kernel_alg_bytes_per_site(kname, w)
         if kb is None:
@@ -188,17 +365,17 @@ def main():
                              "traffic": traffic_for(kname, args.workload),
                              "avg_launch_ms": round(avg_s * 1e3, 4), "launches": klaunch,
                              "alg_bytes_per_site": kb}
-    dom = max(ktimes, key=lambda r: r[2])[0]
+    dom = max(r["ktimes"], key=lambda t: t[2])[0]
     roofline = per_kernel.get(dom)
-    step_frac = mlups * 1e6 * alg_bytes_per_site(w) / (HBM_PEAK_GBS * 1e9)
+    step_frac = r["mlups"] * 1e6 * alg_bytes_per_site(w) / (HBM_PEAK_GBS * 1e9)
     out = {
         "metric": METRIC,
-        "value": round(mlups, 2),
+        "value": round(r["mlups"], 2),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(r["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -208,16 +385,36 @@ def main():
                    "smol": "FD" if w["smol"] == 0 else "FV",
                    "storage": "fp64" if w["precision"] == 0 else "fp32-deviation",
                    "shape": list(w["shape"]), "sites": N, "global_batch": 1,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "schedule": r["schedule"]},
         "hbm_alg_frac_step": round(step_frac, 4),
         "alg_bytes_per_site_step": alg_bytes_per_site(w),
         "roofline": roofline,
         "kernel_rooflines": {k: {"frac": v["frac"], "achieved": v["achieved"],
                                  "avg_launch_ms": v["avg_launch_ms"]}
                              for k, v in per_kernel.items()},
-        "kernels_ms_per_step": {r[0]: round(r[2] / max(1, args.steps), 4) for r in ktimes},
-        "mass_total": tot[0],
+        "kernels_ms_per_step": {t[0]: round(t[2] / max(1, args.steps), 4) for t in r["ktimes"]},
+        "mass_total": r["totals"][0],
     }
+    if w["precision"] == 0:
+        r32 = run_single(lbl, torch, w, args.workload, args.steps, args.warmup, tune, precision=1)
+        out["fp32dev_same_lattice"] = {"value": round(r32["mlups"], 2), "unit": "MLUPS",
+                                       "ms_per_step": round(r32["ms_per_step"], 4),
+                                       "schedule": r32["schedule"]}
+        print("fp32 run done: %.1f MLUPS" % r32["mlups"], file=sys.stderr, flush=True)
+    if not args.no_batched:
+        out["batched"] = {}
+        for prec, name in ((1, "fp32"), (0, "fp64")):
+            out["batched"][name] = run_ensemble(lbl, torch, prec, args.ensemble_steps, tune)
+            print("ensemble %s done: %.1f MLUPS" % (name, out["batched"][name]["mlups"]),
+                  file=sys.stderr, flush=True)
+    if not args.no_served:
+        out["served"] = run_served(lbl, torch, args.serve_rate, args.serve_seconds)
+        if args.serve_rate != 20.0 or args.serve_seconds != 300.0:
+            out["served"]["sample"] = ("bounded sample of the 20/s x 300 s mix (rate %.3g/s, "
+                                       "window %.3g s)" % (args.serve_rate, args.serve_seconds))
+        print("served done: p50 %.2f s p99 %.2f s" % (out["served"]["p50_s"],
+                                                       out["served"]["p99_s"]),
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.workload)
     print(json.dumps(out), flush=True)

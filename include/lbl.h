@@ -275,8 +275,10 @@ int lbl_pool_submit(lbl_pool *pool, const lbl_params *params, const lbl_init *in
 
 /* One tick: admit what fits, advance every running request by up to
  * max_steps steps (each stops at its own step count), retire the finished
- * ones.  Synchronises the pool's stream.  *pending (may be NULL) receives the
- * number of queued plus running requests afterwards. */
+ * ones.  max_steps = 0 only admits (creating and initialising the admitted
+ * requests and their work tables).  Synchronises the pool's stream.
+ * *pending (may be NULL) receives the number of queued plus running requests
+ * afterwards.  Errors: LBL_E_INVAL (NULL pool, max_steps < 0). */
 int lbl_pool_run(lbl_pool *pool, int64_t max_steps, int64_t *pending);
 
 /* State and completed steps of a request.  LBL_E_INVAL for an unknown id. */
@@ -297,10 +299,14 @@ int lbl_pool_release(lbl_pool *pool, int64_t request);
 
 int lbl_pool_stats(const lbl_pool *pool, lbl_pool_info *out);
 
-/* Work-table schedule of the batched launches: xcd_swizzle != 0 maps
- * consecutive tiles of a request to the same XCD (L2); zc > 0 overrides the
- * planes per tile of the 3-D kernels (0 = automatic). */
-int lbl_pool_set_schedule(lbl_pool *pool, int32_t xcd_swizzle, int32_t zc);
+/* Work-table schedule of the batched launches (speed only, never results):
+ * lb_width as for lbl_set_schedule (tiles of the LB work table);
+ * xcd_swizzle != 0 gives each XCD a contiguous range of each work table, so
+ * a request's neighbouring tiles share one L2; zc > 0 overrides the planes
+ * per tile of the 3-D SMOL kernels (0: each request's own).  Takes effect at
+ * the next lbl_pool_run.  Errors: LBL_E_INVAL. */
+int lbl_pool_set_schedule(lbl_pool *pool, const lbl_schedule *schedule);
+int lbl_pool_get_schedule(const lbl_pool *pool, lbl_schedule *out);
 
 /* Device memory one simulation with these parameters needs (0 if invalid). */
 uint64_t lbl_sim_bytes(const lbl_params *params);

@@ -563,8 +563,9 @@ struct Impl {
 
   // Fill the descriptor array for `sims` (host memory, replica_bytes() each)
   // and the two work tables.
-  static void tables(const std::vector<lbl_sim*>& sims, int zc_override, void* reps_host,
-                     std::vector<Work>& wlb, std::vector<Work>& wtile) {
+  static void tables(const std::vector<lbl_sim*>& sims, int zc_override, int lb_lw,
+                     void* reps_host, std::vector<Work>& wlb, std::vector<Work>& wtile) {
+    const int lbw = 1 << lb_lw, lbh = kSiteBlock >> lb_lw;
     Replica<S>* reps = static_cast<Replica<S>*>(reps_host);
     wlb.clear();
     wtile.clear();
@@ -574,8 +575,8 @@ struct Impl {
       reps[i] = replica(s, zc);
       const int rep = static_cast<int>(i);
       for (int bz = 0; bz < s->p.nz; ++bz)
-        for (int by = 0; by < (s->p.ny + kBY - 1) / kBY; ++by)
-          for (int bx = 0; bx < (s->p.nx + kBX - 1) / kBX; ++bx) wlb.push_back(Work{rep, bx, by, bz});
+        for (int by = 0; by < (s->p.ny + lbh - 1) / lbh; ++by)
+          for (int bx = 0; bx < (s->p.nx + lbw - 1) / lbw; ++bx) wlb.push_back(Work{rep, bx, by, bz});
       const int nzc = Lat<Q>::D == 3 ? (s->p.nz + zc - 1) / zc : 1;
       for (int bz = 0; bz < nzc; ++bz)
         for (int by = 0; by < (s->p.ny + kTY - 1) / kTY; ++by)
@@ -586,17 +587,18 @@ struct Impl {
   // Enqueue `nsteps` batched steps of a group on `stream` (captured by the
   // caller into a graph).
   static int enqueue_group(hipStream_t stream, const void* reps_dev, RepState* states, int nrep,
-                           const Work* wlb, int nlb, const Work* wtile, int ntile, int rk,
-                           bool ghost, int64_t nsteps) {
+                           const Work* wlb, int nlb, int lb_lw, const Work* wtile, int ntile,
+                           int rk, bool ghost, int64_t nsteps) {
     const Replica<S>* reps = static_cast<const Replica<S>*>(reps_dev);
-    const dim3 bsite(kBX, kBY), btile(kTX, kTY);
+    const dim3 bsite(kSiteBlock), btile(kTX, kTY);
     for (int64_t k = 0; k < nsteps; ++k) {
       kb_prep<S, Q, SMOL><<<ntile, btile, 0, stream>>>(reps, states, wtile);
       if (ghost)
-        kb_lb<S, DEV, Q, SMOL, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb);
+        kb_lb<S, DEV, Q, SMOL, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw);
       else
-        kb_lb<S, DEV, Q, SMOL, false><<<nlb, bsite, 0, stream>>>(reps, states, wlb);
-      if (rk > 1) kb_uend<S, DEV, Q, SMOL><<<nlb, bsite, 0, stream>>>(reps, states, wlb, rk);
+        kb_lb<S, DEV, Q, SMOL, false><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw);
+      if (rk > 1)
+        kb_uend<S, DEV, Q, SMOL><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw, rk);
       for (int st = 0; st < rk; ++st)
         kb_stage<S, Q, SMOL><<<ntile, btile, 0, stream>>>(reps, states, wtile, st, rk);
       kb_advance<S><<<(nrep + 255) / 256, 256, 0, stream>>>(reps, states, nrep);
@@ -655,10 +657,10 @@ using StepFn = int (*)(lbl_sim*, int64_t);
 using InitFn = int (*)(lbl_sim*, const lbl_init*);
 using ObsFn = int (*)(lbl_sim*, int, double*);
 
-using TablesFn = void (*)(const std::vector<lbl_sim*>&, int, void*, std::vector<Work>&,
+using TablesFn = void (*)(const std::vector<lbl_sim*>&, int, int, void*, std::vector<Work>&,
                           std::vector<Work>&);
-using EnqueueFn = int (*)(hipStream_t, const void*, RepState*, int, const Work*, int, const Work*,
-                          int, int, bool, int64_t);
+using EnqueueFn = int (*)(hipStream_t, const void*, RepState*, int, const Work*, int, int,
+                          const Work*, int, int, bool, int64_t);
 
 struct Table {
   StepFn step;
@@ -778,6 +780,10 @@ int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* e
     while (zc > 8 && bxy * ((params->nz + zc - 1) / zc) < 2048) zc = (zc + 1) / 2;
     s->zc = std::max(1, zc);
   }
+  // LB blocks: the widest power of two up to 256 that fits along x (whole
+  // rows where possible, so that pulls shifted along x stay inside a block).
+  s->lb_lw = 5;
+  while (s->lb_lw < 8 && (2 << s->lb_lw) <= params->nx) ++s->lb_lw;
   s->nparts = std::min(1024, std::max(1, grid_for(s->N)));
   const std::vector<size_t> plan = alloc_plan(*params);
   std::vector<void*> bufs;
@@ -875,6 +881,7 @@ struct Group {
   std::vector<int64_t> members;
   DevBuf reps, states, wlb, wtile;
   int nlb = 0, ntile = 0;
+  int lb_lw = 6;  // tile width the LB work table was built with
   bool dirty = true;
   hipGraphExec_t exec = nullptr;
   int64_t exec_steps = 0;
@@ -897,6 +904,7 @@ struct lbl_pool {
   std::map<GroupKey, Group> groups;
   int xcd_swizzle = 1;
   int zc_override = 0;
+  int lb_lw = 6;  // log2 of the LB tile width of the batched launches
   int64_t ticks = 0, site_updates = 0;
   std::string err;
 };
@@ -1044,7 +1052,7 @@ int run_group(lbl_pool* pl, Group& g, int64_t max_steps) {
     }
     std::vector<unsigned char> reps(t.replica_bytes * n);
     std::vector<Work> wlb, wtile;
-    t.tables(sims, pl->zc_override, reps.data(), wlb, wtile);
+    t.tables(sims, pl->zc_override, pl->lb_lw, reps.data(), wlb, wtile);
     if (pl->xcd_swizzle) {
       xcd_order(wlb);
       xcd_order(wtile);
@@ -1068,6 +1076,7 @@ int run_group(lbl_pool* pl, Group& g, int64_t max_steps) {
     if (e != hipSuccess)
       return pool_fail(pl, LBL_E_DEVICE, std::string("pool tables: ") + hipGetErrorString(e));
     g.nlb = static_cast<int>(wlb.size());
+    g.lb_lw = pl->lb_lw;
     g.ntile = static_cast<int>(wtile.size());
     g.dirty = false;
   }
@@ -1085,7 +1094,7 @@ int run_group(lbl_pool* pl, Group& g, int64_t max_steps) {
     if (e != hipSuccess)
       return pool_fail(pl, LBL_E_DEVICE, std::string("begin capture: ") + hipGetErrorString(e));
     const int rc = t.enqueue(pl->stream, g.reps.ptr, static_cast<RepState*>(g.states.ptr), n,
-                             static_cast<const Work*>(g.wlb.ptr), g.nlb,
+                             static_cast<const Work*>(g.wlb.ptr), g.nlb, g.lb_lw,
                              static_cast<const Work*>(g.wtile.ptr), g.ntile, g.key.rk,
                              g.key.ghost != 0, steps);
     e = hipStreamEndCapture(pl->stream, &graph);
@@ -1398,7 +1407,7 @@ int lbl_pool_submit(lbl_pool* pl, const lbl_params* params, const lbl_init* init
 }
 
 int lbl_pool_run(lbl_pool* pl, int64_t max_steps, int64_t* pending) {
-  if (!pl || max_steps <= 0) return LBL_E_INVAL;
+  if (!pl || max_steps < 0) return LBL_E_INVAL;
   try {
     return pool_run_impl(pl, max_steps, pending);
   } catch (...) {
@@ -1489,14 +1498,28 @@ int lbl_pool_stats(const lbl_pool* pl, lbl_pool_info* out) {
   return LBL_OK;
 }
 
-int lbl_pool_set_schedule(lbl_pool* pl, int32_t xcd_swizzle, int32_t zc) {
-  if (!pl || zc < 0) return LBL_E_INVAL;
-  pl->xcd_swizzle = xcd_swizzle != 0;
-  pl->zc_override = zc;
+int lbl_pool_set_schedule(lbl_pool* pl, const lbl_schedule* sch) {
+  if (!pl || !sch || sch->zc < 0 || sch->reserved != 0) return LBL_E_INVAL;
+  int lw = -1;
+  for (int k = 5; k <= 8; ++k)
+    if (sch->lb_width == (1 << k)) lw = k;
+  if (lw < 0) return LBL_E_INVAL;
+  pl->lb_lw = lw;
+  pl->xcd_swizzle = sch->xcd_swizzle != 0;
+  pl->zc_override = sch->zc;
   for (auto& kv : pl->groups) {
     kv.second.dirty = true;
     drop_graph(kv.second);
   }
+  return LBL_OK;
+}
+
+int lbl_pool_get_schedule(const lbl_pool* pl, lbl_schedule* out) {
+  if (!pl || !out) return LBL_E_INVAL;
+  out->lb_width = 1 << pl->lb_lw;
+  out->xcd_swizzle = pl->xcd_swizzle;
+  out->zc = pl->zc_override;
+  out->reserved = 0;
   return LBL_OK;
 }
 

@@ -72,10 +72,17 @@ __global__ __launch_bounds__(kTX* kTY) void kb_prep(const Replica<S>* __restrict
     prep_fd_body<S, Q>(a, w.bx, w.by, w.bz);
 }
 
+// LB work items are tiles of 2^lw sites along x by 256 / 2^lw rows of one
+// plane (one 256-thread block each).
+__device__ __forceinline__ void lb_tile_site(const Work& w, int lw, int& x, int& y) {
+  x = (w.bx << lw) + (threadIdx.x & ((1 << lw) - 1));
+  y = w.by * (kSiteBlock >> lw) + (threadIdx.x >> lw);
+}
+
 template <typename S, bool DEV, int Q, int SMOL, bool GHOST>
-__global__ __launch_bounds__(kBX* kBY, 5) void kb_lb(const Replica<S>* __restrict__ reps,
-                                                 const RepState* __restrict__ st,
-                                                 const Work* __restrict__ work) {
+__global__ __launch_bounds__(kSiteBlock, 5) void kb_lb(const Replica<S>* __restrict__ reps,
+                                                      const RepState* __restrict__ st,
+                                                      const Work* __restrict__ work, int lw) {
   const Work w = work[blockIdx.x];
   const RepState rs = st[w.rep];
   const Replica<S>& r = reps[w.rep];
@@ -99,7 +106,8 @@ __global__ __launch_bounds__(kBX* kBY, 5) void kb_lb(const Replica<S>* __restric
   a.step = rs.step;
   a.force = r.coupling == kCplFull;
   a.noise = r.noise_on;
-  const int x = w.bx * kBX + threadIdx.x, y = w.by * kBY + threadIdx.y;
+  int x, y;
+  lb_tile_site(w, lw, x, y);
   if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, GHOST, true>(a, x, y, w.bz);
 }
 
@@ -107,9 +115,9 @@ __global__ __launch_bounds__(kBX* kBY, 5) void kb_lb(const Replica<S>* __restric
 // the Runge-Kutta stages at t_{n+1}: the LB body without collision, pulling
 // the populations the step just wrote.
 template <typename S, bool DEV, int Q, int SMOL>
-__global__ __launch_bounds__(kBX* kBY) void kb_uend(const Replica<S>* __restrict__ reps,
-                                                   const RepState* __restrict__ st,
-                                                   const Work* __restrict__ work, int rk) {
+__global__ __launch_bounds__(kSiteBlock) void kb_uend(const Replica<S>* __restrict__ reps,
+                                                     const RepState* __restrict__ st,
+                                                     const Work* __restrict__ work, int lw, int rk) {
   const Work w = work[blockIdx.x];
   const RepState rs = st[w.rep];
   const Replica<S>& r = reps[w.rep];
@@ -124,7 +132,8 @@ __global__ __launch_bounds__(kBX* kBY) void kb_uend(const Replica<S>* __restrict
   a.rho0 = r.rho0;
   a.force = 1;
   a.noise = 0;
-  const int x = w.bx * kBX + threadIdx.x, y = w.by * kBY + threadIdx.y;
+  int x, y;
+  lb_tile_site(w, lw, x, y);
   if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, false, false>(a, x, y, w.bz);
 }
 

@@ -133,13 +133,14 @@ def library():
         L.lbl_pool_result_bytes.restype = ctypes.c_size_t
         L.lbl_pool_release.argtypes = [vp, i64]
         L.lbl_pool_stats.argtypes = [vp, P(lbl_pool_info)]
-        L.lbl_pool_set_schedule.argtypes = [vp, i32, i32]
+        L.lbl_pool_set_schedule.argtypes = [vp, P(lbl_schedule)]
+        L.lbl_pool_get_schedule.argtypes = [vp, P(lbl_schedule)]
         L.lbl_pool_destroy.argtypes = [vp]
         L.lbl_pool_last_error.argtypes = [vp]
         L.lbl_pool_last_error.restype = ctypes.c_char_p
         for n in ("lbl_pool_create", "lbl_pool_submit", "lbl_pool_run", "lbl_pool_poll",
                   "lbl_pool_result", "lbl_pool_release", "lbl_pool_stats",
-                  "lbl_pool_set_schedule", "lbl_pool_destroy"):
+                  "lbl_pool_set_schedule", "lbl_pool_get_schedule", "lbl_pool_destroy"):
             getattr(L, n).restype = ctypes.c_int
         L.lbl_abi_version.argtypes = []
         L.lbl_abi_version.restype = ctypes.c_int
@@ -436,8 +437,19 @@ class Pool:
         self._check(library().lbl_pool_stats(self.handle, ctypes.byref(info)))
         return {k: getattr(info, k) for k, _ in lbl_pool_info._fields_}
 
-    def set_schedule(self, xcd_swizzle=True, zc=0):
-        self._check(library().lbl_pool_set_schedule(self.handle, int(bool(xcd_swizzle)), int(zc)))
+    def set_schedule(self, lb_width=None, xcd_swizzle=None, zc=None):
+        """Work-table schedule of the batched launches (speed only)."""
+        cur = self.schedule()
+        sch = lbl_schedule(int(lb_width if lb_width is not None else cur["lb_width"]),
+                           int(bool(xcd_swizzle if xcd_swizzle is not None
+                                    else cur["xcd_swizzle"])),
+                           int(zc if zc is not None else cur["zc"]), 0)
+        self._check(library().lbl_pool_set_schedule(self.handle, ctypes.byref(sch)))
+
+    def schedule(self):
+        sch = lbl_schedule()
+        self._check(library().lbl_pool_get_schedule(self.handle, ctypes.byref(sch)))
+        return {"lb_width": sch.lb_width, "xcd_swizzle": sch.xcd_swizzle, "zc": sch.zc}
 
     def close(self):
         if getattr(self, "handle", None):

@@ -118,3 +118,22 @@ def test_conservation_on_gpu(lattice, precision):
     tol = 1e-13 if precision == H.FP64 else 1e-6
     assert abs(t1[0] - t0[0]) <= tol * t0[5]
     assert abs(t1[4] - t0[4]) <= tol * t0[9]
+
+
+@pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q19])
+def test_schedule_does_not_change_results(lattice):
+    """Every launch schedule (LB block width, XCD-contiguous block order,
+    planes per SMOL tile) gives bitwise the same fields."""
+    from paper_1104_0078_amd import lbl
+    c = H.config(lattice=lattice, smol=H.FV, shape=SHAPES[lattice], init=0)
+    ini = lbl.make_init(kind=0, psi_std=1e-3)
+    out = []
+    for w, swz, zc in ((64, 0, 0), (256, 0, 0), (128, 1, 0), (32, 1, 3), (256, 1, 5)):
+        with lbl.Sim(H.lbl_params(c), ini) as sim:
+            sim.set_schedule(lb_width=w, xcd_swizzle=swz, zc=zc)
+            assert sim.schedule()["lb_width"] == w
+            sim.step(7)
+            out.append((sim.observe(lbl.LBL_OBS_POP), sim.observe(lbl.LBL_OBS_PSI)))
+    for f, p in out[1:]:
+        np.testing.assert_array_equal(f, out[0][0])
+        np.testing.assert_array_equal(p, out[0][1])

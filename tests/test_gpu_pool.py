@@ -124,9 +124,9 @@ def test_schedule_does_not_change_results():
     from paper_1104_0078_amd import lbl
     c, n = MIX[4]
     out = []
-    for swz, zc in ((0, 0), (1, 0), (1, 8), (0, 40)):
+    for w, swz, zc in ((64, 0, 0), (64, 1, 0), (128, 1, 8), (32, 0, 40), (256, 1, 0)):
         with lbl.Pool(1 << 30) as pool:
-            pool.set_schedule(xcd_swizzle=swz, zc=zc)
+            pool.set_schedule(lb_width=w, xcd_swizzle=swz, zc=zc)
             rid = pool.submit(H.lbl_params(c), lbl.make_init(kind=1, psi_std=1e-3), n,
                               keep_psi=True)
             _run_pool(pool, chunk=6)
