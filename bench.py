@@ -1,8 +1,9 @@
 """Benchmark of the coupled FLBE + SMOL sweep on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                [--no-cpu-baseline] [--no-batched] [--no-served]
-                [--serve-rate R] [--serve-seconds T] [--no-tune]
+                [--no-cpu-baseline] [--no-fp32] [--no-batched] [--no-served]
+                [--serve-rate R] [--serve-seconds T] [--no-tune] [--tune-single]
+                [--schedule W,S,Z]
 
 Prints ONE JSON line.  A "step" is one full coupled time step (LB collide and
 stream with noise, chemical potential, force, SMOL Runge-Kutta with noise) over
@@ -62,16 +63,24 @@ def alg_bytes_per_site(w):
 
 
 def kernel_alg_bytes_per_site(name, w, rk=2):
-    """Algorithmic bytes per site of one launch of each kernel: the data the
-    kernel must move at minimum.
-      k_lb:    read and write the Q populations, read psi;
-      k_prep:  read psi, write mu and the SMOL noise;
-      k_stage: read the stage input, u (d values) and the noise, write the
-               output; the final Heun stage also reads psi^n (per-launch mean)."""
+    """Algorithmic bytes per site of one launch of each kernel: every field
+    the kernel needs read once and every field it produces written once (no
+    halo re-reads); b bytes per stored value, d dimensions.
+      k_lb:    pull the Q populations, read psi and mu (force), write the Q
+               post-collision populations and u^n:          (2Q + 2 + d) b;
+      k_uend:  pull the Q streamed populations, read psi and mu, write the
+               stage velocity at t_{n+1}:                   (Q + 2 + d) b;
+      k_prep:  read psi, write mu and the SMOL noise:        3 b;
+      k_stage: read the stage input, the velocity (d values) and the noise,
+               write the output; the final Heun stage also reads psi^n
+               (mean over the two launches of a step):      (3 + d) b + b/2."""
     b = 8 if w["precision"] == 0 else 4
     d = 2 if w["lattice"] == 9 else 3
+    q = w["lattice"]
     if name.startswith("k_lb"):
-        return 2 * w["lattice"] * b + b
+        return (2 * q + 2 + d) * b
+    if name.startswith("k_uend"):
+        return (q + 2 + d) * b
     if name.startswith("k_prep"):
         return 3 * b
     if name.startswith("k_stage"):
@@ -134,7 +143,7 @@ def make_sim_params(lbl, w, precision=None, seed=1234):
                            b=w["b"], kappa=w["kappa"], kT=w["kT"], seed=seed)
 
 
-def run_single(lbl, torch, w, wname, steps, warmup, tune, precision=None):
+def run_single(lbl, torch, w, wname, steps, warmup, tune, precision=None, schedule=None):
     """Plain single-simulation run: warm-up, then `steps` timed steps."""
     from paper_1104_0078_amd import autotune
     params = make_sim_params(lbl, w, precision)
@@ -142,7 +151,11 @@ def run_single(lbl, torch, w, wname, steps, warmup, tune, precision=None):
     stream = torch.cuda.current_stream()
     N = w["shape"][0] * w["shape"][1] * w["shape"][2]
     with lbl.Sim(params, init, device=0, stream=stream) as sim:
-        tuned = autotune.tune_sim(sim, params) if tune else None
+        tuned = None
+        if schedule is not None:
+            sim.set_schedule(**schedule)
+        elif tune:
+            tuned = autotune.tune_sim(sim, params)
         sim.step(warmup)
         torch.cuda.synchronize()
         sim.timing(True)
@@ -318,7 +331,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the FP32-deviation run of the same lattice")
+    ap.add_argument("--no-tune", action="store_true", help="no autotuning of the pool legs")
+    ap.add_argument("--tune-single", action="store_true",
+                    help="autotune the single-run schedule too (default: the library's own)")
+    ap.add_argument("--schedule", default=None,
+                    help="fix the single-run schedule as lb_width,xcd_swizzle,zc (no tuning)")
     ap.add_argument("--ensemble-steps", type=int, default=5000)
     ap.add_argument("--serve-rate", type=float, default=2.0,
                     help="Poisson arrival rate (requests/s); the full mix is 20/s")
@@ -346,8 +365,13 @@ def main():
         return
 
     tune = not args.no_tune
+    fixed = None
+    if args.schedule:
+        lw_, sw_, zc_ = (int(v) for v in args.schedule.split(","))
+        fixed = dict(lb_width=lw_, xcd_swizzle=sw_, zc=zc_)
     w = WORKLOADS[args.workload]
-    r = run_single(lbl, torch, w, args.workload, args.steps, args.warmup, tune)
+    r = run_single(lbl, torch, w, args.workload, args.steps, args.warmup, args.tune_single,
+                   schedule=fixed)
     N = r["N"]
     print("single run done: %.1f MLUPS" % r["mlups"], file=sys.stderr, flush=True)
     # Per-kernel HBM roofline from the event timings; the dominant kernel is
@@ -395,8 +419,9 @@ def main():
         "kernels_ms_per_step": {t[0]: round(t[2] / max(1, args.steps), 4) for t in r["ktimes"]},
         "mass_total": r["totals"][0],
     }
-    if w["precision"] == 0:
-        r32 = run_single(lbl, torch, w, args.workload, args.steps, args.warmup, tune, precision=1)
+    if w["precision"] == 0 and not args.no_fp32:
+        r32 = run_single(lbl, torch, w, args.workload, args.steps, args.warmup,
+                         args.tune_single, precision=1)
         out["fp32dev_same_lattice"] = {"value": round(r32["mlups"], 2), "unit": "MLUPS",
                                        "ms_per_step": round(r32["ms_per_step"], 4),
                                        "schedule": r32["schedule"]}

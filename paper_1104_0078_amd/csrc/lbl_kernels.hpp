@@ -198,26 +198,6 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
   const Nbr nb(g, x, y, z);
   const int s = nb.at(0, 0, 0);
 
-  // Noise of the non-conserved modes, drawn first: n_k = sigma_k z_k, with
-  // sigma_k^2 = (1 - gamma_k^2) rho0 kT / c_s^2 per mode class.
-  S nk[NB * 4];
-#pragma unroll
-  for (int k = 0; k < NB * 4; ++k) nk[k] = 0;
-  if (COLLIDE && a.noise) {
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      S z4[4];
-      Normal4<S>::gen(static_cast<uint32_t>(s), a.step, b, kTagLB, a.k0, a.k1, z4);
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        const int k = 4 * b + l;
-        if (k >= NR) continue;
-        const S sig = k == 0 ? a.sigma_b : (k < L::NSTRESS ? a.sigma_s : a.sigma_g);
-        nk[k] = sig * z4[l];
-      }
-    }
-  }
-
   // Force density F = -psi grad mu: FD central difference (Sec. IV) or the FV
   // gradient (1/c_s^2) sum_i w_i c_i mu(x + c_i) (Eq. fvgrad).
   S F[3] = {0, 0, 0};
@@ -250,6 +230,27 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
 #pragma unroll
   for (int i = 0; i < Q; ++i)
     fv[i] = a.f_in[static_cast<size_t>(i) * g.N + nb.at(-L::cx[i], -L::cy[i], -L::cz[i])];
+
+  // Noise of the non-conserved modes, n_k = sigma_k z_k, with
+  // sigma_k^2 = (1 - gamma_k^2) rho0 kT / c_s^2 per mode class.  Drawn after
+  // the pulls are issued, so that its arithmetic overlaps their latency.
+  S nk[NB * 4];
+#pragma unroll
+  for (int k = 0; k < NB * 4; ++k) nk[k] = 0;
+  if (COLLIDE && a.noise) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      S z4[4];
+      Normal4<S>::gen(static_cast<uint32_t>(s), a.step, b, kTagLB, a.k0, a.k1, z4);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const int k = 4 * b + l;
+        if (k >= NR) continue;
+        const S sig = k == 0 ? a.sigma_b : (k < L::NSTRESS ? a.sigma_s : a.sigma_g);
+        nk[k] = sig * z4[l];
+      }
+    }
+  }
 
   S S0 = 0, jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
 #pragma unroll
@@ -357,7 +358,7 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
 }
 
 template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool COLLIDE>
-__global__ __launch_bounds__(kSiteBlock, 5) void k_lb(LBArgs<S> a, SiteMap m) {
+__global__ __launch_bounds__(kSiteBlock) void k_lb(LBArgs<S> a, SiteMap m) {
   int x, y, z;
   if (site_of(m, a.g, x, y, z)) lb_body<S, DEV, Q, SMOL, GHOST, COLLIDE>(a, x, y, z);
 }
