@@ -207,16 +207,22 @@ int lbl_timing_read(lbl_sim *sim, lbl_kernel_time *out, int max_entries, int *n_
 /* Launch schedule of one simulation.  It changes only speed, never results.
  * lb_width: sites along x per 256-thread block of the per-site LB kernels
  * (32, 64, 128 or 256; a block covers 256 / lb_width rows of one plane);
- * xcd_swizzle != 0: the blocks are ordered so that each of the 8 XCDs sweeps
- * one contiguous eighth of the lattice (pulls across block edges then hit the
- * same L2); zc: planes per block of the z-marching SMOL kernels of a 3-D
- * lattice (0 keeps the current value, larger than nz is clamped).
- * Errors: LBL_E_INVAL (NULL, unsupported width, zc < 0, reserved != 0). */
+ * xcd_swizzle, bit 0: the LB blocks, bit 1: the SMOL tiles are ordered so
+ * that each of the 8 XCDs sweeps one contiguous eighth of them (reads across
+ * block edges then hit the same L2); zc: planes per block of the z-marching SMOL kernels of a 3-D
+ * lattice (0 keeps the current value, larger than nz is clamped); overlap:
+ * 1 runs the first Runge-Kutta stage on a second stream of the library's
+ * own (default priority), concurrently with the velocity pass of the
+ * streamed populations that only the later stages read (full coupling, 2 or
+ * 4 stages); 0 runs everything on the simulation's stream.  Default: the
+ * widest width up to 256 that fits nx, no swizzle, zc for >= 2048 tiles,
+ * overlap 0.  Errors: LBL_E_INVAL (NULL, unsupported width, zc < 0,
+ * overlap not 0 or 1). */
 typedef struct lbl_schedule {
   int32_t lb_width;
   int32_t xcd_swizzle;
   int32_t zc;
-  int32_t reserved; /* must be 0 */
+  int32_t overlap;
 } lbl_schedule;
 int lbl_set_schedule(lbl_sim *sim, const lbl_schedule *schedule);
 int lbl_get_schedule(const lbl_sim *sim, lbl_schedule *out);
@@ -304,7 +310,7 @@ int lbl_pool_stats(const lbl_pool *pool, lbl_pool_info *out);
  * xcd_swizzle != 0 gives each XCD a contiguous range of each work table, so
  * a request's neighbouring tiles share one L2; zc > 0 overrides the planes
  * per tile of the 3-D SMOL kernels (0: each request's own).  Takes effect at
- * the next lbl_pool_run.  Errors: LBL_E_INVAL. */
+ * the next lbl_pool_run; overlap must be 0.  Errors: LBL_E_INVAL. */
 int lbl_pool_set_schedule(lbl_pool *pool, const lbl_schedule *schedule);
 int lbl_pool_get_schedule(const lbl_pool *pool, lbl_schedule *out);
 

@@ -63,7 +63,10 @@ struct lbl_sim {
   uint32_t k0 = 0, k1 = 0;
   int zc = 1;  // planes per block of the z-marching kernels
   int lb_lw = 6;       // log2 of the LB block width along x
-  int lb_swizzle = 0;  // XCD-contiguous block order of the LB kernels
+  int lb_swizzle = 0;  // XCD-contiguous block order: bit 0 LB kernels, bit 1 tile kernels
+  int overlap = 0;     // first RK stage on `aux`, concurrent with the velocity pass
+  hipStream_t aux = nullptr;  // created on first use (default priority)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double gamma_s = 0, gamma_b = 0, gamma_g = 0, sigma_s = 0, sigma_b = 0, sigma_g = 0;
   int deferred = LBL_OK;
   std::string err;
@@ -156,21 +159,50 @@ int kernel_slot(lbl_sim* s, const char* name) {
 
 // Launch `fn` (a kernel launch on s->stream), bracketed by timing events when
 // timing is enabled, and check the launch.
+// Launch through `fn` on `stream`, bracketed by timing events when timing is on.
 template <class Fn>
-int launch(lbl_sim* s, const char* name, Fn&& fn) {
+int launch_on(lbl_sim* s, hipStream_t stream, const char* name, Fn&& fn) {
   hipEvent_t a = nullptr, b = nullptr;
   if (s->timing) {
     a = take_event(s);
     b = take_event(s);
-    if (a) (void)hipEventRecord(a, s->stream);
+    if (a) (void)hipEventRecord(a, stream);
   }
   fn();
   const hipError_t e = hipGetLastError();
   if (s->timing && a && b) {
-    (void)hipEventRecord(b, s->stream);
+    (void)hipEventRecord(b, stream);
     s->pending.push_back(lbl_sim::Pending{kernel_slot(s, name), a, b});
   }
   return hip_check(s, e, name);
+}
+
+template <class Fn>
+int launch(lbl_sim* s, const char* name, Fn&& fn) {
+  return launch_on(s, s->stream, name, static_cast<Fn&&>(fn));
+}
+
+// Second stream and fork/join events for the concurrent first stage.  Work
+// on `aux` is always joined back into the simulation's stream, so a
+// synchronisation of that stream covers it.
+int ensure_aux(lbl_sim* s) {
+  if (s->aux) return LBL_OK;
+  if (int rc = hip_check(s, hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking), "aux stream"))
+    return rc;
+  if (int rc = hip_check(s, hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming), "event"))
+    return rc;
+  return hip_check(s, hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming), "event");
+}
+
+void destroy_aux(lbl_sim* s) {
+  if (s->aux) {
+    (void)hipStreamSynchronize(s->aux);
+    (void)hipStreamDestroy(s->aux);
+  }
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+  s->aux = nullptr;
+  s->ev_fork = s->ev_join = nullptr;
 }
 
 int drain_timing(lbl_sim* s) {
@@ -338,13 +370,9 @@ struct Impl {
   static dim3 site_grid(const lbl_sim* s) {
     return dim3((s->p.nx + kBX - 1) / kBX, (s->p.ny + kBY - 1) / kBY, s->p.nz);
   }
-  static dim3 tile_grid(const lbl_sim* s) {
-    return dim3((s->p.nx + kTX - 1) / kTX, (s->p.ny + kTY - 1) / kTY,
-                Lat<Q>::D == 3 ? (s->p.nz + s->zc - 1) / s->zc : 1);
-  }
 
   static int launch_lb(lbl_sim* s, const LBArgs<S>& a, bool collide, const char* name) {
-    const SiteMap m = make_site_map(s->p.nx, s->p.ny, s->p.nz, s->lb_lw, s->lb_swizzle != 0);
+    const SiteMap m = make_site_map(s->p.nx, s->p.ny, s->p.nz, s->lb_lw, (s->lb_swizzle & 1) != 0);
     const dim3 grid(site_map_blocks(m)), block(kSiteBlock);
     const bool ghost = s->gamma_g != 0.0;
     if (!collide)
@@ -378,7 +406,10 @@ struct Impl {
     S* u = static_cast<S*>(s->u);
 
     S* noise = static_cast<S*>(s->noise);
-    const dim3 tg = tile_grid(s), tb(kTX, kTY);
+    const TileMap tm = make_tile_map(s->p.nx, s->p.ny,
+                                     Lat<Q>::D == 3 ? (s->p.nz + s->zc - 1) / s->zc : 1,
+                                     (s->lb_swizzle & 2) != 0);
+    const dim3 tg(tile_map_blocks(tm)), tb(kTX, kTY);
     const bool want_noise = cpl != LBL_LB_ONLY && s->p.kT > 0;
     const bool want_mu = cpl == LBL_FULL;
     if (want_noise || want_mu) {
@@ -395,17 +426,26 @@ struct Impl {
       pa.mu = want_mu ? static_cast<S*>(s->mu) : nullptr;
       int rc;
       if (SMOL == kFV)
-        rc = launch(s, "k_prep", [&] { k_prep_fv<S, Q><<<tg, tb, 0, s->stream>>>(pa); });
+        rc = launch(s, "k_prep", [&] { k_prep_fv<S, Q><<<tg, tb, 0, s->stream>>>(pa, tm); });
       else
-        rc = launch(s, "k_prep", [&] { k_prep_fd<S, Q><<<tg, tb, 0, s->stream>>>(pa); });
+        rc = launch(s, "k_prep", [&] { k_prep_fd<S, Q><<<tg, tb, 0, s->stream>>>(pa, tm); });
       if (rc) return rc;
     }
     if (cpl != LBL_SMOL_ONLY) {
       const LBArgs<S> a = lb_args(s, fin, fout, psin, u, cpl == LBL_FULL, n);
       if (int rc = launch_lb(s, a, true, "k_lb")) return rc;
     }
-    if (cpl == LBL_FULL && s->p.rk_stages > 1) {
-      // Velocity of the streamed populations for the stages at t_{n+1}.
+    // The velocity of the streamed populations (for the stages at t_{n+1})
+    // and the first stage (at t_n) are independent: with `overlap` the first
+    // stage runs on the second stream while the velocity pass runs here.
+    const bool uend = cpl == LBL_FULL && s->p.rk_stages > 1;
+    const bool fork = uend && s->overlap;
+    if (fork) {
+      if (int rc = ensure_aux(s)) return rc;
+      if (int rc = hip_check(s, hipEventRecord(s->ev_fork, s->stream), "fork")) return rc;
+      if (int rc = hip_check(s, hipStreamWaitEvent(s->aux, s->ev_fork, 0), "fork")) return rc;
+    }
+    if (uend && !fork) {
       const LBArgs<S> a = lb_args(s, fout, nullptr, psin, static_cast<S*>(s->u_end), 1, n);
       if (int rc = launch_lb(s, a, false, "k_uend")) return rc;
     }
@@ -441,14 +481,20 @@ struct Impl {
           a.cacc = S(ca4[st]);
         }
         a.out = a.last ? psout : static_cast<S*>(s->phi[st & 1]);
+        const hipStream_t ss = (fork && st == 0) ? s->aux : s->stream;
         int rc;
         if (SMOL == kFV)
-          rc = launch(s, "k_stage",
-                      [&] { k_stage_fv<S, Q><<<tg, tb, 0, s->stream>>>(a); });
+          rc = launch_on(s, ss, "k_stage", [&] { k_stage_fv<S, Q><<<tg, tb, 0, ss>>>(a, tm); });
         else
-          rc = launch(s, "k_stage",
-                      [&] { k_stage_fd<S, Q><<<tg, tb, 0, s->stream>>>(a); });
+          rc = launch_on(s, ss, "k_stage", [&] { k_stage_fd<S, Q><<<tg, tb, 0, ss>>>(a, tm); });
         if (rc) return rc;
+        if (fork && st == 0) {
+          if (int rc2 = hip_check(s, hipEventRecord(s->ev_join, s->aux), "join")) return rc2;
+          const LBArgs<S> b = lb_args(s, fout, nullptr, psin, static_cast<S*>(s->u_end), 1, n);
+          if (int rc2 = launch_lb(s, b, false, "k_uend")) return rc2;
+          if (int rc2 = hip_check(s, hipStreamWaitEvent(s->stream, s->ev_join, 0), "join"))
+            return rc2;
+        }
         phi = a.out;
       }
       s->pcur = 1 - s->pcur;
@@ -1292,9 +1338,11 @@ int lbl_set_schedule(lbl_sim* sim, const lbl_schedule* sch) {
   for (int k = 5; k <= 8; ++k)
     if (w == (1 << k)) lw = k;
   if (lw < 0) return fail(sim, LBL_E_INVAL, "lb_width must be 32, 64, 128 or 256");
-  if (sch->zc < 0 || sch->reserved != 0) return fail(sim, LBL_E_INVAL, "zc < 0 or reserved != 0");
+  if (sch->zc < 0 || sch->overlap < 0 || sch->overlap > 1)
+    return fail(sim, LBL_E_INVAL, "zc < 0 or overlap not 0/1");
   sim->lb_lw = lw;
-  sim->lb_swizzle = sch->xcd_swizzle != 0;
+  sim->lb_swizzle = sch->xcd_swizzle & 3;
+  sim->overlap = sch->overlap;
   if (sch->zc > 0) sim->zc = std::min(sch->zc, sim->p.nz);
   return LBL_OK;
 }
@@ -1304,7 +1352,7 @@ int lbl_get_schedule(const lbl_sim* sim, lbl_schedule* out) {
   out->lb_width = 1 << sim->lb_lw;
   out->xcd_swizzle = sim->lb_swizzle;
   out->zc = sim->zc;
-  out->reserved = 0;
+  out->overlap = sim->overlap;
   return LBL_OK;
 }
 
@@ -1335,6 +1383,7 @@ int lbl_destroy(lbl_sim* sim) {
   if (!sim) return LBL_OK;
   if (sim->stream || !sim->owned.empty()) (void)hipSetDevice(sim->device);
   (void)hipStreamSynchronize(sim->stream);
+  destroy_aux(sim);
   destroy_events(sim);
   release_all(sim);
   delete sim;
@@ -1499,7 +1548,7 @@ int lbl_pool_stats(const lbl_pool* pl, lbl_pool_info* out) {
 }
 
 int lbl_pool_set_schedule(lbl_pool* pl, const lbl_schedule* sch) {
-  if (!pl || !sch || sch->zc < 0 || sch->reserved != 0) return LBL_E_INVAL;
+  if (!pl || !sch || sch->zc < 0 || sch->overlap != 0) return LBL_E_INVAL;
   int lw = -1;
   for (int k = 5; k <= 8; ++k)
     if (sch->lb_width == (1 << k)) lw = k;
@@ -1519,7 +1568,7 @@ int lbl_pool_get_schedule(const lbl_pool* pl, lbl_schedule* out) {
   out->lb_width = 1 << pl->lb_lw;
   out->xcd_swizzle = pl->xcd_swizzle;
   out->zc = pl->zc_override;
-  out->reserved = 0;
+  out->overlap = 0;
   return LBL_OK;
 }
 

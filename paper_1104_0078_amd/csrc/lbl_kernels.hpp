@@ -30,6 +30,8 @@ struct Coef {
 // wavefront, contiguous in memory) by 4 rows.
 constexpr int kBX = 64, kBY = 4;
 constexpr int kSiteBlock = 256;  // threads per block of the per-site kernels
+// Tile of the z-marching stencil kernels.
+constexpr int kTX = 32, kTY = 8;
 
 // Schedule of the single-simulation per-site kernels: 256-thread blocks that
 // cover 2^lw sites along x by 256 / 2^lw rows of one z-plane, enumerated with
@@ -72,8 +74,41 @@ __device__ __forceinline__ bool site_of(const SiteMap& m, const Geom& g, int& x,
   y = by * (kSiteBlock >> m.lw) + (threadIdx.x >> m.lw);
   return x < g.nx && y < g.ny;
 }
-// Tile of the z-marching stencil kernels.
-constexpr int kTX = 32, kTY = 8;
+
+// Schedule of the single-simulation z-marching tile kernels: a 1-D grid over
+// ntx x nty x nzc tiles (x fastest); with `per` > 0 block b takes virtual tile
+// (b % 8) per + b / 8, so each XCD marches a contiguous range of tiles and the
+// halo rows that neighbouring tiles re-read stay in its L2.
+struct TileMap {
+  int ntx, nty;  // tiles along x and y
+  int nt;        // tiles in total
+  int per;       // tiles per XCD when swizzled, else 0
+};
+
+__host__ inline TileMap make_tile_map(int nx, int ny, int nzc, bool swizzle) {
+  TileMap m;
+  m.ntx = (nx + kTX - 1) / kTX;
+  m.nty = (ny + kTY - 1) / kTY;
+  m.nt = m.ntx * m.nty * nzc;
+  m.per = swizzle ? (m.nt + 7) / 8 : 0;
+  return m;
+}
+
+__host__ inline int tile_map_blocks(const TileMap& m) { return m.per ? 8 * m.per : m.nt; }
+
+// Tile of this block; false for padding blocks.
+__device__ __forceinline__ bool tile_of(const TileMap& m, int& bx, int& by, int& bz) {
+  int b = blockIdx.x;
+  if (m.per) {
+    b = (b & 7) * m.per + (b >> 3);
+    if (b >= m.nt) return false;
+  }
+  bx = b % m.ntx;
+  const int r = b / m.ntx;
+  by = r % m.nty;
+  bz = r / m.nty;
+  return true;
+}
 
 // Periodic neighbourhood of one site: wrapped coordinates and row offsets.
 struct Nbr {
@@ -518,8 +553,9 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
 }
 
 template <typename S, int Q>
-__global__ __launch_bounds__(kTX* kTY) void k_prep_fv(PrepArgs<S> a) {
-  prep_fv_body<S, Q>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+__global__ __launch_bounds__(kTX* kTY) void k_prep_fv(PrepArgs<S> a, TileMap m) {
+  int bx, by, bz;
+  if (tile_of(m, bx, by, bz)) prep_fv_body<S, Q>(a, bx, by, bz);
 }
 
 // FD noise (Sec. V.A, reading): one flux zeta_l per undirected Laplacian link,
@@ -595,8 +631,9 @@ __device__ __forceinline__ void prep_fd_body(const PrepArgs<S>& a, int bx, int b
 }
 
 template <typename S, int Q>
-__global__ __launch_bounds__(kTX* kTY) void k_prep_fd(PrepArgs<S> a) {
-  prep_fd_body<S, Q>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+__global__ __launch_bounds__(kTX* kTY) void k_prep_fd(PrepArgs<S> a, TileMap m) {
+  int bx, by, bz;
+  if (tile_of(m, bx, by, bz)) prep_fd_body<S, Q>(a, bx, by, bz);
 }
 
 // ---------------------------------------------------------------------------
@@ -841,8 +878,9 @@ __device__ __forceinline__ void stage_fv_body(const StageArgs<S>& a, int bx, int
 }
 
 template <typename S, int Q>
-__global__ __launch_bounds__(kTX* kTY) void k_stage_fv(StageArgs<S> a) {
-  stage_fv_body<S, Q>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+__global__ __launch_bounds__(kTX* kTY) void k_stage_fv(StageArgs<S> a, TileMap m) {
+  int bx, by, bz;
+  if (tile_of(m, bx, by, bz)) stage_fv_body<S, Q>(a, bx, by, bz);
 }
 
 // FD stage (Sec. V.A): G = -D.(u phi) + M L_SO mu(phi) + N with the central
@@ -920,8 +958,9 @@ __device__ __forceinline__ void stage_fd_body(const StageArgs<S>& a, int bx, int
 }
 
 template <typename S, int Q>
-__global__ __launch_bounds__(kTX* kTY) void k_stage_fd(StageArgs<S> a) {
-  stage_fd_body<S, Q>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+__global__ __launch_bounds__(kTX* kTY) void k_stage_fd(StageArgs<S> a, TileMap m) {
+  int bx, by, bz;
+  if (tile_of(m, bx, by, bz)) stage_fd_body<S, Q>(a, bx, by, bz);
 }
 
 // ---------------------------------------------------------------------------

@@ -59,7 +59,7 @@ class lbl_kernel_time(ctypes.Structure):
 
 class lbl_schedule(ctypes.Structure):
     _fields_ = [("lb_width", ctypes.c_int32), ("xcd_swizzle", ctypes.c_int32),
-                ("zc", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("zc", ctypes.c_int32), ("overlap", ctypes.c_int32)]
 
 
 class lbl_pool_info(ctypes.Structure):
@@ -340,13 +340,14 @@ class Sim:
             raise LblError(rc, lbl_last_error(self.handle))
         return rows
 
-    def set_schedule(self, lb_width=None, xcd_swizzle=None, zc=0):
+    def set_schedule(self, lb_width=None, xcd_swizzle=None, zc=0, overlap=None):
         """Launch schedule (speed only): LB block width along x (32..256),
-        XCD-contiguous block order, planes per SMOL tile (0 keeps)."""
+        XCD-contiguous block order (bit 0: LB kernels, bit 1: SMOL tiles),
+        planes per SMOL tile (0 keeps), first stage on a second stream."""
         cur = self.schedule()
         sch = lbl_schedule(int(lb_width if lb_width is not None else cur["lb_width"]),
-                           int(bool(xcd_swizzle if xcd_swizzle is not None
-                                    else cur["xcd_swizzle"])), int(zc), 0)
+                           int(xcd_swizzle if xcd_swizzle is not None else cur["xcd_swizzle"]),
+                           int(zc), int(overlap if overlap is not None else cur["overlap"]))
         rc = library().lbl_set_schedule(self.handle, ctypes.byref(sch))
         if rc != LBL_OK:
             raise LblError(rc, lbl_last_error(self.handle))
@@ -356,7 +357,8 @@ class Sim:
         rc = library().lbl_get_schedule(self.handle, ctypes.byref(sch))
         if rc != LBL_OK:
             raise LblError(rc, lbl_last_error(self.handle))
-        return {"lb_width": sch.lb_width, "xcd_swizzle": sch.xcd_swizzle, "zc": sch.zc}
+        return {"lb_width": sch.lb_width, "xcd_swizzle": sch.xcd_swizzle, "zc": sch.zc,
+                "overlap": sch.overlap}
 
     def close(self):
         if getattr(self, "handle", None):

@@ -37,7 +37,7 @@ def _sample_sites(N, rng):
 
 @pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
 @pytest.mark.parametrize("schedule", [None, dict(lb_width=128, xcd_swizzle=0, zc=64),
-                                      dict(lb_width=256, xcd_swizzle=1, zc=16)])
+                                      dict(lb_width=256, xcd_swizzle=3, zc=16)])
 def test_full_size_sampled_parity(oracle_state, precision, schedule):
     import torch
     from paper_1104_0078_amd import lbl

@@ -123,14 +123,16 @@ def test_conservation_on_gpu(lattice, precision):
 @pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q19])
 def test_schedule_does_not_change_results(lattice):
     """Every launch schedule (LB block width, XCD-contiguous block order,
-    planes per SMOL tile) gives bitwise the same fields."""
+    planes per SMOL tile, first stage on a second stream) gives bitwise the
+    same fields."""
     from paper_1104_0078_amd import lbl
     c = H.config(lattice=lattice, smol=H.FV, shape=SHAPES[lattice], init=0)
     ini = lbl.make_init(kind=0, psi_std=1e-3)
     out = []
-    for w, swz, zc in ((64, 0, 0), (256, 0, 0), (128, 1, 0), (32, 1, 3), (256, 1, 5)):
+    for w, swz, zc, ov in ((64, 0, 0, 0), (256, 0, 0, 1), (128, 1, 0, 0), (32, 3, 3, 1),
+                           (256, 2, 5, 0)):
         with lbl.Sim(H.lbl_params(c), ini) as sim:
-            sim.set_schedule(lb_width=w, xcd_swizzle=swz, zc=zc)
+            sim.set_schedule(lb_width=w, xcd_swizzle=swz, zc=zc, overlap=ov)
             assert sim.schedule()["lb_width"] == w
             sim.step(7)
             out.append((sim.observe(lbl.LBL_OBS_POP), sim.observe(lbl.LBL_OBS_PSI)))
