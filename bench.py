@@ -115,10 +115,10 @@ def traffic_for(kernel, workload):
     return None
 
 
-def cpu_baseline(w, workload_name):
-    """The FP64 oracle, as it stands, on a bounded sample: one step of the same
-    lattice (or a few on small lattices), timed on the host cores."""
-    import numpy as np  # noqa: F401
+def cpu_baseline(w, workload_name, min_seconds=10.0, max_steps=200):
+    """The FP64 oracle, as it stands, on a bounded sample of the same
+    workload: steps of the same lattice until at least `min_seconds` of host
+    time have passed (at most `max_steps`), timed on the host cores."""
     import oracle as O
 
     p = O.make_params(lattice=w["lattice"], smol=w["smol"], shape=w["shape"], a=w["a"],
@@ -126,10 +126,12 @@ def cpu_baseline(w, workload_name):
                       seed=1234)
     f, psi = O.init(p, w["init"], w["psi_std"])
     N = O.nsites(p)
-    nsteps = max(1, min(200, int(2e7 // N)))
+    nsteps, dt = 0, 0.0
     t0 = time.perf_counter()
-    O.run(p, f, psi, 0, nsteps)
-    dt = time.perf_counter() - t0
+    while nsteps < max_steps and dt < min_seconds:
+        O.run(p, f, psi, nsteps, 1)
+        nsteps += 1
+        dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": N * nsteps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": "%d step(s) of %s (%d sites), FP64 oracle, %.1f s" % (
