@@ -139,3 +139,27 @@ def test_schedule_does_not_change_results(lattice):
     for f, p in out[1:]:
         np.testing.assert_array_equal(f, out[0][0])
         np.testing.assert_array_equal(p, out[0][1])
+
+
+@pytest.mark.parametrize("lattice,shape", [(H.D2Q9, (4, 4, 1)), (H.D2Q9, (5, 33, 1)),
+                                           (H.D3Q19, (4, 4, 4)), (H.D3Q19, (5, 7, 4)),
+                                           (H.D3Q19, (33, 9, 5))])
+@pytest.mark.parametrize("smol", [H.FD, H.FV])
+def test_smallest_and_odd_lattices(lattice, shape, smol):
+    """Sides at the minimum the ABI accepts (4, where every stencil halo
+    wraps onto the lattice itself several times) and odd sides just past one
+    tile, two-phase so that the nonlinear terms are exercised."""
+    c = H.config(lattice=lattice, smol=smol, shape=shape, init=0, a=-0.04, b=0.04)
+    _check(c, 12)
+
+
+def test_zero_steps_and_observe_before_stepping():
+    from paper_1104_0078_amd import lbl
+    c = H.config(lattice=H.D2Q9, smol=H.FV, shape=(20, 12, 1), init=0)
+    f_ref, psi_ref = H.oracle_run(c, 0)
+    with lbl.Sim(H.lbl_params(c), lbl.make_init(kind=0, psi_std=1e-3)) as sim:
+        sim.step(0)
+        assert sim.observe(lbl.LBL_OBS_STEP) == 0
+        f = sim.observe(lbl.LBL_OBS_POP)
+        psi = sim.observe(lbl.LBL_OBS_PSI)
+    assert H.rel_err(f, f_ref) <= 1e-15 and H.rel_err(psi, psi_ref) <= 1e-15
