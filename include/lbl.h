@@ -227,6 +227,19 @@ typedef struct lbl_schedule {
 int lbl_set_schedule(lbl_sim *sim, const lbl_schedule *schedule);
 int lbl_get_schedule(const lbl_sim *sim, lbl_schedule *out);
 
+/* Diagnostics: the normals the sweep draws (App. A noise of Secs. III-V drawn
+ * from Philox4x32-10 with the Box-Muller map).  dst (host, n_sites * n_slots
+ * FP64, [site][slot]) receives the normal of slot s (Philox block s/4, lane
+ * s%4) of the counter (site0 + i, step, block, tag) under key seed, computed
+ * on `device` with the transform of the given storage (LBL_FP64 or
+ * LBL_FP32DEV).  Synchronous; allocates and frees its own device memory.
+ * For tests of the generator against independent implementations.
+ * Errors: LBL_E_INVAL (NULL dst, n_sites outside 1..2^24, n_slots outside
+ * 1..64, unknown precision), LBL_E_NOMEM, LBL_E_DEVICE. */
+int lbl_diag_normals(int32_t device, int32_t precision, uint64_t seed, uint32_t step,
+                     uint32_t tag, uint32_t site0, int64_t n_sites, int32_t n_slots,
+                     double *dst);
+
 /* ------------------------------------------------------------------------
  * Pool: independent simulations batched on one device (the library's own
  * serving and ensemble layer, not the paper's).  Requests are admitted in

@@ -1331,6 +1331,28 @@ int lbl_observe(lbl_sim* sim, int what, void* dst, size_t bytes, int dst_is_devi
   }
 }
 
+int lbl_diag_normals(int32_t device, int32_t precision, uint64_t seed, uint32_t step,
+                     uint32_t tag, uint32_t site0, int64_t n_sites, int32_t n_slots,
+                     double* dst) {
+  if (!dst || n_sites <= 0 || n_sites > (1 << 24) || n_slots <= 0 || n_slots > 64 ||
+      (precision != LBL_FP64 && precision != LBL_FP32DEV))
+    return LBL_E_INVAL;
+  if (hipSetDevice(device) != hipSuccess) return LBL_E_DEVICE;
+  const size_t bytes = sizeof(double) * static_cast<size_t>(n_sites) * n_slots;
+  double* d = nullptr;
+  if (hipMalloc(&d, bytes) != hipSuccess) return LBL_E_NOMEM;
+  const int n = static_cast<int>(n_sites);
+  const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+  if (precision == LBL_FP64)
+    k_diag_normals<double><<<(n + 255) / 256, 256>>>(site0, n, n_slots, step, tag, k0, k1, d);
+  else
+    k_diag_normals<float><<<(n + 255) / 256, 256>>>(site0, n, n_slots, step, tag, k0, k1, d);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpy(dst, d, bytes, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  return e == hipSuccess ? LBL_OK : LBL_E_DEVICE;
+}
+
 int lbl_set_schedule(lbl_sim* sim, const lbl_schedule* sch) {
   if (!sim || !sch) return LBL_E_INVAL;
   const int w = sch->lb_width;

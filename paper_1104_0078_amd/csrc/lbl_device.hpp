@@ -208,11 +208,29 @@ enum : uint32_t { kTagLB = 0, kTagSMOL = 1, kTagInit = 2 };
 template <typename C>
 struct Normal4;
 
+// Square root of a in [1e-10, 1e2] (the radii of Box-Muller, -2 ln u with
+// u in [2^-33, 1 - 2^-33]): the hardware reciprocal square root refined by
+// two coupled Newton (Goldschmidt) iterations for g ~ sqrt(a), h ~ 1/(2 sqrt a),
+// then one residual correction g + (a - g^2) h.  No scaling or special cases
+// are needed on this range.
+__device__ __forceinline__ double sqrt_radius(double a) {
+  const double y = __builtin_amdgcn_rsq(a);
+  double g = a * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, a);
+  return fma(d, h, g);
+}
+
 template <>
 struct Normal4<double> {
   // Box-Muller pair from two 32-bit outputs: sqrt(-2 ln u_a) (cos, sin)(2 pi u_b).
   __device__ __forceinline__ static void pair(uint32_t ka, uint32_t kb, double& za, double& zb) {
-    const double r = sqrt(-2.0 * bm::log_unit(bm::unit(ka)));
+    const double r = sqrt_radius(-2.0 * bm::log_unit(bm::unit(ka)));
     double s, c;
     bm::sincos_turn(kb, &s, &c);
     za = r * c;

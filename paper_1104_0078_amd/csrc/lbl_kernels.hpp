@@ -966,6 +966,22 @@ __global__ __launch_bounds__(kTX* kTY) void k_stage_fd(StageArgs<S> a, TileMap m
 // ---------------------------------------------------------------------------
 // Initial state and observables (one thread per site, 1-D grid).
 // ---------------------------------------------------------------------------
+// Diagnostics: normals of Philox blocks 0 .. nblk-1 at sites site0 + i,
+// written as FP64 [site][slot] (slots beyond nslots dropped).
+template <typename S>
+__global__ __launch_bounds__(256) void k_diag_normals(uint32_t site0, int n, int nslots, uint32_t step,
+                                                       uint32_t tag, uint32_t k0, uint32_t k1,
+                                                       double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int b = 0; 4 * b < nslots; ++b) {
+    S z[4];
+    Normal4<S>::gen(site0 + static_cast<uint32_t>(i), step, static_cast<uint32_t>(b), tag, k0, k1, z);
+    for (int l = 0; l < 4 && 4 * b + l < nslots; ++l)
+      out[static_cast<size_t>(i) * nslots + 4 * b + l] = static_cast<double>(z[l]);
+  }
+}
+
 template <typename S, bool DEV, int Q>
 __global__ __launch_bounds__(256) void k_init_uniform(Geom g, double rho0, double ux, double uy,
                                                       double uz, S* __restrict__ f) {

@@ -95,16 +95,14 @@ __host__ __device__ inline void sincos_turn(uint32_t k, double* s, double* c) {
   const double phi = (static_cast<double>(r) + 0.5) * kTurn;
   double sp, cp;
   sincos_octant(phi, &sp, &cp);
-  if (refl) {
-    const double t = sp;
-    sp = cp;
-    cp = t;
-  }
-  // Rotate by quad * pi/2.
-  const double so = (quad & 1u) ? cp : sp;
-  const double co = (quad & 1u) ? sp : cp;
-  *s = (quad == 2u || quad == 3u) ? -so : so;
-  *c = (quad == 1u || quad == 2u) ? -co : co;
+  // The reflection swaps sine and cosine, and so does a rotation by an odd
+  // multiple of pi/2: one swap for both.  Then the signs of the rotation by
+  // quad * pi/2: sine negative in quadrants 2, 3, cosine in 1, 2.
+  const bool swap = refl != ((quad & 1u) != 0);
+  const double so = swap ? cp : sp;
+  const double co = swap ? sp : cp;
+  *s = (quad & 2u) ? -so : so;
+  *c = ((quad + 1u) & 2u) ? -co : co;
 }
 
 }  // namespace bm

@@ -88,9 +88,15 @@ _lib = None
 
 
 def library():
-    """Load liblbl.so; raises if it has not been built."""
+    """Load liblbl.so; raises if it has not been built.
+
+    torch is imported first: it brings its own HIP runtime, and the library's
+    HIP dependency must resolve to that same, already loaded runtime, so that
+    device memory and streams from torch and the library's kernels live in one
+    runtime instance (loading the library first would start a second one)."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (see above: load torch's HIP runtime first)
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 "liblbl.so is not built (run __graft_entry__.build()); the sweep has no "
@@ -118,6 +124,10 @@ def library():
                                       ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.lbl_timing_read.restype = ctypes.c_int
         vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.lbl_diag_normals.argtypes = [i32, i32, ctypes.c_uint64, ctypes.c_uint32,
+                                       ctypes.c_uint32, ctypes.c_uint32, i64, i32,
+                                       P(ctypes.c_double)]
+        L.lbl_diag_normals.restype = ctypes.c_int
         L.lbl_set_schedule.argtypes = [vp, P(lbl_schedule)]
         L.lbl_set_schedule.restype = ctypes.c_int
         L.lbl_get_schedule.argtypes = [vp, P(lbl_schedule)]
@@ -218,6 +228,18 @@ def make_params(lattice=LBL_D2Q9, smol=LBL_SMOL_FD, precision=LBL_FP64, coupling
     p.sample_every = sample_every
     p.reserved = 0
     return p
+
+
+def diag_normals(precision, seed, step, tag, site0, n_sites, n_slots, device=0):
+    """Normals the sweep draws for sites site0 .. site0+n_sites-1, slots
+    0 .. n_slots-1 (array [site][slot], FP64)."""
+    out = np.zeros((int(n_sites), int(n_slots)))
+    rc = library().lbl_diag_normals(int(device), int(precision), int(seed), int(step), int(tag),
+                                    int(site0), int(n_sites), int(n_slots),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != LBL_OK:
+        raise LblError(rc, "lbl_diag_normals")
+    return out
 
 
 def make_init(kind=LBL_INIT_REST, psi_std=1e-3, boost=(0, 0, 0), f0=None, psi0=None):
