@@ -928,6 +928,7 @@ struct Group {
   DevBuf reps, states, wlb, wtile;
   int nlb = 0, ntile = 0;
   int lb_lw = 6;  // tile width the LB work table was built with
+  int lane = 0;   // stream lane this tick of the group runs on
   bool dirty = true;
   hipGraphExec_t exec = nullptr;
   int64_t exec_steps = 0;
@@ -939,10 +940,13 @@ GroupKey key_of(const lbl_params& p) {
 
 }  // namespace
 
+constexpr int kPoolLanes = 4;  // streams on which groups of different kinds run concurrently
+
 struct lbl_pool {
   uint64_t budget = 0, used = 0;
   lbl_env env{};
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;           // admission, tables, retirement
+  hipStream_t lane[kPoolLanes] = {};      // batched ticks, one lane per group
   int device = 0;
   std::deque<int64_t> queue;
   std::map<int64_t, PoolReq> reqs;
@@ -1133,17 +1137,18 @@ int run_group(lbl_pool* pl, Group& g, int64_t max_steps) {
   }
   steps = std::min(steps, max_steps);
   if (steps <= 0) return LBL_OK;
+  const hipStream_t ls = pl->lane[g.lane];
   if (!g.exec || g.exec_steps != steps) {
     drop_graph(g);
     hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal);
+    hipError_t e = hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess)
       return pool_fail(pl, LBL_E_DEVICE, std::string("begin capture: ") + hipGetErrorString(e));
-    const int rc = t.enqueue(pl->stream, g.reps.ptr, static_cast<RepState*>(g.states.ptr), n,
+    const int rc = t.enqueue(ls, g.reps.ptr, static_cast<RepState*>(g.states.ptr), n,
                              static_cast<const Work*>(g.wlb.ptr), g.nlb, g.lb_lw,
                              static_cast<const Work*>(g.wtile.ptr), g.ntile, g.key.rk,
                              g.key.ghost != 0, steps);
-    e = hipStreamEndCapture(pl->stream, &graph);
+    e = hipStreamEndCapture(ls, &graph);
     if (rc || e != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
       return pool_fail(pl, LBL_E_DEVICE, "graph capture of the batched step failed");
@@ -1156,7 +1161,7 @@ int run_group(lbl_pool* pl, Group& g, int64_t max_steps) {
     }
     g.exec_steps = steps;
   }
-  const hipError_t e = hipGraphLaunch(g.exec, pl->stream);
+  const hipError_t e = hipGraphLaunch(g.exec, ls);
   if (e != hipSuccess)
     return pool_fail(pl, LBL_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
   return LBL_OK;
@@ -1197,8 +1202,20 @@ int pool_run_impl(lbl_pool* pl, int64_t max_steps, int64_t* pending) {
   if (int rc = hip_check(nullptr, hipSetDevice(pl->device), "hipSetDevice"))
     return pool_fail(pl, rc, g_create_error);
   admit(pl);
-  for (auto& kv : pl->groups)
+  // Admission and table uploads ran on the pool stream; the lanes start after.
+  if (int rc = hip_check(nullptr, hipStreamSynchronize(pl->stream), "pool sync"))
+    return pool_fail(pl, rc, g_create_error);
+  int lane = 0;
+  for (auto& kv : pl->groups) {
+    if (kv.second.members.empty()) continue;
+    kv.second.lane = lane++ % kPoolLanes;
     if (int rc = run_group(pl, kv.second, max_steps)) return rc;
+  }
+  // Groups of different kinds ran concurrently on their lanes; wait for all
+  // before reading the states back and retiring on the pool stream.
+  for (hipStream_t ls : pl->lane)
+    if (hipStreamSynchronize(ls) != hipSuccess)
+      return pool_fail(pl, LBL_E_DEVICE, "pool lane synchronisation failed");
   for (auto& kv : pl->groups)
     if (int rc = settle_group(pl, kv.second)) return rc;
   pl->ticks += 1;
@@ -1441,6 +1458,15 @@ int lbl_pool_create(uint64_t budget_bytes, const lbl_env* env, lbl_pool** out) {
   }
   pl->stream = st;
   pl->env.stream = st;
+  for (hipStream_t& ls : pl->lane) {
+    if (hipStreamCreateWithFlags(&ls, hipStreamNonBlocking) != hipSuccess) {
+      for (hipStream_t x : pl->lane)
+        if (x) (void)hipStreamDestroy(x);
+      (void)hipStreamDestroy(st);
+      delete pl;
+      return fail(nullptr, LBL_E_DEVICE, "pool stream creation failed");
+    }
+  }
   *out = pl;
   return LBL_OK;
 }
@@ -1597,6 +1623,7 @@ int lbl_pool_get_schedule(const lbl_pool* pl, lbl_schedule* out) {
 int lbl_pool_destroy(lbl_pool* pl) {
   if (!pl) return LBL_OK;
   (void)hipSetDevice(pl->device);
+  for (hipStream_t ls : pl->lane) (void)hipStreamSynchronize(ls);
   (void)hipStreamSynchronize(pl->stream);
   for (auto& kv : pl->reqs)
     if (kv.second.sim) finish_request(pl, kv.second, LBL_REQ_FAILED);
@@ -1607,6 +1634,7 @@ int lbl_pool_destroy(lbl_pool* pl) {
     pool_free(pl, kv.second.wlb.ptr);
     pool_free(pl, kv.second.wtile.ptr);
   }
+  for (hipStream_t ls : pl->lane) (void)hipStreamDestroy(ls);
   (void)hipStreamDestroy(pl->stream);
   delete pl;
   return LBL_OK;

@@ -80,7 +80,7 @@ __device__ __forceinline__ void lb_tile_site(const Work& w, int lw, int& x, int&
 }
 
 template <typename S, bool DEV, int Q, int SMOL, bool GHOST>
-__global__ __launch_bounds__(kSiteBlock, 5) void kb_lb(const Replica<S>* __restrict__ reps,
+__global__ __launch_bounds__(kSiteBlock) void kb_lb(const Replica<S>* __restrict__ reps,
                                                       const RepState* __restrict__ st,
                                                       const Work* __restrict__ work, int lw) {
   const Work w = work[blockIdx.x];
