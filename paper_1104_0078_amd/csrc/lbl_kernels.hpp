@@ -730,7 +730,8 @@ __device__ __forceinline__ void combine_in(const StageArgs<S>& a, int s, S G, co
 // three planes) and mu (halo 2, three planes) and one plane of J (halo 1):
 // each J plane is folded into register partial sums of G for the planes
 // below, at and above it, so J never needs a ring.  The next phi plane and the
-// site values of the current plane are fetched one step ahead.
+// site values of the current plane are fetched one step ahead, the velocity
+// at the J points once mu is done (fewer registers live during mu).
 template <typename S, int Q>
 __device__ __forceinline__ void stage_fv_body(const StageArgs<S>& a, int bx, int by, int bz) {
   using L = Lat<Q>;
@@ -857,12 +858,12 @@ __device__ __forceinline__ void stage_fv_body(const StageArgs<S>& a, int bx, int
       store_phi(t + 3);
       if (t + 1 < z1) fetch_phi(t + 4);
       const bool do_mu = t + 2 >= z0 - 2, do_J = t + 1 >= z0 - 1, do_G = t >= z0 && live;
-      if (do_J) fetch_u(t + 1);
       const int s = x + g.nx * (y + g.ny * t);
       SiteIn<S> sv{};
       if (do_G) sv = fetch_site(a, s);
       __syncthreads();
       if (do_mu) comp_mu(t + 2);
+      if (do_J) fetch_u(t + 1);
       __syncthreads();
       if (do_J) comp_J(t + 1);
       __syncthreads();
