@@ -148,7 +148,10 @@ int lbl_create(const lbl_params *params, const lbl_init *init, const lbl_env *en
 
 /* Enqueue nsteps coupled steps (Sec. VI: FLBE and SMOL marched alternately)
  * on the simulation's stream and return without waiting.  Step n draws the
- * noise of counter step n.  Errors of earlier asynchronous work (including
+ * noise of counter step n.  Within a step the SMOL noise is frozen over the
+ * Runge-Kutta stages (Sec. V) and each stage advects with the velocity of
+ * its own time level: u^n at t_n, the velocity of the streamed populations
+ * (jbar^{n+1} + F^n/2)/rho^{n+1} at t_{n+1}, their mean at RK4 midpoints.  Errors of earlier asynchronous work (including
  * LBL_E_NONFINITE from the sampled totals) are reported by the next call that
  * synchronises (lbl_observe).  nsteps < 0 gives LBL_E_INVAL. */
 int lbl_step(lbl_sim *sim, int64_t nsteps);
@@ -227,8 +230,8 @@ typedef struct lbl_schedule {
 int lbl_set_schedule(lbl_sim *sim, const lbl_schedule *schedule);
 int lbl_get_schedule(const lbl_sim *sim, lbl_schedule *out);
 
-/* Diagnostics: the normals the sweep draws (App. A noise of Secs. III-V drawn
- * from Philox4x32-10 with the Box-Muller map).  dst (host, n_sites * n_slots
+/* Diagnostics: the normals the sweep draws (the Gaussian noise of Secs. IV,
+ * V and App. B, drawn from Philox4x32-10 with the Box-Muller map).  dst (host, n_sites * n_slots
  * FP64, [site][slot]) receives the normal of slot s (Philox block s/4, lane
  * s%4) of the counter (site0 + i, step, block, tag) under key seed, computed
  * on `device` with the transform of the given storage (LBL_FP64 or
