@@ -175,8 +175,11 @@ enum lbl_observable {
                            SMOL_ONLY, whose flow is imposed) */
   LBL_OBS_STEP = 7,     /* 1 int64: steps taken */
   LBL_OBS_NSAMPLES = 8, /* 1 int64: samples accumulated into SK/UK */
-  LBL_OBS_PSIK_AXES = 9 /* 2*d*Lmax FP64: the current sum_x psi e^{-i k x_alpha} at
+  LBL_OBS_PSIK_AXES = 9, /* 2*d*Lmax FP64: the current sum_x psi e^{-i k x_alpha} at
                            k = 2 pi m / L_alpha, element [(alpha*Lmax + m)*2 + {0: re, 1: im}] */
+  LBL_OBS_SK2_AXES = 10, /* d*Lmax FP64: mean over samples of the square of each
+                           SK_AXES sample (its variance is SK2 - SK^2) */
+  LBL_OBS_UK2_AXES = 11  /* d*d*Lmax FP64: the same for UK_AXES */
 };
 
 /* Copy an observable of the current state into dst (host memory, or device

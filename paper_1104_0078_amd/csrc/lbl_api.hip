@@ -56,8 +56,8 @@ struct lbl_sim {
   bool tot_pending = false;
   double* planes = nullptr;  // [kMaxFields][3][Lmax] plane sums
   double* col = nullptr;     // [kMaxFields][nz][nx] column sums
-  double* sk = nullptr;      // [d][Lmax] accumulated S_a(k)
-  double* uk = nullptr;      // [d][d][Lmax] accumulated U_ab(k)
+  double* sk = nullptr;      // [2][d][Lmax] sums of |psi_k|^2/N and of its square
+  double* uk = nullptr;      // [2][d][d][Lmax] the same for each velocity component
   int64_t step = 0;
   int64_t nsamples = 0;
   uint32_t k0 = 0, k1 = 0;
@@ -686,10 +686,15 @@ struct Impl {
       case LBL_OBS_PSIK_AXES:
         return sample(s, false, dst);
       case LBL_OBS_SK_AXES:
-      case LBL_OBS_UK_AXES: {
+      case LBL_OBS_UK_AXES:
+      case LBL_OBS_SK2_AXES:
+      case LBL_OBS_UK2_AXES: {
+        // Accumulators hold the sums of |X|^2/N, then of its square.
         const double inv = 1.0 / static_cast<double>(s->nsamples > 0 ? s->nsamples : 1);
-        const double* src = what == LBL_OBS_SK_AXES ? s->sk : s->uk;
-        const int n = static_cast<int>((what == LBL_OBS_SK_AXES ? 1 : s->d) * s->d * s->Lmax);
+        const bool psi_k = what == LBL_OBS_SK_AXES || what == LBL_OBS_SK2_AXES;
+        const bool second = what == LBL_OBS_SK2_AXES || what == LBL_OBS_UK2_AXES;
+        const int n = static_cast<int>((psi_k ? 1 : s->d) * s->d * s->Lmax);
+        const double* src = (psi_k ? s->sk : s->uk) + (second ? n : 0);
         k_scale<<<grid_for(n), kBlock, 0, s->stream>>>(n, inv, src, dst);
         return launched(s, "k_scale");
       }
@@ -746,7 +751,7 @@ std::vector<size_t> alloc_plan(const lbl_params& p) {
           sz * N * d, sz * N, sizeof(double) * 10 * nparts, sizeof(double) * 16,
           sizeof(double) * kMaxFields * 3 * Lmax,
           sizeof(double) * kMaxFields * static_cast<size_t>(p.nz) * p.nx,
-          sizeof(double) * d * Lmax, sizeof(double) * d * d * Lmax, sz * N * d};
+          sizeof(double) * 2 * d * Lmax, sizeof(double) * 2 * d * d * Lmax, sz * N * d};
 }
 
 size_t obs_bytes(const lbl_sim* s, int what) {
@@ -762,8 +767,10 @@ size_t obs_bytes(const lbl_sim* s, int what) {
     case LBL_OBS_TOTALS:
       return 8 * 10;
     case LBL_OBS_SK_AXES:
+    case LBL_OBS_SK2_AXES:
       return 8 * static_cast<size_t>(s->d) * s->Lmax;
     case LBL_OBS_UK_AXES:
+    case LBL_OBS_UK2_AXES:
       return 8 * static_cast<size_t>(s->d) * s->d * s->Lmax;
     case LBL_OBS_PSIK_AXES:
       return 8 * 2 * static_cast<size_t>(s->d) * s->Lmax;
@@ -866,10 +873,11 @@ int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* e
   }
   rc = hip_check(s, hipMemsetAsync(s->noise, 0, sz * N, s->stream), "clear noise");
   if (!rc)
-    rc = hip_check(s, hipMemsetAsync(s->sk, 0, sizeof(double) * s->d * s->Lmax, s->stream),
+    rc = hip_check(s, hipMemsetAsync(s->sk, 0, sizeof(double) * 2 * s->d * s->Lmax, s->stream),
                    "clear sk");
   if (!rc)
-    rc = hip_check(s, hipMemsetAsync(s->uk, 0, sizeof(double) * s->d * s->d * s->Lmax, s->stream),
+    rc = hip_check(s, hipMemsetAsync(s->uk, 0, sizeof(double) * 2 * s->d * s->d * s->Lmax,
+                                     s->stream),
                    "clear uk");
   if (!rc) rc = hip_check(s, hipMemsetAsync(s->u, 0, sz * N * s->d, s->stream), "clear u");
   if (!rc) rc = select(s->p).init(s, init);

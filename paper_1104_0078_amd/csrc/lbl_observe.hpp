@@ -3,7 +3,8 @@
 // velocity spectrum at wave vectors on the lattice axes,
 //   S_a(k)       = |sum_x psi(x) e^{-i k x_a}|^2 / N,
 //   U_{a,b}(k)   = |sum_x u_b(x) e^{-i k x_a}|^2 / N,   k = 2 pi m / L_a,
-// accumulated in FP64 over samples.  A Fourier mode on an axis only needs the
+// accumulated in FP64 over samples together with their squares (for the
+// sampling error).  A Fourier mode on an axis only needs the
 // plane sums of the field along that axis, so each sample is: plane sums
 // (coalesced, fixed-order reductions) and a length-L DFT per axis.
 #pragma once
@@ -94,8 +95,10 @@ __global__ __launch_bounds__(kRedBlock) void k_plane_x2(Geom g, int nf, const do
 }
 
 // DFT of the plane sums along each axis.  One thread per (field, axis, m).
-// sk[a*Lmax + m] += |X|^2/N for field 0; uk[(a*d + b)*Lmax + m] += |X|^2/N for
-// field 1 + b; cur (if non-null) receives field 0's complex X as [a][m][re,im].
+// sk[a*Lmax + m] += |X|^2/N for field 0 and sk[(d + a)*Lmax + m] += its
+// square; uk[(a*d + b)*Lmax + m] and uk[(d*d + a*d + b)*Lmax + m] likewise
+// for field 1 + b; cur (if non-null) receives field 0's complex X as
+// [a][m][re,im].
 __global__ __launch_bounds__(kRedBlock) void k_axis_dft(Geom g, int d, int nf, int Lmax,
                                                         const double* __restrict__ planes,
                                                         double* __restrict__ sk,
@@ -123,13 +126,17 @@ __global__ __launch_bounds__(kRedBlock) void k_axis_dft(Geom g, int d, int nf, i
   }
   const double pw = (re * re + im * im) / static_cast<double>(g.N);
   if (f == 0) {
-    if (sk) sk[a * Lmax + m] += pw;
+    if (sk) {
+      sk[a * Lmax + m] += pw;
+      sk[(d + a) * Lmax + m] += pw * pw;
+    }
     if (cur) {
       cur[(a * Lmax + m) * 2 + 0] = re;
       cur[(a * Lmax + m) * 2 + 1] = im;
     }
   } else if (uk) {
     uk[(a * d + (f - 1)) * Lmax + m] += pw;
+    uk[(d * d + a * d + (f - 1)) * Lmax + m] += pw * pw;
   }
 }
 

@@ -27,7 +27,8 @@ LBL_FP64, LBL_FP32DEV = 0, 1
 LBL_FULL, LBL_SMOL_ONLY, LBL_LB_ONLY = 0, 1, 2
 LBL_INIT_REST, LBL_INIT_TANH_2IF, LBL_INIT_USER = 0, 1, 2
 (LBL_OBS_PSI, LBL_OBS_RHO, LBL_OBS_U, LBL_OBS_POP, LBL_OBS_TOTALS, LBL_OBS_SK_AXES,
- LBL_OBS_UK_AXES, LBL_OBS_STEP, LBL_OBS_NSAMPLES, LBL_OBS_PSIK_AXES) = range(10)
+ LBL_OBS_UK_AXES, LBL_OBS_STEP, LBL_OBS_NSAMPLES, LBL_OBS_PSIK_AXES, LBL_OBS_SK2_AXES,
+ LBL_OBS_UK2_AXES) = range(12)
 
 
 class lbl_params(ctypes.Structure):
@@ -330,9 +331,9 @@ class Sim:
         if what in (LBL_OBS_STEP, LBL_OBS_NSAMPLES):
             return int(out[0])
         L = max(self.params.nx, self.params.ny, self.params.nz)
-        if what == LBL_OBS_SK_AXES:
+        if what in (LBL_OBS_SK_AXES, LBL_OBS_SK2_AXES):
             return out.reshape(self.d, L)
-        if what == LBL_OBS_UK_AXES:
+        if what in (LBL_OBS_UK_AXES, LBL_OBS_UK2_AXES):
             return out.reshape(self.d, self.d, L)
         if what == LBL_OBS_PSIK_AXES:
             o = out.reshape(self.d, L, 2)

@@ -1,7 +1,8 @@
 """GPU parity of the on-device Fourier observables and of the non-finite
 trap: the sampled axis structure factors S_a(k) and velocity spectra
-U_ab(k) against the oracle's axis spectra of the same trajectory, the
-instantaneous psi(k) against numpy's FFT of the oracle's field."""
+U_ab(k), and the means of their squares, against the oracle's axis spectra of
+the same trajectory; the instantaneous psi(k) against numpy's FFT of the
+oracle's field."""
 import numpy as np
 import pytest
 
@@ -23,6 +24,8 @@ def test_sampled_spectra_match_oracle(lattice, shape, smol, precision):
         sim.step(nsteps)
         sk = sim.observe(lbl.LBL_OBS_SK_AXES)
         uk = sim.observe(lbl.LBL_OBS_UK_AXES)
+        sk2 = sim.observe(lbl.LBL_OBS_SK2_AXES)
+        uk2 = sim.observe(lbl.LBL_OBS_UK2_AXES)
         assert sim.observe(lbl.LBL_OBS_NSAMPLES) == nsteps // every
         psik = sim.observe(lbl.LBL_OBS_PSIK_AXES)
     p = H.oracle_params(c)
@@ -31,18 +34,26 @@ def test_sampled_spectra_match_oracle(lattice, shape, smol, precision):
     L = max(shape)
     sk_ref = np.zeros((d, L))
     uk_ref = np.zeros((d, d, L))
+    sk2_ref = np.zeros((d, L))
+    uk2_ref = np.zeros((d, d, L))
     for n in range(nsteps):
         u = O.velocity(p, f, O.force(p, psi))
         O.step(p, f, psi, n)
         if (n + 1) % every == 0:
-            sk_ref += O.axis_spectrum(p, psi, L)
+            s_ = O.axis_spectrum(p, psi, L)
+            sk_ref += s_
+            sk2_ref += s_ ** 2
             for b in range(d):
-                uk_ref[:, b, :] += O.axis_spectrum(p, u[b], L)
-    sk_ref /= nsteps // every
-    uk_ref /= nsteps // every
+                u_ = O.axis_spectrum(p, u[b], L)
+                uk_ref[:, b, :] += u_
+                uk2_ref[:, b, :] += u_ ** 2
+    ns = nsteps // every
+    sk_ref, uk_ref, sk2_ref, uk2_ref = sk_ref / ns, uk_ref / ns, sk2_ref / ns, uk2_ref / ns
     tol = 1e-11 if precision == H.FP64 else 2e-5
     assert H.rel_err(sk, sk_ref) < tol
     assert H.rel_err(uk, uk_ref) < tol
+    assert H.rel_err(sk2, sk2_ref) < 2 * tol
+    assert H.rel_err(uk2, uk2_ref) < 2 * tol
     grid = psi.reshape(shape[::-1] if d == 3 else shape[1::-1])
     F = np.fft.fftn(grid)  # axes (z,) y, x
     ref = [F[0, :], F[:, 0]] if d == 2 else [F[0, 0, :], F[0, :, 0], F[:, 0, 0]]
