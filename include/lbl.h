@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define LBL_ABI_VERSION 1
+#define LBL_ABI_VERSION 2
 
 typedef struct lbl_sim lbl_sim;
 
@@ -112,7 +112,11 @@ enum lbl_init_kind {
 
 /* Initial state.  z is the normal of Philox slot 0, tag 2, step 0 at each
  * site.  f0 (Q*N FP64, canonical order) and psi0 (N FP64) are read during
- * lbl_create only; they are device pointers if user_on_device != 0. */
+ * lbl_create only; they are device pointers if user_on_device != 0.
+ * step0 is the step counter of the initial state: the first lbl_step draws
+ * the noise of counter step0, so a simulation created with USER from the
+ * POP and PSI observables of another one at step n, with step0 = n,
+ * continues it bitwise (resume).  0 <= step0 < 2^32 (the noise counter). */
 typedef struct lbl_init {
   int32_t kind;
   int32_t user_on_device;
@@ -120,6 +124,7 @@ typedef struct lbl_init {
   double boost_u[3];
   const double *psi0;
   const double *f0;
+  int64_t step0;
 } lbl_init;
 
 /* Device memory and stream injection.  If alloc is NULL the library uses

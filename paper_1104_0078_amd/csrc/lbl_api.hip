@@ -275,6 +275,8 @@ int validate(const lbl_params* p, const lbl_init* in) {
     return fail(nullptr, LBL_E_INVAL, "USER init needs psi0 and f0");
   if (!std::isfinite(in->psi_std) || in->psi_std < 0)
     return fail(nullptr, LBL_E_INVAL, "psi_std must be finite and >= 0");
+  if (in->step0 < 0 || in->step0 > 0xffffffffLL)
+    return fail(nullptr, LBL_E_INVAL, "step0 must lie in [0, 2^32)");
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(in->boost_u[k])) return fail(nullptr, LBL_E_INVAL, "boost must be finite");
   return LBL_OK;
@@ -881,6 +883,7 @@ int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* e
                    "clear uk");
   if (!rc) rc = hip_check(s, hipMemsetAsync(s->u, 0, sz * N * s->d, s->stream), "clear u");
   if (!rc) rc = select(s->p).init(s, init);
+  s->step = init->step0;
   if (!rc) rc = hip_check(s, hipStreamSynchronize(s->stream), "create sync");
   if (rc) {
     std::string msg = s->err;

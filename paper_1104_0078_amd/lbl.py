@@ -50,6 +50,7 @@ class lbl_init(ctypes.Structure):
         ("kind", ctypes.c_int32), ("user_on_device", ctypes.c_int32),
         ("psi_std", ctypes.c_double), ("boost_u", ctypes.c_double * 3),
         ("psi0", ctypes.POINTER(ctypes.c_double)), ("f0", ctypes.POINTER(ctypes.c_double)),
+        ("step0", ctypes.c_int64),
     ]
 
 
@@ -243,10 +244,12 @@ def diag_normals(precision, seed, step, tag, site0, n_sites, n_slots, device=0):
     return out
 
 
-def make_init(kind=LBL_INIT_REST, psi_std=1e-3, boost=(0, 0, 0), f0=None, psi0=None):
-    """f0 (q, N) and psi0 (N,) float64 numpy arrays for LBL_INIT_USER."""
+def make_init(kind=LBL_INIT_REST, psi_std=1e-3, boost=(0, 0, 0), f0=None, psi0=None, step0=0):
+    """f0 (q, N) and psi0 (N,) float64 numpy arrays for LBL_INIT_USER; step0
+    is the step counter of the initial state (resume)."""
     ini = lbl_init()
     ini.kind = kind
+    ini.step0 = int(step0)
     ini.user_on_device = 0
     ini.psi_std = psi_std
     for k in range(3):
