@@ -268,7 +268,8 @@ enum lbl_request_state {
   LBL_REQ_QUEUED = 0,
   LBL_REQ_RUNNING = 1,
   LBL_REQ_DONE = 2,
-  LBL_REQ_FAILED = 3
+  LBL_REQ_FAILED = 3 /* creation failed, or the final FP64 totals were not
+                        finite (the request fails alone; no result) */
 };
 
 enum lbl_submit_flags {

@@ -1039,6 +1039,11 @@ void retire(lbl_pool* pl, PoolReq& r) {
   double t[10];
   int rc = lbl_observe(s, LBL_OBS_TOTALS, t, sizeof(t), 0);
   if (!rc) r.totals.insert(r.totals.end(), t, t + 10);
+  // A request whose state became non-finite fails alone: replicas share no
+  // memory, so the others are unaffected.
+  if (!rc && !std::all_of(t, t + 10, [](double v) { return std::isfinite(v); })) {
+    rc = fail(s, LBL_E_NONFINITE, "non-finite state at completion");
+  }
   std::vector<double> cur(2 * static_cast<size_t>(s->d) * s->Lmax);
   if (!rc) rc = lbl_observe(s, LBL_OBS_PSIK_AXES, cur.data(), cur.size() * 8, 0);
   if (!rc) {

@@ -133,3 +133,32 @@ def test_schedule_does_not_change_results():
             out.append(pool.result(rid, lbl.LBL_RES_PSI))
     for o in out[1:]:
         np.testing.assert_array_equal(o, out[0])
+
+
+def test_nonfinite_request_fails_alone():
+    """A request whose state holds a NaN fails on its own; the requests
+    batched with it finish with exactly the fields they have alone."""
+    from paper_1104_0078_amd import lbl
+    import oracle as O
+    bad_c = H.config(lattice=H.D2Q9, smol=H.FD, shape=(48, 40, 1), seed=21)
+    f0, psi0 = O.init(H.oracle_params(bad_c), 0, 1e-3)
+    psi0[77] = np.nan
+    good = MIX[:2]
+    alone = []
+    for c, n in good:
+        with lbl.Pool(1 << 30) as pool:
+            rid = pool.submit(H.lbl_params(c), lbl.make_init(kind=c["init"], psi_std=1e-3), n,
+                              keep_psi=True)
+            _run_pool(pool)
+            alone.append(pool.result(rid, lbl.LBL_RES_PSI))
+    with lbl.Pool(1 << 30) as pool:
+        bad = pool.submit(H.lbl_params(bad_c),
+                          lbl.make_init(kind=lbl.LBL_INIT_USER, f0=f0, psi0=psi0), 30)
+        ids = [pool.submit(H.lbl_params(c), lbl.make_init(kind=c["init"], psi_std=1e-3), n,
+                           keep_psi=True) for c, n in good]
+        _run_pool(pool)
+        assert pool.poll(bad)[0] == lbl.LBL_REQ_FAILED
+        for rid, ref in zip(ids, alone):
+            assert pool.poll(rid)[0] == lbl.LBL_REQ_DONE
+            np.testing.assert_array_equal(pool.result(rid, lbl.LBL_RES_PSI), ref)
+        assert pool.stats()["failed"] == 1
