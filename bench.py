@@ -273,6 +273,7 @@ def run_served(lbl, torch, rate, seconds, budget_gb=200, tick=200, seed=1234):
     import numpy as np
     mix = served_mix(rate, seconds, seed)
     lat, lups, drift = [], 0.0, 0.0
+    max_queued = max_running = 0
     with lbl.Pool(int(budget_gb * 1e9)) as pool:
         live = {}
         nxt = 0
@@ -300,6 +301,9 @@ def run_served(lbl, torch, rate, seconds, budget_gb=200, tick=200, seed=1234):
                 continue
             pool.run(tick)
             t_end = time.monotonic() - t_start
+            st_ = pool.stats()
+            max_queued = max(max_queued, int(st_["queued"]))
+            max_running = max(max_running, int(st_["running"]))
             for rid in list(live):
                 st, _ = pool.poll(rid)
                 if st in (lbl.LBL_REQ_DONE, lbl.LBL_REQ_FAILED):
@@ -320,6 +324,7 @@ def run_served(lbl, torch, rate, seconds, budget_gb=200, tick=200, seed=1234):
             "p99_s": round(float(np.percentile(lat, 99)), 3),
             "aggregate_mlups": round(lups / t_total / 1e6, 1), "wall_s": round(t_total, 2),
             "budget_gb": budget_gb, "max_mass_drift_rel": drift,
+            "max_queued": max_queued, "max_running": max_running,
             "mix": "70% D2Q9+FD side U{64..512}, 30% D3Q19+FV side U{64..192}; one/two-phase, "
                    "FP32/FP64 50/50; steps log-uniform [500, 20000]; S(k) and totals returned"}
 
