@@ -264,7 +264,8 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
   S fv[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    fv[i] = a.f_in[static_cast<size_t>(i) * g.N + nb.at(-L::cx[i], -L::cy[i], -L::cz[i])];
+    fv[i] = __builtin_nontemporal_load(
+        &a.f_in[static_cast<size_t>(i) * g.N + nb.at(-L::cx[i], -L::cy[i], -L::cz[i])]);
 
   // Noise of the non-conserved modes, n_k = sigma_k z_k, with
   // sigma_k^2 = (1 - gamma_k^2) rho0 kT / c_s^2 per mode class.  Drawn after
@@ -387,8 +388,10 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
       constexpr int c = kIB<Q, D + 1 + k, i>;
       if constexpr (c != 0) nz += S(c) * nk[k];
     });
-    a.f_out[static_cast<size_t>(i) * g.N + s] =
-        S(L::w[i]) * (S0 + S(3) * cj + S(4.5) * pq + nz);
+    // Populations are streamed: written once here, read once by the next
+    // step, so they bypass the caches (non-temporal).
+    __builtin_nontemporal_store(S(L::w[i]) * (S0 + S(3) * cj + S(4.5) * pq + nz),
+                                &a.f_out[static_cast<size_t>(i) * g.N + s]);
   });
 }
 
