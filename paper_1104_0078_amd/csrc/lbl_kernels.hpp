@@ -309,9 +309,10 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
   const S uy = (jy + S(0.5) * F[1]) * inv_rho;
   const S uz = D == 3 ? (jz + S(0.5) * F[2]) * inv_rho : S(0);
   if (a.u_out) {
-    a.u_out[s] = ux;
-    a.u_out[g.N + s] = uy;
-    if (D == 3) a.u_out[2 * g.N + s] = uz;
+    // Read back only after other passes have streamed through the caches.
+    __builtin_nontemporal_store(ux, &a.u_out[s]);
+    __builtin_nontemporal_store(uy, &a.u_out[g.N + s]);
+    if (D == 3) __builtin_nontemporal_store(uz, &a.u_out[2 * g.N + s]);
   }
   if constexpr (!COLLIDE) return;
 
