@@ -366,6 +366,7 @@ struct Impl {
     a.step = step;
     a.force = force;
     a.noise = s->p.kT > 0;
+    a.nt = 2.0 * sizeof(S) * s->q * static_cast<double>(s->N) > kStreamBytes;
     return a;
   }
 
@@ -377,16 +378,24 @@ struct Impl {
     const SiteMap m = make_site_map(s->p.nx, s->p.ny, s->p.nz, s->lb_lw, (s->lb_swizzle & 1) != 0);
     const dim3 grid(site_map_blocks(m)), block(kSiteBlock);
     const bool ghost = s->gamma_g != 0.0;
-    if (!collide)
-      return launch(s, name, [&] {
-        k_lb<S, DEV, Q, SMOL, false, false><<<grid, block, 0, s->stream>>>(a, m);
-      });
-    if (ghost)
-      return launch(s, name, [&] {
-        k_lb<S, DEV, Q, SMOL, true, true><<<grid, block, 0, s->stream>>>(a, m);
-      });
+    const hipStream_t st = s->stream;
     return launch(s, name, [&] {
-      k_lb<S, DEV, Q, SMOL, false, true><<<grid, block, 0, s->stream>>>(a, m);
+      if (!collide) {
+        if (a.nt)
+          k_lb<S, DEV, Q, SMOL, false, false, true><<<grid, block, 0, st>>>(a, m);
+        else
+          k_lb<S, DEV, Q, SMOL, false, false, false><<<grid, block, 0, st>>>(a, m);
+      } else if (ghost) {
+        if (a.nt)
+          k_lb<S, DEV, Q, SMOL, true, true, true><<<grid, block, 0, st>>>(a, m);
+        else
+          k_lb<S, DEV, Q, SMOL, true, true, false><<<grid, block, 0, st>>>(a, m);
+      } else {
+        if (a.nt)
+          k_lb<S, DEV, Q, SMOL, false, true, true><<<grid, block, 0, st>>>(a, m);
+        else
+          k_lb<S, DEV, Q, SMOL, false, true, false><<<grid, block, 0, st>>>(a, m);
+      }
     });
   }
 
@@ -636,17 +645,23 @@ struct Impl {
   // caller into a graph).
   static int enqueue_group(hipStream_t stream, const void* reps_dev, RepState* states, int nrep,
                            const Work* wlb, int nlb, int lb_lw, const Work* wtile, int ntile,
-                           int rk, bool ghost, int64_t nsteps) {
+                           int rk, bool ghost, int nt, int64_t nsteps) {
     const Replica<S>* reps = static_cast<const Replica<S>*>(reps_dev);
     const dim3 bsite(kSiteBlock), btile(kTX, kTY);
     for (int64_t k = 0; k < nsteps; ++k) {
       kb_prep<S, Q, SMOL><<<ntile, btile, 0, stream>>>(reps, states, wtile);
-      if (ghost)
-        kb_lb<S, DEV, Q, SMOL, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw);
+      if (ghost && nt)
+        kb_lb<S, DEV, Q, SMOL, true, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw);
+      else if (ghost)
+        kb_lb<S, DEV, Q, SMOL, true, false><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw);
+      else if (nt)
+        kb_lb<S, DEV, Q, SMOL, false, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw);
       else
-        kb_lb<S, DEV, Q, SMOL, false><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw);
-      if (rk > 1)
-        kb_uend<S, DEV, Q, SMOL><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw, rk);
+        kb_lb<S, DEV, Q, SMOL, false, false><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw);
+      if (rk > 1 && nt)
+        kb_uend<S, DEV, Q, SMOL, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw, rk);
+      else if (rk > 1)
+        kb_uend<S, DEV, Q, SMOL, false><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw, rk);
       for (int st = 0; st < rk; ++st)
         kb_stage<S, Q, SMOL><<<ntile, btile, 0, stream>>>(reps, states, wtile, st, rk);
       kb_advance<S><<<(nrep + 255) / 256, 256, 0, stream>>>(reps, states, nrep);
@@ -713,7 +728,7 @@ using ObsFn = int (*)(lbl_sim*, int, double*);
 using TablesFn = void (*)(const std::vector<lbl_sim*>&, int, int, void*, std::vector<Work>&,
                           std::vector<Work>&);
 using EnqueueFn = int (*)(hipStream_t, const void*, RepState*, int, const Work*, int, int,
-                          const Work*, int, int, bool, int64_t);
+                          const Work*, int, int, bool, int, int64_t);
 
 struct Table {
   StepFn step;
@@ -939,6 +954,7 @@ struct Group {
   DevBuf reps, states, wlb, wtile;
   int nlb = 0, ntile = 0;
   int lb_lw = 6;  // tile width the LB work table was built with
+  int nt = 0;     // populations streamed non-temporally (large groups)
   int lane = 0;   // stream lane this tick of the group runs on
   bool dirty = true;
   hipGraphExec_t exec = nullptr;
@@ -1143,6 +1159,11 @@ int run_group(lbl_pool* pl, Group& g, int64_t max_steps) {
       return pool_fail(pl, LBL_E_DEVICE, std::string("pool tables: ") + hipGetErrorString(e));
     g.nlb = static_cast<int>(wlb.size());
     g.lb_lw = pl->lb_lw;
+    // Stream the populations past the caches when the group's populations
+    // together outgrow the memory-side cache.
+    double pop_bytes = 0;
+    for (const lbl_sim* m : sims) pop_bytes += 2.0 * m->ssize * m->q * static_cast<double>(m->N);
+    g.nt = pop_bytes > kStreamBytes;
     g.ntile = static_cast<int>(wtile.size());
     g.dirty = false;
   }
@@ -1163,7 +1184,7 @@ int run_group(lbl_pool* pl, Group& g, int64_t max_steps) {
     const int rc = t.enqueue(ls, g.reps.ptr, static_cast<RepState*>(g.states.ptr), n,
                              static_cast<const Work*>(g.wlb.ptr), g.nlb, g.lb_lw,
                              static_cast<const Work*>(g.wtile.ptr), g.ntile, g.key.rk,
-                             g.key.ghost != 0, steps);
+                             g.key.ghost != 0, g.nt, steps);
     e = hipStreamEndCapture(ls, &graph);
     if (rc || e != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);

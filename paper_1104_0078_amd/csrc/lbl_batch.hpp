@@ -79,7 +79,7 @@ __device__ __forceinline__ void lb_tile_site(const Work& w, int lw, int& x, int&
   y = w.by * (kSiteBlock >> lw) + (threadIdx.x >> lw);
 }
 
-template <typename S, bool DEV, int Q, int SMOL, bool GHOST>
+template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool NT>
 __global__ __launch_bounds__(kSiteBlock) void kb_lb(const Replica<S>* __restrict__ reps,
                                                       const RepState* __restrict__ st,
                                                       const Work* __restrict__ work, int lw) {
@@ -106,15 +106,16 @@ __global__ __launch_bounds__(kSiteBlock) void kb_lb(const Replica<S>* __restrict
   a.step = rs.step;
   a.force = r.coupling == kCplFull;
   a.noise = r.noise_on;
+  a.nt = NT;
   int x, y;
   lb_tile_site(w, lw, x, y);
-  if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, GHOST, true>(a, x, y, w.bz);
+  if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, GHOST, true, NT>(a, x, y, w.bz);
 }
 
 // Velocity of the streamed populations, (jbar^{n+1} + F^n/2)/rho^{n+1}, for
 // the Runge-Kutta stages at t_{n+1}: the LB body without collision, pulling
 // the populations the step just wrote.
-template <typename S, bool DEV, int Q, int SMOL>
+template <typename S, bool DEV, int Q, int SMOL, bool NT>
 __global__ __launch_bounds__(kSiteBlock) void kb_uend(const Replica<S>* __restrict__ reps,
                                                      const RepState* __restrict__ st,
                                                      const Work* __restrict__ work, int lw, int rk) {
@@ -132,9 +133,10 @@ __global__ __launch_bounds__(kSiteBlock) void kb_uend(const Replica<S>* __restri
   a.rho0 = r.rho0;
   a.force = 1;
   a.noise = 0;
+  a.nt = NT;
   int x, y;
   lb_tile_site(w, lw, x, y);
-  if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, false, false>(a, x, y, w.bz);
+  if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, false, false, NT>(a, x, y, w.bz);
 }
 
 // Stage `st` of `ns` (ns = 1, 2 or 4), with the same combinations as the

@@ -218,12 +218,17 @@ struct LBArgs {
   uint32_t k0, k1, step;
   int force;  // 0: F = 0 (LB_ONLY)
   int noise;  // 0: kT == 0
+  int nt;     // host's choice of the NT kernel variant (see kStreamBytes)
 };
+
+// Launches whose populations outgrow the memory-side cache (256 MB on
+// MI355X) stream them non-temporally; smaller working sets keep them cached.
+constexpr double kStreamBytes = 256.0 * 1024 * 1024;
 
 // GHOST: the ghost modes keep gamma_g m_g (omega_ghost != 1).
 // COLLIDE: false computes only u (observable).
 // The caller passes a site on the lattice.
-template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool COLLIDE>
+template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool COLLIDE, bool NT>
 __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z) {
   using L = Lat<Q>;
   constexpr int D = L::D;
@@ -263,9 +268,13 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
 
   S fv[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i)
-    fv[i] = __builtin_nontemporal_load(
-        &a.f_in[static_cast<size_t>(i) * g.N + nb.at(-L::cx[i], -L::cy[i], -L::cz[i])]);
+  for (int i = 0; i < Q; ++i) {
+    const S* src = &a.f_in[static_cast<size_t>(i) * g.N + nb.at(-L::cx[i], -L::cy[i], -L::cz[i])];
+    if constexpr (NT)
+      fv[i] = __builtin_nontemporal_load(src);
+    else
+      fv[i] = *src;
+  }
 
   // Noise of the non-conserved modes, n_k = sigma_k z_k, with
   // sigma_k^2 = (1 - gamma_k^2) rho0 kT / c_s^2 per mode class.  Drawn after
@@ -310,9 +319,15 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
   const S uz = D == 3 ? (jz + S(0.5) * F[2]) * inv_rho : S(0);
   if (a.u_out) {
     // Read back only after other passes have streamed through the caches.
-    __builtin_nontemporal_store(ux, &a.u_out[s]);
-    __builtin_nontemporal_store(uy, &a.u_out[g.N + s]);
-    if (D == 3) __builtin_nontemporal_store(uz, &a.u_out[2 * g.N + s]);
+    if constexpr (NT) {
+      __builtin_nontemporal_store(ux, &a.u_out[s]);
+      __builtin_nontemporal_store(uy, &a.u_out[g.N + s]);
+      if (D == 3) __builtin_nontemporal_store(uz, &a.u_out[2 * g.N + s]);
+    } else {
+      a.u_out[s] = ux;
+      a.u_out[g.N + s] = uy;
+      if (D == 3) a.u_out[2 * g.N + s] = uz;
+    }
   }
   if constexpr (!COLLIDE) return;
 
@@ -390,16 +405,20 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
       if constexpr (c != 0) nz += S(c) * nk[k];
     });
     // Populations are streamed: written once here, read once by the next
-    // step, so they bypass the caches (non-temporal).
-    __builtin_nontemporal_store(S(L::w[i]) * (S0 + S(3) * cj + S(4.5) * pq + nz),
-                                &a.f_out[static_cast<size_t>(i) * g.N + s]);
+    // step, so large lattices bypass the caches with them (non-temporal).
+    const S fo = S(L::w[i]) * (S0 + S(3) * cj + S(4.5) * pq + nz);
+    S* dst = &a.f_out[static_cast<size_t>(i) * g.N + s];
+    if constexpr (NT)
+      __builtin_nontemporal_store(fo, dst);
+    else
+      *dst = fo;
   });
 }
 
-template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool COLLIDE>
+template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool COLLIDE, bool NT>
 __global__ __launch_bounds__(kSiteBlock) void k_lb(LBArgs<S> a, SiteMap m) {
   int x, y, z;
-  if (site_of(m, a.g, x, y, z)) lb_body<S, DEV, Q, SMOL, GHOST, COLLIDE>(a, x, y, z);
+  if (site_of(m, a.g, x, y, z)) lb_body<S, DEV, Q, SMOL, GHOST, COLLIDE, NT>(a, x, y, z);
 }
 
 // ---------------------------------------------------------------------------
