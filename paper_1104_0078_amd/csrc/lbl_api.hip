@@ -1,6 +1,7 @@
 // lbl_api.hip -- the C ABI of include/lbl.h: simulation lifecycle, parameter
-// validation, device memory through the injected allocator, and the per-step
-// launch sequence of the coupled FLBE + SMOL sweep.
+// validation, device memory through the injected allocator, the per-step
+// launch sequence of the coupled FLBE + SMOL sweep, observables, launch
+// schedules, and the pool that batches independent simulations.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -157,9 +158,8 @@ int kernel_slot(lbl_sim* s, const char* name) {
   return static_cast<int>(s->kt.size()) - 1;
 }
 
-// Launch `fn` (a kernel launch on s->stream), bracketed by timing events when
-// timing is enabled, and check the launch.
-// Launch through `fn` on `stream`, bracketed by timing events when timing is on.
+// Launch through `fn` on `stream`, bracketed by timing events when timing is
+// on, and check the launch.
 template <class Fn>
 int launch_on(lbl_sim* s, hipStream_t stream, const char* name, Fn&& fn) {
   hipEvent_t a = nullptr, b = nullptr;

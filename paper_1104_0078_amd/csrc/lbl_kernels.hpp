@@ -3,16 +3,18 @@
 // Storage type S is double (FP64 path) or float (FP32-deviation path, where
 // populations hold fbar_i - w_i rho0).  Arithmetic runs in S.
 //
-// Per step (full coupling):
-//   k_mu        mu(psi^n)                                    one thread/site
+// Per step (full coupling), in launch order:
+//   k_prep_*    mu(psi^n) for the LB force and the SMOL noise N^n (frozen
+//               over the stages); z-marching tiles, noise folded through LDS
 //   k_lb        pull-stream, force -psi grad mu, MRT collision with noise,
 //               writes f*^n and u^n                          one thread/site
-//   k_noise_*   SMOL noise N^n, each site's normals drawn once, neighbours
-//               shared through LDS (z-marching tiles)
+//   k_lb (no collision, "k_uend")  velocity of the streamed populations,
+//               (jbar^{n+1} + F^n/2)/rho^{n+1}, for the stages at t_{n+1}
 //   k_stage_*   one Runge-Kutta stage: phi -> mu(phi) -> fluxes -> divergence,
-//               all in LDS (z-marching tiles)
-// Populations are structure-of-arrays f[i*N + s]; the stored buffer holds the
-// post-collision values f*^{n-1} and step n pulls fbar^n(x) = f*^{n-1}(x - c_i).
+//               in LDS rings (z-marching tiles); once per stage
+// k_mu (mu alone) serves the velocity observable.  Populations are
+// structure-of-arrays f[i*N + s]; the stored buffer holds the post-collision
+// values f*^{n-1} and step n pulls fbar^n(x) = f*^{n-1}(x - c_i).
 #pragma once
 
 #include "lbl_device.hpp"
