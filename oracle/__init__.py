@@ -19,7 +19,7 @@ from . import build as _build
 
 FD, FV = 0, 1
 FULL, SMOL_ONLY, LB_ONLY = 0, 1, 2
-D2Q9, D3Q19 = 9, 19
+D2Q9, D3Q15, D3Q19 = 9, 15, 19
 TAG_LB, TAG_SMOL, TAG_INIT = 0, 1, 2
 
 

@@ -43,22 +43,39 @@ static const double W19[19] = {
     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 
-int orc_q(int lattice) { return lattice == ORC_D2Q9 ? 9 : (lattice == ORC_D3Q19 ? 19 : 0); }
-int orc_d(int lattice) { return lattice == ORC_D2Q9 ? 2 : (lattice == ORC_D3Q19 ? 3 : 0); }
+/* D3Q15, the paper's own lattice (Sec. VI): rest 2/9, the 6 axis links 1/9,
+ * the 8 cube corners 1/72; opposite velocities adjacent. */
+static const int32_t C15[15][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+    {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+static const double W15[15] = {
+    2.0 / 9,
+    1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+    1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72};
+
+int orc_q(int lattice) {
+  return lattice == ORC_D2Q9 ? 9 : (lattice == ORC_D3Q15 ? 15 : (lattice == ORC_D3Q19 ? 19 : 0));
+}
+int orc_d(int lattice) {
+  return lattice == ORC_D2Q9 ? 2 : ((lattice == ORC_D3Q15 || lattice == ORC_D3Q19) ? 3 : 0);
+}
 
 void orc_velocities(int lattice, int32_t *c, double *w) {
   int q = orc_q(lattice);
   for (int i = 0; i < q; i++) {
     for (int a = 0; a < 3; a++)
-      c[3 * i + a] = lattice == ORC_D2Q9 ? C9[i][a] : C19[i][a];
-    w[i] = lattice == ORC_D2Q9 ? W9[i] : W19[i];
+      c[3 * i + a] = lattice == ORC_D2Q9 ? C9[i][a] : (lattice == ORC_D3Q15 ? C15[i][a] : C19[i][a]);
+    w[i] = lattice == ORC_D2Q9 ? W9[i] : (lattice == ORC_D3Q15 ? W15[i] : W19[i]);
   }
 }
 
 /* Monomial k evaluated at velocity (x, y, z).  Reading: the mode basis is the
  * Gram-Schmidt orthonormalisation of these monomials under the weighted inner
  * product <a,b> = sum_i w_i a(c_i) b(c_i).  Modes 0..d are mass and momentum,
- * then the stress modes (bulk first, then shear), then the ghosts. */
+ * then the stress modes (bulk first, then shear), then the ghosts.  Every
+ * 3-D lattice has 6 stress modes (4..9). */
 static double monomial(int lattice, int k, double x, double y, double z) {
   if (lattice == ORC_D2Q9) {
     switch (k) {
@@ -71,6 +88,27 @@ static double monomial(int lattice, int k, double x, double y, double z) {
       case 6: return x * y * y;
       case 7: return x * x * y;
       default: return x * x * y * y;
+    }
+  }
+  if (lattice == ORC_D3Q15) {
+    /* 1, x, y, z, c^2, x^2, y^2, xy, xz, yz, x c^2, y c^2, z c^2, c^4, xyz */
+    double c2 = x * x + y * y + z * z;
+    switch (k) {
+      case 0: return 1.0;
+      case 1: return x;
+      case 2: return y;
+      case 3: return z;
+      case 4: return c2;
+      case 5: return x * x;
+      case 6: return y * y;
+      case 7: return x * y;
+      case 8: return x * z;
+      case 9: return y * z;
+      case 10: return x * c2;
+      case 11: return y * c2;
+      case 12: return z * c2;
+      case 13: return c2 * c2;
+      default: return x * y * z;
     }
   }
   switch (k) {
@@ -232,7 +270,7 @@ static int64_t shift(const orc_params *p, int64_t s, int cx, int cy, int cz) {
  * with symbol cos qx + cos qy + cos qx cos qy - 3. */
 void orc_laplacian(const orc_params *p, const double *in, double *out) {
   int64_t N = nsites(p);
-  int three_d = p->lattice == ORC_D3Q19;
+  int three_d = orc_d(p->lattice) == 3;
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < N; s++) {
     double s1 = 0.0, s2 = 0.0, s3 = 0.0;

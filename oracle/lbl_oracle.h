@@ -27,13 +27,13 @@
 extern "C" {
 #endif
 
-enum { ORC_D2Q9 = 9, ORC_D3Q19 = 19 };
+enum { ORC_D2Q9 = 9, ORC_D3Q15 = 15, ORC_D3Q19 = 19 };
 enum { ORC_FD = 0, ORC_FV = 1 };
 enum { ORC_FULL = 0, ORC_SMOL_ONLY = 1, ORC_LB_ONLY = 2 };
 enum { ORC_TAG_LB = 0, ORC_TAG_SMOL = 1, ORC_TAG_INIT = 2 };
 
 typedef struct orc_params {
-  int32_t lattice;     /* ORC_D2Q9 or ORC_D3Q19 */
+  int32_t lattice;     /* ORC_D2Q9, ORC_D3Q15 or ORC_D3Q19 */
   int32_t smol;        /* ORC_FD or ORC_FV */
   int32_t coupling;    /* ORC_FULL, ORC_SMOL_ONLY, ORC_LB_ONLY */
   int32_t rk_stages;   /* 1 (Euler), 2 (Heun), 4 (classical RK4) */

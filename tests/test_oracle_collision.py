@@ -54,7 +54,7 @@ def _eta_for(omega, rho0=1.0):
     return (1.0 / omega - 0.5) * rho0 * CS2
 
 
-@pytest.mark.parametrize("lattice", [O.D2Q9, O.D3Q19])
+@pytest.mark.parametrize("lattice", [O.D2Q9, O.D3Q15, O.D3Q19])
 def test_basis_structure(lattice):
     E = O.basis(lattice)
     c, w, d = _lat(lattice)
@@ -84,7 +84,7 @@ def test_basis_structure(lattice):
         assert abs((E[k] * w) @ trQ) < 1e-14
 
 
-@pytest.mark.parametrize("lattice", [O.D2Q9, O.D3Q19])
+@pytest.mark.parametrize("lattice", [O.D2Q9, O.D3Q15, O.D3Q19])
 def test_equal_rates_is_single_relaxation_update(lattice):
     rng = np.random.default_rng(11)
     c, w, d = _lat(lattice)
@@ -102,7 +102,7 @@ def test_equal_rates_is_single_relaxation_update(lattice):
             np.testing.assert_allclose(got, expect, atol=2e-15)
 
 
-@pytest.mark.parametrize("lattice", [O.D2Q9, O.D3Q19])
+@pytest.mark.parametrize("lattice", [O.D2Q9, O.D3Q15, O.D3Q19])
 def test_ghost_projection_is_paper_bab(lattice):
     rng = np.random.default_rng(12)
     c, w, d = _lat(lattice)
@@ -132,7 +132,7 @@ def _moments(c, w, f):
     return rho, j, Pi, f - hydro
 
 
-@pytest.mark.parametrize("lattice", [O.D2Q9, O.D3Q19])
+@pytest.mark.parametrize("lattice", [O.D2Q9, O.D3Q15, O.D3Q19])
 def test_unequal_rates_relax_each_moment(lattice):
     rng = np.random.default_rng(13)
     c, w, d = _lat(lattice)
@@ -158,7 +158,7 @@ def test_unequal_rates_relax_each_moment(lattice):
         np.testing.assert_allclose(ghost2, (1 - wg) * ghost, atol=2e-15)
 
 
-@pytest.mark.parametrize("lattice", [O.D2Q9, O.D3Q19])
+@pytest.mark.parametrize("lattice", [O.D2Q9, O.D3Q15, O.D3Q19])
 def test_noise_only_in_nonconserved_modes(lattice):
     rng = np.random.default_rng(14)
     c, w, d = _lat(lattice)

@@ -16,6 +16,7 @@ import pytest
 import oracle as O
 
 CASES = [(O.D2Q9, O.FD, (20, 14, 1)), (O.D2Q9, O.FV, (20, 14, 1)),
+         (O.D3Q15, O.FD, (8, 7, 6)), (O.D3Q15, O.FV, (8, 7, 6)),
          (O.D3Q19, O.FD, (8, 7, 6)), (O.D3Q19, O.FV, (8, 7, 6))]
 
 
@@ -68,7 +69,8 @@ def _energy(p, f, psi):
 @pytest.mark.parametrize("lattice,smol,shape", [(O.D2Q9, O.FD, (24, 24, 1)),
                                                 (O.D2Q9, O.FV, (24, 24, 1)),
                                                 (O.D3Q19, O.FD, (10, 10, 10)),
-                                                (O.D3Q19, O.FV, (10, 10, 10))])
+                                                (O.D3Q19, O.FV, (10, 10, 10)),
+                                                (O.D3Q15, O.FV, (10, 10, 10))])
 def test_force_sign_dissipates_energy(lattice, smol, shape):
     p = O.make_params(lattice=lattice, smol=smol, shape=shape, a=-0.04, b=0.04, kappa=0.05,
                       kT=0.0, M=0.0)

@@ -15,7 +15,7 @@ import pytest
 
 import oracle as O
 
-CASES = [(O.D2Q9, (10, 8, 1)), (O.D3Q19, (6, 5, 4))]
+CASES = [(O.D2Q9, (10, 8, 1)), (O.D3Q15, (5, 6, 4)), (O.D3Q19, (6, 5, 4))]
 
 
 def _coords(p):
@@ -26,7 +26,7 @@ def _coords(p):
 
 def _so_symbol(q, lattice):
     c = np.cos(q)
-    if lattice == O.D3Q19:
+    if lattice != O.D2Q9:
         return (12 * c.sum() + 12 * (c[0] * c[1] + c[0] * c[2] + c[1] * c[2])
                 + 8 * c.prod() - 80) / 22
     return c[0] + c[1] + c[0] * c[1] - 3
@@ -37,6 +37,9 @@ def _fv_gamma(q, lattice):
     if lattice == O.D3Q19:
         return np.array([s[0] * (1 + c[1] + c[2]), s[1] * (1 + c[0] + c[2]),
                          s[2] * (1 + c[0] + c[1])]) / 3
+    if lattice == O.D3Q15:
+        return np.array([s[0] * (2 + c[1] * c[2]), s[1] * (2 + c[0] * c[2]),
+                         s[2] * (2 + c[0] * c[1])]) / 3
     return np.array([s[0] * (2 + c[1]), s[1] * (2 + c[0])]) / 3
 
 
@@ -92,7 +95,8 @@ def _matrix(fn, n_in, n_out):
     return M
 
 
-@pytest.mark.parametrize("lattice,shape", [(O.D2Q9, (5, 4, 1)), (O.D3Q19, (4, 4, 3))])
+@pytest.mark.parametrize("lattice,shape", [(O.D2Q9, (5, 4, 1)), (O.D3Q15, (4, 4, 3)),
+                                           (O.D3Q19, (4, 4, 3))])
 def test_fd_link_noise_covariance(lattice, shape):
     p = O.make_params(lattice=lattice, smol=O.FD, shape=shape, kT=0.7, M=0.3)
     N = O.nsites(p)
@@ -104,7 +108,8 @@ def test_fd_link_noise_covariance(lattice, shape):
     np.testing.assert_allclose(E.sum(axis=0), 0.0, atol=1e-14)
 
 
-@pytest.mark.parametrize("lattice,shape", [(O.D2Q9, (5, 4, 1)), (O.D3Q19, (4, 4, 3))])
+@pytest.mark.parametrize("lattice,shape", [(O.D2Q9, (5, 4, 1)), (O.D3Q15, (4, 4, 3)),
+                                           (O.D3Q19, (4, 4, 3))])
 def test_fv_noise_covariance(lattice, shape):
     p = O.make_params(lattice=lattice, smol=O.FV, shape=shape, kT=0.7, M=0.3)
     N = O.nsites(p)
@@ -120,7 +125,8 @@ def test_fv_noise_covariance(lattice, shape):
 @pytest.mark.parametrize("lattice,shape,smol", [(O.D2Q9, (16, 12, 1), O.FD),
                                                 (O.D2Q9, (16, 12, 1), O.FV),
                                                 (O.D3Q19, (6, 6, 6), O.FD),
-                                                (O.D3Q19, (6, 6, 6), O.FV)])
+                                                (O.D3Q19, (6, 6, 6), O.FV),
+                                                (O.D3Q15, (6, 6, 6), O.FV)])
 def test_generated_noise_variance(lattice, shape, smol):
     # Realised noise (Philox) has the diagonal variance -2 kT M L_out(0 offset).
     p = O.make_params(lattice=lattice, smol=smol, shape=shape, kT=2.0, M=0.25)

@@ -25,6 +25,7 @@ def _grid(p):
 
 
 @pytest.mark.parametrize("lattice,shape,nsteps", [(O.D2Q9, (12, 10, 1), 12000),
+                                                  (O.D3Q15, (6, 6, 4), 5000),
                                                   (O.D3Q19, (6, 6, 4), 5000)])
 def test_lb_equipartition(lattice, shape, nsteps):
     p = O.make_params(lattice=lattice, coupling=O.LB_ONLY, shape=shape, kT=1e-4, rho0=1.0)
@@ -49,12 +50,9 @@ def test_lb_equipartition(lattice, shape, nsteps):
     for a in range(d):
         mask = np.ones(g, dtype=bool)
         mask[(0,) * d] = False
-        L = g[d - 1 - a]
-        if L % 2 == 0:
-            idx = [0] * d
-            idx[d - 1 - a] = L // 2
-            assert Sj[a][tuple(idx)] < 1e-20  # staggered invariant, never excited
-            mask[tuple(idx)] = False
+        for idx in _staggered_invariants(lattice, g, a):
+            assert Sj[a][idx] < 1e-20  # staggered invariant, never excited
+            mask[idx] = False
         vals = Sj[a][mask]
         assert abs(vals.mean() - 1) < 0.03
         assert np.all(np.abs(vals - 1) < 0.3)
@@ -63,9 +61,33 @@ def test_lb_equipartition(lattice, shape, nsteps):
     assert abs(Sr[mask].mean() - 1) < 0.03
 
 
+def _staggered_invariants(lattice, g, a):
+    """Wave vectors (array indices, axes (z,) y, x) at which momentum component
+    a is invariant under the LB (R19): the longitudinal Nyquist mode of every
+    lattice, and on D3Q15, whose moving velocities all change the parity of
+    x + y + z, also k_a = 0 with the other two components at pi, and
+    (pi, pi, pi)."""
+    d = len(g)
+    half = [L // 2 if L % 2 == 0 else None for L in g]  # Nyquist index per array axis
+    ax = d - 1 - a  # array axis of component a
+    out = []
+    if half[ax] is not None:
+        idx = [0] * d
+        idx[ax] = half[ax]
+        out.append(tuple(idx))
+    if lattice == O.D3Q15 and all(h is not None for h in half):
+        others = [x for x in range(d) if x != ax]
+        idx = [0] * d
+        for x in others:
+            idx[x] = half[x]
+        out.append(tuple(idx))
+        out.append(tuple(half))
+    return out
+
+
 def _so_symbol(q, lattice):
     c = np.cos(q)
-    if lattice == O.D3Q19:
+    if lattice != O.D2Q9:
         return (12 * c.sum(0) + 12 * (c[0] * c[1] + c[0] * c[2] + c[1] * c[2])
                 + 8 * c[0] * c[1] * c[2] - 80) / 22
     return c[0] + c[1] + c[0] * c[1] - 3
@@ -76,6 +98,9 @@ def _fv_lap(q, lattice):
     if lattice == O.D3Q19:
         return -(s[0] ** 2 * (1 + c[1] + c[2]) ** 2 + s[1] ** 2 * (1 + c[0] + c[2]) ** 2
                  + s[2] ** 2 * (1 + c[0] + c[1]) ** 2) / 9
+    if lattice == O.D3Q15:
+        return -(s[0] ** 2 * (2 + c[1] * c[2]) ** 2 + s[1] ** 2 * (2 + c[0] * c[2]) ** 2
+                 + s[2] ** 2 * (2 + c[0] * c[1]) ** 2) / 9
     return -(s[0] ** 2 * (2 + c[1]) ** 2 + s[1] ** 2 * (2 + c[0]) ** 2) / 9
 
 
@@ -114,7 +139,8 @@ def test_smol_static_structure_factor(lattice, smol, shape, nsteps):
     assert np.all(np.abs(theory[live] / oz[live] - 1) < 0.25)
 
 
-@pytest.mark.parametrize("lattice,shape", [(O.D2Q9, (96, 2, 1)), (O.D3Q19, (64, 2, 2))])
+@pytest.mark.parametrize("lattice,shape", [(O.D2Q9, (96, 2, 1)), (O.D3Q15, (64, 2, 2)),
+                                           (O.D3Q19, (64, 2, 2))])
 def test_shear_wave_decay(lattice, shape):
     eta = 0.1
     p = O.make_params(lattice=lattice, coupling=O.LB_ONLY, shape=shape, kT=0.0, eta=eta)

@@ -62,10 +62,13 @@ def gamma_fv(q, lattice):
     if lattice == O.D3Q19:
         return 1j / 3 * np.array([s[0] * (1 + c[1] + c[2]), s[1] * (1 + c[0] + c[2]),
                                   s[2] * (1 + c[0] + c[1])])
+    if lattice == O.D3Q15:
+        return 1j / 3 * np.array([s[0] * (2 + c[1] * c[2]), s[1] * (2 + c[0] * c[2]),
+                                  s[2] * (2 + c[0] * c[1])])
     return 1j / 3 * np.array([s[0] * (2 + c[1]), s[1] * (2 + c[0])])
 
 
-CASES = [(O.D2Q9, (12, 10, 1)), (O.D3Q19, (8, 6, 5))]
+CASES = [(O.D2Q9, (12, 10, 1)), (O.D3Q15, (7, 6, 5)), (O.D3Q19, (8, 6, 5))]
 
 
 @pytest.mark.parametrize("lattice,shape", CASES)
@@ -73,12 +76,12 @@ def test_laplacian_symbol(lattice, shape):
     p = O.make_params(lattice=lattice, shape=shape)
     for k in _wavevectors(p):
         q, out, e = _apply_scalar(O.laplacian, p, k)
-        sym = so3(q) if lattice == O.D3Q19 else so2(q)
+        sym = so3(q) if lattice != O.D2Q9 else so2(q)
         np.testing.assert_allclose(out, sym * e, atol=1e-14)
         # the small-q limit is -q^2 for every admissible stencil (Sec. III)
-    p2 = O.make_params(lattice=lattice, shape=(64, 64, 64 if lattice == O.D3Q19 else 1))
-    q = 2 * np.pi * np.array([1, 2, 1 if lattice == O.D3Q19 else 0]) / 64
-    sym = so3(q) if lattice == O.D3Q19 else so2(q)
+    p2 = O.make_params(lattice=lattice, shape=(64, 64, 64 if lattice != O.D2Q9 else 1))
+    q = 2 * np.pi * np.array([1, 2, 1 if lattice != O.D2Q9 else 0]) / 64
+    sym = so3(q) if lattice != O.D2Q9 else so2(q)
     assert abs(sym + q @ q) < 0.01 * (q @ q)
 
 
@@ -112,6 +115,11 @@ def test_fv_laplacian_symbol(lattice, shape):
         if lattice == O.D3Q19:
             sym = -(sn[0] ** 2 * (1 + cs[1] + cs[2]) ** 2 + sn[1] ** 2 * (1 + cs[0] + cs[2]) ** 2
                     + sn[2] ** 2 * (1 + cs[0] + cs[1]) ** 2) / 9
+        elif lattice == O.D3Q15:
+            # The paper's own FV Laplacian of D3Q15, Eq. (fvlapft), written out.
+            sym = -((2 * sn[0] + sn[0] * cs[1] * cs[2]) ** 2
+                    + (2 * sn[1] + sn[1] * cs[0] * cs[2]) ** 2
+                    + (2 * sn[2] + sn[2] * cs[0] * cs[1]) ** 2) / 9
         else:
             sym = -(sn[0] ** 2 * (2 + cs[1]) ** 2 + sn[1] ** 2 * (2 + cs[0]) ** 2) / 9
         np.testing.assert_allclose(lc + 1j * ls, sym * e, atol=1e-14)

@@ -1,7 +1,8 @@
 """Closed forms used by the statistical and deterministic checks (test side).
 
 Lattice symbols: Shinozaki-Oono Laplacian (the paper's Eq. solapft in 3-D, its
-2-D analogue), FV Gamma and Gamma.Gamma for D2Q9/D3Q19, central difference.
+2-D analogue), FV Gamma and Gamma.Gamma for D2Q9/D3Q15/D3Q19 (for D3Q15 the
+paper's own Eq. fvlapft), central difference.
 SMOL discrete-time response for frozen-noise Runge-Kutta: the stability
 polynomial R(z) and noise transfer phi(z), the static structure factor
 2 kT M (-L_out) |phi|^2 / (1 - |R|^2), whose dt -> 0 limit is kT/(A - K L_SO)
@@ -9,13 +10,13 @@ polynomial R(z) and noise transfer phi(z), the static structure factor
 """
 import numpy as np
 
-D2Q9, D3Q19 = 9, 19
+D2Q9, D3Q15, D3Q19 = 9, 15, 19
 FD, FV = 0, 1
 
 
 def so_symbol(q, lattice):
     c = np.cos(q)
-    if lattice == D3Q19:
+    if lattice != D2Q9:
         return (12 * (c[0] + c[1] + c[2]) + 12 * (c[0] * c[1] + c[0] * c[2] + c[1] * c[2])
                 + 8 * c[0] * c[1] * c[2] - 80) / 22
     return c[0] + c[1] + c[0] * c[1] - 3
@@ -27,6 +28,9 @@ def fv_gamma(q, lattice):
     if lattice == D3Q19:
         return np.array([s[0] * (1 + c[1] + c[2]), s[1] * (1 + c[0] + c[2]),
                          s[2] * (1 + c[0] + c[1])]) / 3
+    if lattice == D3Q15:
+        return np.array([s[0] * (2 + c[1] * c[2]), s[1] * (2 + c[0] * c[2]),
+                         s[2] * (2 + c[0] * c[1])]) / 3
     return np.array([s[0] * (2 + c[1]), s[1] * (2 + c[0])]) / 3
 
 
