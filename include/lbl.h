@@ -2,7 +2,7 @@
  * lbl.h -- C ABI of the MI355X (gfx950) coupled lattice Boltzmann - Langevin
  * sweep for model H.
  *
- * One simulation advances a binary fluid on a periodic D2Q9 or D3Q19 lattice
+ * One simulation advances a binary fluid on a periodic D2Q9, D3Q15 or D3Q19 lattice
  * by the hybrid scheme of Sumesh, Pagonabarraga & Adhikari (arXiv:1104.0078):
  *   - momentum: fluctuating lattice Boltzmann (FLBE, Sec. IV and App. B),
  *     multiple-relaxation-time collision with the force density
@@ -24,6 +24,9 @@
  *     [i*N + s] for velocity i in the canonical order
  *       D2Q9 : 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1)
  *              7:(-1,-1) 8:(1,-1)
+ *       D3Q15: 0:(0,0,0) 1:(1,0,0) 2:(-1,0,0) 3:(0,1,0) 4:(0,-1,0) 5:(0,0,1)
+ *              6:(0,0,-1) 7:(1,1,1) 8:(-1,-1,-1) 9:(1,1,-1) 10:(-1,-1,1)
+ *              11:(1,-1,1) 12:(-1,1,-1) 13:(-1,1,1) 14:(1,-1,-1)
  *       D3Q19: 0:(0,0,0) 1:(1,0,0) 2:(-1,0,0) 3:(0,1,0) 4:(0,-1,0) 5:(0,0,1)
  *              6:(0,0,-1) 7:(1,1,0) 8:(-1,-1,0) 9:(1,-1,0) 10:(-1,1,0)
  *              11:(1,0,1) 12:(-1,0,-1) 13:(1,0,-1) 14:(-1,0,1) 15:(0,1,1)
@@ -58,7 +61,7 @@ enum lbl_status {
   LBL_E_UNSUPPORTED = -6 /* observable not available for this simulation */
 };
 
-enum lbl_lattice { LBL_D2Q9 = 9, LBL_D3Q19 = 19 };
+enum lbl_lattice { LBL_D2Q9 = 9, LBL_D3Q15 = 15, LBL_D3Q19 = 19 };
 enum lbl_smol { LBL_SMOL_FD = 0, LBL_SMOL_FV = 1 };
 enum lbl_precision {
   LBL_FP64 = 0,   /* populations, psi and all arithmetic in FP64 */

@@ -241,8 +241,8 @@ bool finite_all(const lbl_params& p) {
 
 int validate(const lbl_params* p, const lbl_init* in) {
   if (!p || !in) return fail(nullptr, LBL_E_INVAL, "params and init must not be NULL");
-  if (p->lattice != LBL_D2Q9 && p->lattice != LBL_D3Q19)
-    return fail(nullptr, LBL_E_INVAL, "lattice must be LBL_D2Q9 or LBL_D3Q19");
+  if (p->lattice != LBL_D2Q9 && p->lattice != LBL_D3Q15 && p->lattice != LBL_D3Q19)
+    return fail(nullptr, LBL_E_INVAL, "lattice must be LBL_D2Q9, LBL_D3Q15 or LBL_D3Q19");
   if (p->smol != LBL_SMOL_FD && p->smol != LBL_SMOL_FV)
     return fail(nullptr, LBL_E_INVAL, "smol must be LBL_SMOL_FD or LBL_SMOL_FV");
   if (p->precision != LBL_FP64 && p->precision != LBL_FP32DEV)
@@ -253,7 +253,7 @@ int validate(const lbl_params* p, const lbl_init* in) {
     return fail(nullptr, LBL_E_INVAL, "rk_stages must be 1, 2 or 4");
   if (p->nx < 4 || p->ny < 4) return fail(nullptr, LBL_E_INVAL, "nx and ny must be >= 4");
   if (p->lattice == LBL_D2Q9 && p->nz != 1) return fail(nullptr, LBL_E_INVAL, "D2Q9 needs nz == 1");
-  if (p->lattice == LBL_D3Q19 && p->nz < 4) return fail(nullptr, LBL_E_INVAL, "nz must be >= 4");
+  if (p->lattice != LBL_D2Q9 && p->nz < 4) return fail(nullptr, LBL_E_INVAL, "nz must be >= 4");
   const double n = static_cast<double>(p->nx) * p->ny * p->nz;
   if (n >= 2147483648.0) return fail(nullptr, LBL_E_INVAL, "nx*ny*nz must be < 2^31");
   if (!finite_all(*p)) return fail(nullptr, LBL_E_INVAL, "parameters must be finite");
@@ -745,16 +745,18 @@ Table table_for() {
   return Table{&I::steps, &I::init, &I::observe, &I::tables, &I::enqueue_group, I::replica_bytes()};
 }
 
-Table select(const lbl_params& p) {
-  const bool f32 = p.precision == LBL_FP32DEV;
-  const bool d3 = p.lattice == LBL_D3Q19;
+template <typename S, bool DEV>
+Table select_lattice(const lbl_params& p) {
   const bool fv = p.smol == LBL_SMOL_FV;
-  if (!f32) {
-    if (!d3) return fv ? table_for<double, false, 9, kFV>() : table_for<double, false, 9, kFD>();
-    return fv ? table_for<double, false, 19, kFV>() : table_for<double, false, 19, kFD>();
-  }
-  if (!d3) return fv ? table_for<float, true, 9, kFV>() : table_for<float, true, 9, kFD>();
-  return fv ? table_for<float, true, 19, kFV>() : table_for<float, true, 19, kFD>();
+  if (p.lattice == LBL_D2Q9) return fv ? table_for<S, DEV, 9, kFV>() : table_for<S, DEV, 9, kFD>();
+  if (p.lattice == LBL_D3Q15)
+    return fv ? table_for<S, DEV, 15, kFV>() : table_for<S, DEV, 15, kFD>();
+  return fv ? table_for<S, DEV, 19, kFV>() : table_for<S, DEV, 19, kFD>();
+}
+
+Table select(const lbl_params& p) {
+  if (p.precision == LBL_FP32DEV) return select_lattice<float, true>(p);
+  return select_lattice<double, false>(p);
 }
 
 // Device allocations of one simulation, in creation order.

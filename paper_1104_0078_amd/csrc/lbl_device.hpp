@@ -74,6 +74,35 @@ struct Lat<19> {
                                     1.0 / 22, 1.0 / 22, 1.0 / 22};
 };
 
+// D3Q15, the paper's own lattice (Sec. VI): rest 2/9, axes 1/9, cube
+// corners 1/72.
+template <>
+struct Lat<15> {
+  static constexpr int Q = 15, D = 3, NSTRESS = 6, NLINKS = 13;
+  static constexpr int cx[15] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1};
+  static constexpr int cy[15] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1};
+  static constexpr int cz[15] = {0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1, 1, -1};
+  static constexpr double w[15] = {2.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9,
+                                   1.0 / 9,  1.0 / 9,  1.0 / 72, 1.0 / 72, 1.0 / 72,
+                                   1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72};
+  // 1, x, y, z, c^2, x^2, y^2, xy, xz, yz, x c^2, y c^2, z c^2, c^4, xyz.
+  static constexpr double mono(int k, double x, double y, double z) {
+    return k == 0 ? 1.0 : k == 1 ? x : k == 2 ? y : k == 3 ? z
+         : k == 4 ? x * x + y * y + z * z : k == 5 ? x * x : k == 6 ? y * y
+         : k == 7 ? x * y : k == 8 ? x * z : k == 9 ? y * z
+         : k == 10 ? x * (x * x + y * y + z * z) : k == 11 ? y * (x * x + y * y + z * z)
+         : k == 12 ? z * (x * x + y * y + z * z)
+         : k == 13 ? (x * x + y * y + z * z) * (x * x + y * y + z * z) : x * y * z;
+  }
+  // The SMOL stencils do not depend on the LB lattice: Shinozaki-Oono links.
+  static constexpr int lx[13] = {1, 0, 0, 1, 1, 1, 1, 0, 0, 1, 1, 1, 1};
+  static constexpr int ly[13] = {0, 1, 0, 1, 0, 0, -1, 1, 1, 1, 1, -1, -1};
+  static constexpr int lz[13] = {0, 0, 1, 0, 1, -1, 0, 1, -1, 1, -1, 1, -1};
+  static constexpr double lw[13] = {6.0 / 22, 6.0 / 22, 6.0 / 22, 3.0 / 22, 3.0 / 22,
+                                    3.0 / 22, 3.0 / 22, 3.0 / 22, 3.0 / 22, 1.0 / 22,
+                                    1.0 / 22, 1.0 / 22, 1.0 / 22};
+};
+
 // ---------------------------------------------------------------------------
 // Compile-time orthonormal mode basis: classical Gram-Schmidt of the
 // monomials under <a,b> = sum_i w_i a(c_i) b(c_i).  e[k][i] = e_k(c_i).

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "liblbl.so")
 LBL_OK = 0
 LBL_E_INVAL, LBL_E_NOMEM, LBL_E_DEVICE = -1, -2, -3
 LBL_E_NONFINITE, LBL_E_BUFSIZE, LBL_E_UNSUPPORTED = -4, -5, -6
-LBL_D2Q9, LBL_D3Q19 = 9, 19
+LBL_D2Q9, LBL_D3Q15, LBL_D3Q19 = 9, 15, 19
 LBL_SMOL_FD, LBL_SMOL_FV = 0, 1
 LBL_FP64, LBL_FP32DEV = 0, 1
 LBL_FULL, LBL_SMOL_ONLY, LBL_LB_ONLY = 0, 1, 2

@@ -5,7 +5,7 @@ import numpy as np
 
 import oracle as O
 
-D2Q9, D3Q19 = 9, 19
+D2Q9, D3Q15, D3Q19 = 9, 15, 19
 FD, FV = 0, 1
 FP64, FP32DEV = 0, 1
 FULL, SMOL_ONLY, LB_ONLY = 0, 1, 2

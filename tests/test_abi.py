@@ -64,7 +64,7 @@ def test_constants_and_strings():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("lattice", 15), ("smol", 2), ("precision", 3), ("coupling", 7), ("rk_stages", 3),
+    ("lattice", 27), ("lattice", 0), ("smol", 2), ("precision", 3), ("coupling", 7), ("rk_stages", 3),
     ("nx", 3), ("nz", 2), ("eta", -1.0), ("rho", 0.0), ("kT", -1e-5), ("omega_bulk", 2.5),
     ("omega_ghost", 0.0), ("M", float("nan")), ("reserved", 1), ("sample_every", -2),
 ])

@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("lattice,shape,smol", [(H.D2Q9, (40, 28, 1), H.FD),
-                                                (H.D3Q19, (20, 12, 10), H.FV)])
+                                                (H.D3Q19, (20, 12, 10), H.FV),
+                                                (H.D3Q15, (12, 14, 10), H.FV)])
 @pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
 def test_sampled_spectra_match_oracle(lattice, shape, smol, precision):
     from paper_1104_0078_amd import lbl

@@ -12,7 +12,7 @@ from tests import harness as H
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = {H.D2Q9: (70, 45, 1), H.D3Q19: (21, 13, 11)}
+SHAPES = {H.D2Q9: (70, 45, 1), H.D3Q15: (19, 14, 9), H.D3Q19: (21, 13, 11)}
 
 
 def _gpu(c, nsteps, init=None):
@@ -34,7 +34,7 @@ def _check(c, nsteps, tol=None):
     assert ef <= tol and ep <= tol
 
 
-@pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q19])
+@pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q15, H.D3Q19])
 @pytest.mark.parametrize("smol", [H.FD, H.FV])
 @pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
 def test_coupled_one_phase(lattice, smol, precision):
@@ -42,7 +42,7 @@ def test_coupled_one_phase(lattice, smol, precision):
     _check(c, 20)
 
 
-@pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q19])
+@pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q15, H.D3Q19])
 @pytest.mark.parametrize("smol", [H.FD, H.FV])
 def test_coupled_two_phase_tanh(lattice, smol):
     c = H.config(lattice=lattice, smol=smol, shape=SHAPES[lattice], a=-0.04, b=0.04,
@@ -58,8 +58,9 @@ def test_partial_couplings_and_stages(coupling, rk):
     _check(c, 15)
 
 
-def test_mrt_rates_and_boost():
-    c = H.config(lattice=H.D3Q19, smol=H.FV, shape=SHAPES[H.D3Q19], omega_bulk=1.3,
+@pytest.mark.parametrize("lattice", [H.D3Q15, H.D3Q19])
+def test_mrt_rates_and_boost(lattice):
+    c = H.config(lattice=lattice, smol=H.FV, shape=SHAPES[lattice], omega_bulk=1.3,
                  omega_ghost=0.8, eta=0.05, boost=(0.02, -0.01, 0.015), kT=1e-4)
     _check(c, 15)
 
@@ -143,6 +144,7 @@ def test_schedule_does_not_change_results(lattice):
 
 @pytest.mark.parametrize("lattice,shape", [(H.D2Q9, (4, 4, 1)), (H.D2Q9, (5, 33, 1)),
                                            (H.D3Q19, (4, 4, 4)), (H.D3Q19, (5, 7, 4)),
+                                           (H.D3Q15, (4, 4, 4)), (H.D3Q15, (6, 5, 7)),
                                            (H.D3Q19, (33, 9, 5))])
 @pytest.mark.parametrize("smol", [H.FD, H.FV])
 def test_smallest_and_odd_lattices(lattice, shape, smol):

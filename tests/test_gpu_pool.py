@@ -40,6 +40,7 @@ MIX = [
               init=1), 25),
     (H.config(lattice=H.D2Q9, smol=H.FV, coupling=H.SMOL_ONLY, shape=(40, 40, 1), seed=16,
               u_imposed=(0.02, 0.01, 0)), 19),
+    (H.config(lattice=H.D3Q15, smol=H.FD, shape=(12, 18, 10), seed=17), 21),
 ]
 
 

@@ -30,7 +30,8 @@ def _sim(c, sample_every=0, init=None):
     return lbl.Sim(H.lbl_params(c, sample_every=sample_every), ini)
 
 
-@pytest.mark.parametrize("lattice,shape", [(H.D2Q9, (48, 40, 1)), (H.D3Q19, (20, 18, 16))])
+@pytest.mark.parametrize("lattice,shape", [(H.D2Q9, (48, 40, 1)), (H.D3Q15, (20, 18, 16)),
+                                           (H.D3Q19, (20, 18, 16))])
 @pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
 def test_equipartition(lattice, shape, precision):
     from paper_1104_0078_amd import lbl
