@@ -1,0 +1,461 @@
+"""The paper's own validation runs (Sec. VI) at its own settings, on the GPU.
+
+Run set-up common to Sec. VI: D3Q15, a 32^3 periodic lattice, tau = 1.1 read
+as nu = c_s^2 tau (eta = 1.1/3, the same reading as for the capillary runs),
+kT = 1/3000, Heun stages, statistics after equilibration.  The paper starts
+from equilibrium initial conditions; here psi is drawn from the stationary
+spectrum of the discrete scheme at rest and the populations start at rest.
+
+* Fig. test1a (and test2dia): error of the equilibrium ratio S(q) A/kT - 1
+  along the diagonal q_x = q_y = q_z for diffusion alone and coupled FD / FV,
+  A = 0.625, B = K = 0, M = 0.095;
+* Fig. test1upsi: no cross-correlation <u_alpha psi*>(q) between velocity
+  and order parameter;
+* Fig. test1b: isotropy of the ER on the |q| = 16 circles of the planes
+  q_z = N/8, 2N/8, 3N/8;
+* Figs. test2a, test2: S(q) over the whole Brillouin zone (the (q_x, q_y)
+  planes included) for A = 0.025, K = 0.01, M = 0.1 against Eq. (test2) with
+  the lattice Laplacian, diffusion alone FD and coupled FD / FV;
+* Fig. test3: the dynamic structure factor S(q, tau)/S(q, 0) of Eq. (strf)
+  for A = 0.065, K = 0.04, M = 0.095, FD and FV;
+* Fig. galinv: a uniform flow along x = y leaves S(q) unchanged at Ma = 0.08
+  and makes it anisotropic at Ma = 0.57, by the amount the discrete scheme
+  predicts;
+* Fig. tanh: the mean profile of a planar interface on a 64 x 64 lattice,
+  -A = B = 0.025, K = 0.01, M = 0.1, follows Eq. (tanh) with the width of
+  Eq. (intthick).
+
+Measured spectra are compared with the exact stationary spectrum of the
+discrete-time scheme (tests/theory.py), whose dt -> 0 limit is the
+paper's formula; the tables print the paper's own quantity (the ER against
+kT/(A - K L)) beside it.  Statistical bars come from the number of
+effectively independent samples the discrete-time relaxation rate gives.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests import harness as H
+from tests import inputs
+from tests import theory as T
+
+pytestmark = pytest.mark.gpu
+
+KT = 1.0 / 3000
+ETA = 1.1 / 3
+SHAPE = (32, 32, 32)
+
+
+def _paper(**kw):
+    base = dict(lattice=H.D3Q15, shape=SHAPE, kT=KT, eta=ETA, rho=1.0, b=0.0, psi_std=0.0,
+                seed=2011)
+    base.update(kw)
+    return H.config(**base)
+
+
+def _qgrid(shape):
+    """Wave vectors of numpy's fftn layout, (3, nz, ny, nx)."""
+    nx, ny, nz = shape
+    kx, ky, kz = (2 * np.pi * np.fft.fftfreq(n) for n in (nx, ny, nz))
+    qz, qy, qx = np.meshgrid(kz, ky, kx, indexing="ij")
+    return np.stack([qx, qy, qz])
+
+
+def _stationary(c, Q, U=(0, 0, 0)):
+    """Exact stationary S(q) of the SMOL scheme alone, its one-step
+    amplification |R|, and the Ornstein-Zernike form kT/(A - K L_SO)."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        s = T.smol_static_sk(Q, c["lattice"], c["smol"], c["M"], c["a"], c["kappa"], c["kT"],
+                             c["rk"], U)
+        z, _, _ = T.smol_z(Q, c["lattice"], c["smol"], c["M"], c["a"], c["kappa"], U)
+        R, _ = T.rk_poly(z, c["rk"])
+        oz = T.ornstein_zernike(Q, c["lattice"], c["a"], c["kappa"], c["kT"])
+    return s, np.abs(R), oz
+
+
+def _equilibrium_init(c, seed):
+    """psi with the stationary spectrum of the scheme at rest (Gaussian, mean
+    zero); populations at rest, f_i = w_i rho0."""
+    from paper_1104_0078_amd import lbl
+    nx, ny, nz = c["shape"]
+    N = nx * ny * nz
+    s, _, oz = _stationary(c, _qgrid(c["shape"]))
+    s = np.where(np.isfinite(s) & (s > 0), s, oz)  # FV modes that never relax
+    s.flat[0] = 0.0
+    w = inputs.random_field(N, 1.0, seed).reshape(nz, ny, nx)
+    psi = np.fft.ifftn(np.fft.fftn(w) * np.sqrt(s)).real
+    _, wts = O.velocities(c["lattice"])
+    f0 = np.repeat(wts[:, None] * c["rho"], N, axis=1)
+    return lbl.make_init(kind=lbl.LBL_INIT_USER, f0=f0, psi0=np.ascontiguousarray(psi.ravel()))
+
+
+def _n_eff(absR, nsamp, every):
+    """Effectively independent samples of |psi_q|^2 for a mode whose
+    amplitude decays by |R| per step, sampled every `every` steps."""
+    with np.errstate(invalid="ignore", over="ignore"):
+        rho = np.clip(absR, 0, 1) ** (2 * every)
+        return np.maximum(nsamp * (1 - rho) / (1 + rho), 1.0)
+
+
+def _run_spectra(c, init, burn, nsamp, every, keep=None, with_u=False):
+    """S(q) = <|psi_q|^2>/N over the whole zone; optionally the time series
+    of psi_q and u_q at the flat indices `keep`."""
+    from paper_1104_0078_amd import lbl
+    nx, ny, nz = c["shape"]
+    N = nx * ny * nz
+    acc = np.zeros((nz, ny, nx))
+    series_p = np.zeros((nsamp, len(keep)), complex) if keep is not None else None
+    series_u = np.zeros((nsamp, 3, len(keep)), complex) if with_u else None
+    t0 = time.perf_counter()
+    with lbl.Sim(H.lbl_params(c), init) as sim:
+        sim.step(burn)
+        for i in range(nsamp):
+            sim.step(every)
+            pk = np.fft.fftn(sim.observe(lbl.LBL_OBS_PSI).reshape(nz, ny, nx))
+            acc += pk.real ** 2 + pk.imag ** 2
+            if keep is not None:
+                series_p[i] = pk.ravel()[keep]
+            if with_u:
+                uk = np.fft.fftn(sim.observe(lbl.LBL_OBS_U).reshape(3, nz, ny, nx), axes=(1, 2, 3))
+                series_u[i] = uk.reshape(3, -1)[:, keep]
+        assert np.isfinite(sim.observe(lbl.LBL_OBS_TOTALS)).all()
+    print("  %d steps in %.1f s" % (burn + nsamp * every, time.perf_counter() - t0), flush=True)
+    return acc / (nsamp * N), series_p, series_u
+
+
+def _diag_indices(shape, m, signs):
+    nx, ny, nz = shape
+    sx, sy, sz = signs
+    return (((sz * m) % nz) * ny + (sy * m) % ny) * nx + (sx * m) % nx
+
+
+DIAGS = ((1, 1, 1), (1, 1, -1), (1, -1, 1), (-1, 1, 1))
+
+
+# Fig. test1a / test1upsi / test1b ------------------------------------------
+
+@pytest.mark.parametrize("coupling,smol", [(H.SMOL_ONLY, H.FD), (H.SMOL_ONLY, H.FV),
+                                           (H.FULL, H.FD), (H.FULL, H.FV)])
+def test_quadratic_free_energy_equilibrium_ratio(coupling, smol):
+    c = _paper(smol=smol, coupling=coupling, a=0.625, kappa=0.0, M=0.095)
+    print("ER case", c, flush=True)
+    Q = _qgrid(SHAPE)
+    s_th, absR, oz = _stationary(c, Q)
+    nsamp, every = 600, 40
+    L = SHAPE[0]
+    ms = np.arange(1, L // 2)
+    diag = np.array([[_diag_indices(SHAPE, m, sg) for sg in DIAGS] for m in ms])
+    rng = np.random.default_rng(5)
+    others = rng.choice(L ** 3, 1500, replace=False)
+    keep = np.concatenate([diag.ravel(), others])
+    S, sp, su = _run_spectra(c, _equilibrium_init(c, 31), 1000, nsamp, every, keep=keep,
+                             with_u=coupling == H.FULL)
+    ok = np.isfinite(s_th) & (s_th > 0)
+    ok.flat[0] = False
+    r = np.where(ok, S / np.where(ok, s_th, 1), np.nan)
+    ne = _n_eff(absR, nsamp, every)
+
+    # Whole zone: every mode relaxes within a few hundred steps at K = 0.
+    sig_all = 1 / np.sqrt(ne[ok].sum() / 2)  # q and -q are one mode
+    mean_all = np.nanmean(r)
+    # Diagonal q_x = q_y = q_z (four equivalent body diagonals).
+    rd = np.array([np.nanmean(r.ravel()[diag[i]]) for i in range(len(ms))])
+    sd = np.array([1 / np.sqrt(ne.ravel()[diag[i]].sum()) for i in range(len(ms))])
+    er = np.array([np.mean(S.ravel()[diag[i]] / oz.ravel()[diag[i]]) for i in range(len(ms))]) - 1
+    print("  zone mean S/S_exact %.4f (stat %.4f)" % (mean_all, sig_all))
+    print("  diagonal m  S/S_exact  ER-1 (paper's ER error)  stat")
+    for m, a, e, s in zip(ms, rd, er, sd):
+        print("    %2d  %.4f  %+.4f  %.4f" % (m, a, e, s))
+    # Fig. test1b: the |q| = 16 circles of the planes q_z = N/8, 2N/8, 3N/8.
+    nz_, ny_, nx_ = np.meshgrid(np.fft.fftfreq(L, 1 / L), np.fft.fftfreq(L, 1 / L),
+                                np.fft.fftfreq(L, 1 / L), indexing="ij")
+    ring = (np.abs(np.hypot(nx_, ny_) - 16) < 0.5) & ok
+    iso = []
+    for kz in (L // 8, 2 * L // 8, 3 * L // 8):
+        sel = ring & (nz_ == kz)
+        ratios = r[sel]
+        bar = 1 / np.sqrt(ne[sel])
+        iso.append((kz, ratios.mean(), ratios.std(), bar.mean(), np.abs((ratios - 1) / bar).max()))
+        print("  ring |q|=16 in plane q_z=%d: %d points, mean %.4f, spread %.4f (stat %.4f)"
+              % (kz, sel.sum(), ratios.mean(), ratios.std(), bar.mean()))
+
+    exact = coupling == H.SMOL_ONLY
+    assert abs(mean_all - 1) < (max(5 * sig_all, 0.003) if exact else 0.02)
+    assert np.all(np.abs(rd - 1) < 5 * sd + (0.0 if exact else 0.03))
+    # The paper's ER error along the diagonal stays within a few per cent.
+    assert np.all(np.abs(er) < 5 * sd + 0.03)
+    for kz, mu, spread, bar, zmax in iso:
+        assert abs(mu - 1) < 0.02 + 3 * bar / np.sqrt(8)
+        assert spread < 1.5 * bar + (0.0 if exact else 0.02)
+
+    if coupling == H.FULL:
+        # Fig. test1upsi: <u_alpha psi*>(q) / sqrt(<|u|^2><|psi|^2>) vanishes.
+        # The null level is the same estimator with u and psi taken half a
+        # run apart (identical autocorrelations, no equal-time correlation).
+        def corr(p, u):
+            num = (u * np.conj(p)[:, None, :]).mean(0)
+            den = np.sqrt((np.abs(u) ** 2).mean(0) * (np.abs(p) ** 2).mean(0)[None, :])
+            return num / den
+        rho = corr(sp, su)
+        rho_null = corr(np.roll(sp, nsamp // 2, axis=0), su)
+        nd = diag.size
+        rms, rms_null = np.sqrt((np.abs(rho) ** 2).mean()), np.sqrt((np.abs(rho_null) ** 2).mean())
+        print("  <u psi*> correlation: rms %.4f (null %.4f); diagonal max %.4f; 1/sqrt(n) %.4f"
+              % (rms, rms_null, np.abs(rho[:, :nd]).max(), 1 / np.sqrt(nsamp)))
+        assert rms < 1.3 * rms_null
+        assert np.abs(rho[:, :nd]).max() < 5 * rms_null
+
+
+# Figs. test2a, test2, test2dia ----------------------------------------------
+
+@pytest.mark.parametrize("coupling,smol", [(H.SMOL_ONLY, H.FD), (H.FULL, H.FD), (H.FULL, H.FV)])
+def test_gradient_free_energy_structure_factor(coupling, smol):
+    c = _paper(smol=smol, coupling=coupling, a=0.025, kappa=0.01, M=0.1)
+    print("S(q) plane case", c, flush=True)
+    Q = _qgrid(SHAPE)
+    s_th, absR, oz = _stationary(c, Q)
+    nsamp, every = 500, 200
+    S, _, _ = _run_spectra(c, _equilibrium_init(c, 32), 2000, nsamp, every)
+    ok = np.isfinite(s_th) & (s_th > 0)
+    ok.flat[0] = False
+    r = np.where(ok, S / np.where(ok, s_th, 1), np.nan)
+    ne = _n_eff(absR, nsamp, every)
+    # Modes that relax many times within the run (the slowest ones start in
+    # equilibrium and are only checked in the zone average).
+    rate = -np.log(np.where(ok, absR, 0.5))
+    fast = ok & (rate * nsamp * every > 50)
+    sig_fast = 1 / np.sqrt(ne[fast].sum() / 2)
+    mean_fast, mean_all = r[fast].mean(), np.nanmean(r)
+    L = SHAPE[0]
+    print("  modes relaxed > 50 times: %d of %d; mean S/S_exact %.4f (stat %.4f); all %.4f"
+          % (fast.sum(), ok.sum(), mean_fast, sig_fast, mean_all))
+    # Plane q_z = 0 (Figs. test2a, test2): shell averages in |n_xy|.
+    nz_, ny_, nx_ = np.meshgrid(*(np.fft.fftfreq(L, 1 / L),) * 3, indexing="ij")
+    plane = ok & (nz_ == 0) & fast
+    shell = np.rint(np.hypot(nx_, ny_)).astype(int)
+    print("  plane q_z = 0: |n|  S/S_exact  S/OZ  stat")
+    worst = 0.0
+    for n in range(1, 17):
+        sel = plane & (shell == n)
+        if not sel.any():
+            continue
+        a = r[sel].mean()
+        b = (S[sel] / oz[sel]).mean()
+        st = 1 / np.sqrt(ne[sel].sum() / 2)
+        worst = max(worst, abs(a - 1) / (st + 1e-12))
+        print("    %2d  %.4f  %.4f  %.4f" % (n, a, b, st))
+    # Fig. test2dia: the ER error along the diagonal.
+    ms = np.arange(2, L // 2)
+    diag = [np.array([_diag_indices(SHAPE, m, sg) for sg in DIAGS]) for m in ms]
+    rd = np.array([r.ravel()[d].mean() for d in diag])
+    sd = np.array([1 / np.sqrt(ne.ravel()[d].sum()) for d in diag])
+    er = np.array([(S.ravel()[d] / oz.ravel()[d]).mean() - 1 for d in diag])
+    print("  diagonal m: ER-1 " + " ".join("%+.3f" % e for e in er))
+    exact = coupling == H.SMOL_ONLY
+    assert abs(mean_fast - 1) < (max(5 * sig_fast, 0.003) if exact else 0.02)
+    assert abs(mean_all - 1) < 0.03
+    assert np.all(np.abs(rd - 1) < 5 * sd + (0.0 if exact else 0.04))
+    assert np.all(np.abs(er) < 5 * sd + 0.04)
+    if exact:
+        assert worst < 5
+
+
+# Fig. test3 -----------------------------------------------------------------
+
+@pytest.mark.parametrize("smol", [H.FD, H.FV])
+def test_dynamic_structure_factor(smol):
+    """S(q, tau)/S(q, 0) on the axis modes m = 2..8 against R(z)^tau of the
+    discrete scheme (Eq. strf with the lattice operators)."""
+    from paper_1104_0078_amd import lbl
+    c = _paper(smol=smol, coupling=H.SMOL_ONLY, a=0.065, kappa=0.04, M=0.095)
+    print("S(q,tau) case", c, flush=True)
+    every, nsamp = 10, 10000
+    L = SHAPE[0]
+    ms = np.arange(2, 9)
+    ser = np.zeros((nsamp, 3, len(ms)), complex)
+    t0 = time.perf_counter()
+    with lbl.Sim(H.lbl_params(c), _equilibrium_init(c, 33)) as sim:
+        sim.step(1000)
+        for i in range(nsamp):
+            sim.step(every)
+            ser[i] = sim.observe(lbl.LBL_OBS_PSIK_AXES)[:, ms]
+    print("  %d steps in %.1f s" % (1000 + nsamp * every, time.perf_counter() - t0), flush=True)
+    slopes = []
+    for j, m in enumerate(ms):
+        q = np.zeros(3)
+        q[0] = 2 * np.pi * m / L
+        z, _, _ = T.smol_z(q, c["lattice"], smol, c["M"], c["a"], c["kappa"])
+        R = T.rk_poly(z, 2)[0].real
+        tau_q = -1 / np.log(R)  # steps per e-fold; -> [M (-L)(A - K L)]^-1
+        nlag = int(1.5 * tau_q / every)
+        lags = np.arange(nlag + 1)
+        x = ser[:, :, j]
+        C = np.array([(x[k:] * np.conj(x[:nsamp - k])).real.mean() for k in lags])
+        C /= C[0]
+        expect = R ** (lags * every)
+        # Statistical bar of C(tau): independent samples ~ run / (2 tau_q) per axis.
+        bar = np.sqrt(2 * tau_q / (nsamp * every) / 3)
+        err = np.abs(C - expect).max()
+        sel = C > 0.25
+        slope = np.polyfit(lags[sel] * every / tau_q, np.log(C[sel]), 1)[0]
+        slopes.append(slope)
+        print("  m=%d tau(q)=%.0f steps: max|C - R^tau| %.3f (bar %.3f), slope %.3f"
+              % (m, tau_q, err, bar, slope), flush=True)
+        assert err < 4 * bar + 0.02
+    assert abs(np.mean(slopes) + 1) < 0.06
+
+
+# Fig. galinv ------------------------------------------------------------------
+
+@pytest.mark.parametrize("smol", [H.FD, H.FV])
+@pytest.mark.parametrize("mach", [0.08, 0.57])
+def test_galilean_invariance_diagonal_flow(smol, mach):
+    """A uniform flow along x = y (imposed; diffusion and advection only),
+    A = 0.025, K = 0.01, M = 0.1.  At Ma = 0.08 S(q) is the rest-frame
+    spectrum; at Ma = 0.57 it becomes anisotropic: the modes along the flow,
+    q ~ (1, 1, 0), are enhanced by up to ~50%, those across it, q ~ (1, -1, 0),
+    are not, as the exact spectrum of the scheme with the advection phase
+    predicts."""
+    U = mach * np.sqrt(1 / 3) / np.sqrt(2)
+    c = _paper(smol=smol, coupling=H.SMOL_ONLY, a=0.025, kappa=0.01, M=0.1,
+               u_imposed=(U, U, 0.0))
+    print("Galilean case Ma=%.2f" % mach, c, flush=True)
+    Q = _qgrid(SHAPE)
+    s_mv, absR, _ = _stationary(c, Q, U=c["u_imposed"])
+    s_rest, _, _ = _stationary(c, Q)
+    assert np.nanmax(np.where(np.isfinite(s_mv), absR, 0)) < 1
+    nsamp, every = 400, 200
+    S, _, _ = _run_spectra(c, _equilibrium_init(c, 34), 2000, nsamp, every)
+    ok = np.isfinite(s_mv) & (s_mv > 0) & np.isfinite(s_rest) & (s_rest > 0)
+    ok.flat[0] = False
+    rate = -np.log(np.where(ok, absR, 0.5))
+    fast = ok & (rate * nsamp * every > 50)
+    ne = _n_eff(absR, nsamp, every)
+    L = SHAPE[0]
+    ms = np.arange(2, 12)
+    # q = (m, m, 0) along the flow and (m, -m, 0) across it, one mode each
+    par = [np.array([_diag_indices(SHAPE, m, (1, 1, 0))]) for m in ms]
+    perp = [np.array([_diag_indices(SHAPE, m, (1, -1, 0))]) for m in ms]
+    flat = S.ravel()
+
+    def row(idx, ref):
+        return (np.array([flat[i].mean() / ref.ravel()[i].mean() for i in idx]),
+                np.array([1 / np.sqrt(ne.ravel()[i].sum()) for i in idx]))
+    par_exact, spar = row(par, s_mv)
+    par_rest, _ = row(par, s_rest)
+    perp_rest, sperp = row(perp, s_rest)
+    pred = np.array([s_mv.ravel()[i].mean() / s_rest.ravel()[i].mean() for i in par])
+    print("  along the flow (m,m,0): S/S_rest " + " ".join("%.3f" % v for v in par_rest))
+    print("        predicted             " + " ".join("%.3f" % v for v in pred))
+    print("  across the flow (m,-m,0): S/S_rest " + " ".join("%.3f" % v for v in perp_rest))
+    r_fast = (S[fast] / s_mv[fast]).mean()
+    print("  zone mean S/S_exact (relaxed modes) %.4f" % r_fast, flush=True)
+    assert abs(r_fast - 1) < 0.01
+    assert np.all(np.abs(par_exact - 1) < 5 * spar)
+    assert np.all(np.abs(perp_rest - 1) < 5 * sperp)
+    if mach < 0.1:
+        assert np.all(np.abs(par_rest - 1) < 5 * spar)
+    else:
+        # the anisotropy of Fig. galinv (b), by the predicted amount
+        assert pred.max() > 1.3
+        assert np.abs(par_rest - pred).max() < 5 * spar.max() * pred.max()
+        assert par_rest.max() > 1.2
+
+
+# Fig. tanh --------------------------------------------------------------------
+
+def _discrete_planar_profile(a, b, kappa, psi_start):
+    """Stationary profile of the lattice free energy for a field that varies
+    along one axis only: a psi + b psi^3 - kappa (psi_{j+1} - 2 psi_j +
+    psi_{j-1}) = 0 (the 2-D Shinozaki-Oono Laplacian reduces to the 1-D
+    three-point one on such a field), by Newton's method from psi_start."""
+    n = psi_start.size
+    lap = -2 * np.eye(n) + np.roll(np.eye(n), 1, axis=1) + np.roll(np.eye(n), -1, axis=1)
+    psi = psi_start.astype(float).copy()
+    for _ in range(60):
+        F = a * psi + b * psi ** 3 - kappa * lap @ psi
+        J = np.diag(a + 3 * b * psi ** 2) - kappa * lap
+        psi -= np.linalg.solve(J, F)
+    assert np.abs(a * psi + b * psi ** 3 - kappa * lap @ psi).max() < 1e-14
+    return psi
+
+
+def _fit_tanh(ys, vals, centre, widths):
+    best = None
+    for y0 in np.linspace(centre - 3, centre + 3, 601):
+        sel = np.abs(ys - y0) < 6
+        for w in widths:
+            res = vals[sel] - np.tanh((ys[sel] - y0) / w)
+            e = (res ** 2).sum()
+            if best is None or e < best[0]:
+                best = (e, y0, w, np.abs(res).max())
+    return best[1:]
+
+
+@pytest.mark.parametrize("smol", [H.FD, H.FV])
+def test_mean_interface_profile(smol):
+    """Two planar interfaces on a 64 x 64 D2Q9 lattice from a sharp initial
+    profile (psi = +-1), -A = B = 0.025, K = 0.01, M = 0.1, kT = 1/3000.  After
+    equilibration the time-averaged profile across the interfaces has the
+    tanh shape of Eq. (tanh), psi_eq = sqrt(-A/B) = 1 in the bulk.
+
+    Its width: Eq. (intthick) gives l = sqrt(-2K/A) = 0.894 lattice spacings,
+    below one site, where the stationary profile of the lattice free energy
+    is sharper than the continuum one (psi(+-1/2) = +-0.631 against the
+    tanh's +-0.507; fitted width 0.685).  The mean profile is checked against
+    that discrete profile, thermal fluctuations broadening it only slightly,
+    and its fitted width must lie between the discrete one and l."""
+    from paper_1104_0078_amd import lbl
+    nx = ny = 64
+    a, b, kappa = -0.025, 0.025, 0.01
+    c = H.config(lattice=H.D2Q9, smol=smol, shape=(nx, ny, 1), a=a, b=b, kappa=kappa, M=0.1,
+                 kT=KT, eta=ETA, rho=1.0, seed=2012)
+    N = nx * ny
+    yrow = np.arange(ny)
+    sharp = np.where((yrow >= ny // 4) & (yrow < 3 * ny // 4), 1.0, -1.0)
+    psi0 = np.repeat(sharp, nx)
+    _, wts = O.velocities(H.D2Q9)
+    f0 = np.repeat(wts[:, None], N, axis=1)
+    ini = lbl.make_init(kind=lbl.LBL_INIT_USER, f0=f0, psi0=psi0)
+    l = np.sqrt(-2 * kappa / a)
+    disc = _discrete_planar_profile(a, b, kappa, sharp)
+    prof = np.zeros(ny)
+    centres = []
+    nsamp, every = 2000, 100
+    t0 = time.perf_counter()
+    with lbl.Sim(H.lbl_params(c), ini) as sim:
+        sim.step(100000)
+        for _ in range(nsamp):
+            sim.step(every)
+            p = sim.observe(lbl.LBL_OBS_PSI).reshape(ny, nx).mean(1)
+            prof += p
+            # the rising interface: zero crossing between the last negative
+            # site below y = ny/2 and its successor
+            lo = 4 + np.argmax(p[4:ny // 2] >= 0) - 1
+            centres.append(lo + p[lo] / (p[lo] - p[lo + 1]))
+    print("  %d steps in %.1f s" % (100000 + nsamp * every, time.perf_counter() - t0), flush=True)
+    prof /= nsamp
+    centres = np.array(centres)
+    yy = np.arange(ny, dtype=float)
+    widths = np.linspace(0.5 * l, 1.6 * l, 221)
+    # The rising interface near ny/4 and the mirror image (y -> ny - 1 - y)
+    # of the falling one near 3 ny/4.
+    halves = ((yy[:ny // 2], prof[:ny // 2]), (ny - 1 - yy[ny // 2:], prof[ny // 2:]))
+    fits = [_fit_tanh(ys, v, ny / 4, widths) for ys, v in halves]
+    _, w_disc, _ = _fit_tanh(yy[:ny // 2], disc[:ny // 2], ny / 4, widths)
+    bulk = 0.5 * (prof[24:40].mean() - np.concatenate([prof[56:], prof[:8]]).mean())
+    dev = np.abs(prof - disc).max()
+    print("  mean profile near y = 15.5: " + " ".join("%.4f" % v for v in prof[12:20]))
+    print("  discrete stationary profile: " + " ".join("%.4f" % v for v in disc[12:20]))
+    for (y0, w, rmax) in fits:
+        print("  interface y0 %.3f: fitted width %.3f (discrete profile %.3f, l = %.3f), "
+              "max residual from tanh %.4f" % (y0, w, w_disc, l, rmax))
+    print("  rising-interface centre: mean %.3f, std over samples %.3f; bulk psi %.4f; "
+          "max |mean - discrete| %.4f" % (centres.mean(), centres.std(), bulk, dev), flush=True)
+    assert abs(bulk - 1) < 0.02
+    assert dev < 0.05
+    for (y0, w, rmax) in fits:
+        assert w_disc - 0.01 < w < l
+        assert rmax < 0.05
