@@ -192,6 +192,44 @@ __device__ __forceinline__ S chem_pot(const Coef<S>& c, At&& at) {
   return c.a * p + c.b * p * p * p - c.kappa * lap_so<S, D>(at);
 }
 
+// The 3-D Shinozaki-Oono Laplacian split by planes for z-marching kernels: with
+// the centre value c, the 4-face sum f and the 4-corner sum k of each plane,
+// L_SO phi = (6 F + 3 E + C - 80 phi)/22 where F = f_z + c_{z-1} + c_{z+1},
+// E = k_z + f_{z-1} + f_{z+1}, C = k_{z-1} + k_{z+1} (face, edge and corner
+// neighbours).  A thread pushes the sums of each new plane (9 LDS reads) and
+// evaluates mu at the middle one of the last three, instead of 27 reads.
+template <typename S>
+struct SoPlanes {
+  S c[3], f[3], k[3];  // planes z-1, z, z+1 (slot 2 newest)
+  __device__ __forceinline__ SoPlanes() {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) c[r] = f[r] = k[r] = S(0);
+  }
+  // P points at the centre of the new plane in an LDS row layout of width W.
+  template <int W>
+  __device__ __forceinline__ void push(const S* P) {
+    c[2] = P[0];
+    f[2] = (P[-1] + P[1]) + (P[-W] + P[W]);
+    k[2] = (P[-W - 1] + P[-W + 1]) + (P[W - 1] + P[W + 1]);
+  }
+  __device__ __forceinline__ S mu(const Coef<S>& co) const {
+    const S ph = c[1];
+    const S F = f[1] + (c[0] + c[2]);
+    const S E = k[1] + (f[0] + f[2]);
+    const S C = k[0] + k[2];
+    const S lap = S(6.0 / 22.0) * F + S(3.0 / 22.0) * E + S(1.0 / 22.0) * C - S(80.0 / 22.0) * ph;
+    return co.a * ph + co.b * ph * ph * ph - co.kappa * lap;
+  }
+  __device__ __forceinline__ void roll() {
+    c[0] = c[1];
+    c[1] = c[2];
+    f[0] = f[1];
+    f[1] = f[2];
+    k[0] = k[1];
+    k[1] = k[2];
+  }
+};
+
 template <typename S, int Q>
 __global__ __launch_bounds__(kBX* kBY) void k_mu(Geom g, Coef<S> c, const S* __restrict__ phi,
                                                  S* __restrict__ mu) {
@@ -454,44 +492,41 @@ struct PrepArgs {
   S* mu;           // mu(psi^n), or nullptr
 };
 
-// psi ring for mu: region with halo 1, 4 planes.
-template <typename S, int D>
-struct PsiRing {
+// One plane of psi for mu: region with halo 1.  The 3-D kernels carry the
+// plane sums of the planes below and above in registers (SoPlanes).
+template <typename S>
+struct PsiPlane {
   static constexpr int W = kTX + 2, H = kTY + 2, RS = W * H;
-  static constexpr int NRING = D == 3 ? 4 : 1;
-  S v[NRING][RS];
+  S v[RS];
 };
 
-template <typename S, int D>
-__device__ __forceinline__ void prep_load_psi(PsiRing<S, D>& r, const PrepArgs<S>& a, int p,
+template <typename S>
+__device__ __forceinline__ void prep_load_psi(PsiPlane<S>& r, const PrepArgs<S>& a, int p,
                                               int x0, int y0, bool near, int tid) {
-  using R = PsiRing<S, D>;
+  using R = PsiPlane<S>;
   const Geom& g = a.g;
-  const int slot = ring(p, R::NRING), pz = wrap_any(p, g.nz);
+  const int pz = wrap_any(p, g.nz);
   for (int e = tid; e < R::RS; e += kTX * kTY) {
     const int i = e % R::W, j = e / R::W;
     const int gx = wrap_r(x0 - 1 + i, g.nx, near), gy = wrap_r(y0 - 1 + j, g.ny, near);
-    r.v[slot][e] = a.psi[gx + g.nx * (gy + g.ny * pz)];
+    r.v[e] = a.psi[gx + g.nx * (gy + g.ny * pz)];
   }
 }
 
-template <typename S, int D>
-__device__ __forceinline__ void prep_mu(const PsiRing<S, D>& r, const PrepArgs<S>& a, int t,
-                                        int x0, int y0, int tx, int ty) {
-  using R = PsiRing<S, D>;
-  const Geom& g = a.g;
-  const int x = x0 + tx, y = y0 + ty;
-  if (x >= g.nx || y >= g.ny) return;
-  a.mu[x + g.nx * (y + g.ny * t)] = chem_pot<S, D>(a.c, [&](int dx, int dy, int dz) {
-    return r.v[ring(t + dz, R::NRING)][(tx + 1 + dx) + R::W * (ty + 1 + dy)];
+// 2-D mu at the tile point (tx, ty).
+template <typename S>
+__device__ __forceinline__ S prep_mu2(const PsiPlane<S>& r, const Coef<S>& c, int tx, int ty) {
+  using R = PsiPlane<S>;
+  return chem_pot<S, 2>(c, [&](int dx, int dy, int) {
+    return r.v[(tx + 1 + dx) + R::W * (ty + 1 + dy)];
   });
 }
 
 // FV noise (Eqs. fvdiff, noiseflux, fdt_orderpara): node noise xi_a = amp z_a
 // and N = Gamma . xi with Gamma = (1/c_s^2) sum_i w_i c_i.  One plane of xi
 // (halo 1) lives in LDS at a time; each plane is folded into register partial
-// sums of N for the planes below, at and above it.  psi has a three-plane ring
-// for mu.
+// sums of N for the planes below, at and above it.  mu(psi) comes from one
+// psi plane and the plane sums of SoPlanes.
 template <typename S, int Q>
 __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int by, int bz) {
   using L = Lat<Q>;
@@ -499,7 +534,7 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
   constexpr int W = kTX + 2, H = kTY + 2, RS = W * H;
   constexpr int NT = kTX * kTY;
   __shared__ S xi[D][RS];
-  __shared__ S spsi[D == 3 ? 3 : 1][RS];
+  __shared__ PsiPlane<S> spsi;
   const Geom& g = a.g;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
   const int x0 = bx * kTX, y0 = by * kTY;
@@ -522,20 +557,7 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
       for (int c = 0; c < D; ++c) xi[c][e] = zz[c];
     }
   };
-  auto load_psi = [&](int p) {
-    const int slot = ring(p, D == 3 ? 3 : 1), pz = wrap_any(p, g.nz);
-    for (int e = tid; e < RS; e += NT) {
-      const int i = e % W, j = e / W;
-      const int gx = wrap_r(x0 - 1 + i, g.nx, near), gy = wrap_r(y0 - 1 + j, g.ny, near);
-      spsi[slot][e] = a.psi[gx + g.nx * (gy + g.ny * pz)];
-    }
-  };
-  auto mu_at = [&](int t) {
-    if (!live) return;
-    a.mu[x + g.nx * (y + g.ny * t)] = chem_pot<S, D>(a.c, [&](int dx, int dy, int dz) {
-      return spsi[ring(t + dz, D == 3 ? 3 : 1)][(tx + 1 + dx) + W * (ty + 1 + dy)];
-    });
-  };
+  SoPlanes<S> so;  // psi planes p-2, p-1, p (3-D)
   S npart[3] = {0, 0, 0};  // N(p-1), N(p), N(p+1)
   auto fold = [&]() {
 #pragma unroll
@@ -550,18 +572,18 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
   };
   if constexpr (D == 2) {
     if (a.noise) gen(0);
-    if (a.mu) load_psi(0);
+    if (a.mu) prep_load_psi(spsi, a, 0, x0, y0, near, tid);
     __syncthreads();
     if (a.noise) {
       fold();
       if (live) a.noise[x + g.nx * y] = S(3) * a.amp * npart[1];
     }
-    if (a.mu) mu_at(0);
+    if (a.mu && live) a.mu[x + g.nx * y] = prep_mu2(spsi, a.c, tx, ty);
   } else {
     // Iteration p: xi(p) and psi(p) staged; N(p-1) and mu(p-1) emitted.
     for (int p = z0 - 1; p <= z1; ++p) {
       if (a.noise) gen(p);
-      if (a.mu) load_psi(p);
+      if (a.mu) prep_load_psi(spsi, a, p, x0, y0, near, tid);
       __syncthreads();
       const bool emit = p - 1 >= z0 && p - 1 < z1;
       if (a.noise) {
@@ -571,7 +593,11 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
         npart[1] = npart[2];
         npart[2] = 0;
       }
-      if (a.mu && emit) mu_at(p - 1);
+      if (a.mu && live) {
+        so.template push<W>(spsi.v + (tx + 1) + W * (ty + 1));
+        if (emit) a.mu[x + g.nx * (y + g.ny * (p - 1))] = so.mu(a.c);
+        so.roll();
+      }
       __syncthreads();
     }
   }
@@ -595,7 +621,8 @@ __device__ __forceinline__ void prep_fd_body(const PrepArgs<S>& a, int bx, int b
   constexpr int NB = (NL + 3) / 4;
   constexpr int W = kTX + 1, H = kTY + 2, RS = W * H;  // x in [x0-1, x0+kTX), y in [y0-1, y0+kTY]
   __shared__ S zeta[NL][RS];
-  __shared__ PsiRing<S, D> pr;
+  __shared__ PsiPlane<S> pr;
+  SoPlanes<S> so;  // psi planes p-2, p-1, p (3-D)
   const Geom& g = a.g;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
   const int x0 = bx * kTX, y0 = by * kTY;
@@ -628,10 +655,17 @@ __device__ __forceinline__ void prep_fd_body(const PrepArgs<S>& a, int bx, int b
         }
       }
     }
-    if (a.mu) prep_load_psi<S, D>(pr, a, p, x0, y0, near, tid);
+    if (a.mu) prep_load_psi(pr, a, p, x0, y0, near, tid);
     __syncthreads();
-    if (a.mu && (D == 2 || (p - 1 >= z0 && p - 1 < z1)))
-      prep_mu<S, D>(pr, a, D == 2 ? 0 : p - 1, x0, y0, tx, ty);
+    if (a.mu && live) {
+      if constexpr (D == 2) {
+        a.mu[x + g.nx * y] = prep_mu2(pr, a.c, tx, ty);
+      } else {
+        so.template push<PsiPlane<S>::W>(pr.v + (tx + 1) + PsiPlane<S>::W * (ty + 1));
+        if (p - 1 >= z0 && p - 1 < z1) a.mu[x + g.nx * (y + g.ny * (p - 1))] = so.mu(a.c);
+        so.roll();
+      }
+    }
     if (live && a.noise) {
       const int own = (tx + 1) + W * (ty + 1);
 #pragma unroll
@@ -751,36 +785,108 @@ __device__ __forceinline__ void combine_in(const StageArgs<S>& a, int s, S G, co
 }
 
 // FV stage (Sec. V.B, Eq. fvft): G = Gamma . J + N with the node flux
-// J = -u phi + M Gamma mu(phi).  z-marching with LDS rings for phi (halo 3,
-// three planes) and mu (halo 2, three planes) and one plane of J (halo 1):
-// each J plane is folded into register partial sums of G for the planes
-// below, at and above it, so J never needs a ring.  The next phi plane and the
-// site values of the current plane are fetched one step ahead, the velocity
-// at the J points once mu is done (fewer registers live during mu).
+// J = -u phi + M Gamma mu(phi).  2-D: one plane, phi (halo 3), mu (halo 2)
+// and J (halo 1) in LDS, one phase each.
 template <typename S, int Q>
-__device__ __forceinline__ void stage_fv_body(const StageArgs<S>& a, int bx, int by, int bz) {
+__device__ __forceinline__ void stage_fv2_body(const StageArgs<S>& a, int bx, int by) {
   using L = Lat<Q>;
   constexpr int D = L::D;
   constexpr int WP = kTX + 6, HP = kTY + 6;
   constexpr int WM = kTX + 4, HM = kTY + 4;
   constexpr int WJ = kTX + 2, HJ = kTY + 2;
-  constexpr int NR = D == 3 ? 3 : 1;
   constexpr int NT = kTX * kTY;
-  constexpr int NPF = (WP * HP + NT - 1) / NT;  // phi elements per thread
-  constexpr int NJ = (WJ * HJ + NT - 1) / NT;   // J elements per thread
-  __shared__ S sphi[NR][WP * HP];
-  __shared__ S smu[NR][WM * HM];
+  __shared__ S sphi[WP * HP];
+  __shared__ S smu[WM * HM];
   __shared__ S sJ[D][WJ * HJ];
   const Geom& g = a.g;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
   const int x0 = bx * kTX, y0 = by * kTY;
   const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
-  const int z0 = D == 3 ? bz * a.zc : 0;
-  const int z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
   const int x = x0 + tx, y = y0 + ty;
   const bool live = x < g.nx && y < g.ny;
+  SiteIn<S> sv{};
+  if (live) sv = fetch_site(a, x + g.nx * y);
+  for (int e = tid; e < WP * HP; e += NT) {
+    const int i = e % WP, j = e / WP;
+    sphi[e] = a.phi[wrap_r(x0 - 3 + i, g.nx, near) + g.nx * wrap_r(y0 - 3 + j, g.ny, near)];
+  }
+  __syncthreads();
+  for (int e = tid; e < WM * HM; e += NT) {
+    const int i = e % WM, j = e / WM;
+    smu[e] = chem_pot<S, D>(a.c, [&](int dx, int dy, int) {
+      return sphi[(i + 1 + dx) + WP * (j + 1 + dy)];
+    });
+  }
+  __syncthreads();
+  for (int e = tid; e < WJ * HJ; e += NT) {
+    const int i = e % WJ, j = e / WJ;
+    const int site = wrap_r(x0 - 1 + i, g.nx, near) + g.nx * wrap_r(y0 - 1 + j, g.ny, near);
+    S gm[2] = {0, 0};
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+      const S t = S(L::w[q]) * smu[(i + 1 + L::cx[q]) + WM * (j + 1 + L::cy[q])];
+      if (L::cx[q]) gm[0] += L::cx[q] * t;
+      if (L::cy[q]) gm[1] += L::cy[q] * t;
+    }
+    const S ph = sphi[(i + 2) + WP * (j + 2)];
+#pragma unroll
+    for (int c = 0; c < D; ++c) sJ[c][e] = -uval(a, c, site) * ph + a.c.M * (S(3) * gm[c]);
+  }
+  __syncthreads();
+  S G = 0;
+#pragma unroll
+  for (int q = 1; q < Q; ++q) {
+    const int e = (tx + 1 + L::cx[q]) + WJ * (ty + 1 + L::cy[q]);
+    S v = 0;
+    if (L::cx[q]) v += L::cx[q] * sJ[0][e];
+    if (L::cy[q]) v += L::cy[q] * sJ[1][e];
+    G += S(L::w[q]) * v;
+  }
+  if (live) combine_in(a, x + g.nx * y, S(3) * G + sv.noise, sv);
+}
 
-  // phi plane p -> registers (issued one iteration before it is stored).
+// 3-D: z-marching with one LDS plane of phi (halo 3), a three-plane ring of mu
+// (halo 2) and one plane of J (halo 1).  mu comes from per-plane sums of phi
+// carried in registers (SoPlanes), so each phi value in LDS is read 9 times
+// instead of 27.
+// Gamma . J of the G points is folded plane by plane into register partial
+// sums for the planes below, at and above (a tap with z-velocity cz reaches
+// the plane z - cz).  A thread owns fixed points of the mu region (index
+// e = tid + k NT in a (kTX+4) x (kTY+4) layout; J lives on its inner ring) and
+// one G point; iteration p loads phi(p) and emits mu(p-1), J(p-2), G(p-3).
+template <typename S, int Q>
+__device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, int by, int bz) {
+  using L = Lat<Q>;
+  constexpr int D = 3;
+  constexpr int WP = kTX + 6, HP = kTY + 6;  // phi region
+  constexpr int WM = kTX + 4, HM = kTY + 4;  // mu region; J on its inner ring
+  constexpr int NT = kTX * kTY;
+  constexpr int NPF = (WP * HP + NT - 1) / NT;
+  constexpr int NE = (WM * HM + NT - 1) / NT;
+  __shared__ S sphi[WP * HP];
+  __shared__ S smu[3][WM * HM];
+  __shared__ S sJ[D][WM * HM];
+  const Geom& g = a.g;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
+  const int x0 = bx * kTX, y0 = by * kTY;
+  const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
+  const int z0 = bz * a.zc;
+  const int z1 = min(z0 + a.zc, g.nz);
+  const int x = x0 + tx, y = y0 + ty;
+  const bool live = x < g.nx && y < g.ny;
+  const int plane = g.nx * g.ny;
+
+  int pxy[NE];
+  bool pon[NE], jon[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    const int e = tid + k * NT;
+    const int i = e % WM, j = e / WM;
+    pon[k] = e < WM * HM;
+    jon[k] = pon[k] && i >= 1 && i < WM - 1 && j >= 1 && j < HM - 1;
+    pxy[k] = wrap_r(x0 - 2 + i, g.nx, near) + g.nx * wrap_r(y0 - 2 + j, g.ny, near);
+  }
+
   S pf[NPF];
   auto fetch_phi = [&](int p) {
     const int pz = wrap_any(p, g.nz);
@@ -794,113 +900,92 @@ __device__ __forceinline__ void stage_fv_body(const StageArgs<S>& a, int bx, int
       }
     }
   };
-  auto store_phi = [&](int p) {
-    const int slot = ring(p, NR);
+
+  SoPlanes<S> so[NE];                  // phi planes p-2, p-1, p
+  S uv[NE][D];
+  S gpart[3] = {0, 0, 0};              // G planes p-3, p-2, p-1
 #pragma unroll
-    for (int k = 0; k < NPF; ++k) {
-      const int e = tid + k * NT;
-      if (e < WP * HP) sphi[slot][e] = pf[k];
+  for (int k = 0; k < NE; ++k)
+#pragma unroll
+    for (int c = 0; c < D; ++c) uv[k][c] = 0;
+
+  fetch_phi(z0 - 3);
+  for (int p = z0 - 3; p <= z1 + 2; ++p) {
+    const bool do_mu = p >= z0 - 1, do_J = p >= z0 + 1, do_G = p >= z0 + 3 && live;
+#pragma unroll
+    for (int k = 0; k < NPF; ++k)
+      if (tid + k * NT < WP * HP) sphi[tid + k * NT] = pf[k];
+    if (p < z1 + 2) fetch_phi(p + 1);
+    const int s = x + g.nx * (y + g.ny * (p - 3));
+    SiteIn<S> sv{};
+    if (do_G) sv = fetch_site(a, s);
+    if (do_J) {
+      const int zo = plane * wrap_any(p - 2, g.nz);
+#pragma unroll
+      for (int k = 0; k < NE; ++k)
+        if (jon[k]) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) uv[k][c] = uval(a, c, pxy[k] + zo);
+        }
     }
-  };
-  // Advecting velocity at the J elements of plane p.
-  S uv[NJ][D];
-  auto fetch_u = [&](int p) {
-    const int pz = wrap_any(p, g.nz);
+    __syncthreads();
+    // Plane sums of phi(p); mu(p-1) from planes p-2, p-1, p.
+    const int mslot = ring(p - 1, 3);
 #pragma unroll
-    for (int k = 0; k < NJ; ++k) {
+    for (int k = 0; k < NE; ++k) {
+      if (!pon[k]) continue;
       const int e = tid + k * NT;
-      if (e < WJ * HJ) {
-        const int i = e % WJ, j = e / WJ;
-        const int gx = wrap_r(x0 - 1 + i, g.nx, near), gy = wrap_r(y0 - 1 + j, g.ny, near);
-        const int site = gx + g.nx * (gy + g.ny * pz);
-#pragma unroll
-        for (int c = 0; c < D; ++c) uv[k][c] = uval(a, c, site);
-      }
+      so[k].template push<WP>(sphi + (e % WM + 1) + WP * (e / WM + 1));
+      if (do_mu) smu[mslot][e] = so[k].mu(a.c);
     }
-  };
-  auto comp_mu = [&](int p) {
-    const int slot = ring(p, NR);
-    for (int e = tid; e < WM * HM; e += NT) {
-      const int i = e % WM, j = e / WM;
-      smu[slot][e] = chem_pot<S, D>(a.c, [&](int dx, int dy, int dz) {
-        return sphi[ring(p + dz, NR)][(i + 1 + dx) + WP * (j + 1 + dy)];
-      });
-    }
-  };
-  auto comp_J = [&](int p) {
-    const int slot = ring(p, NR);
+    __syncthreads();
+    // J(p-2) from mu(p-3), mu(p-2), mu(p-1).
+    if (do_J) {
 #pragma unroll
-    for (int k = 0; k < NJ; ++k) {
-      const int e = tid + k * NT;
-      if (e < WJ * HJ) {
-        const int i = e % WJ, j = e / WJ;
+      for (int k = 0; k < NE; ++k) {
+        if (!jon[k]) continue;
+        const int e = tid + k * NT;
         S gm[3] = {0, 0, 0};
 #pragma unroll
         for (int q = 1; q < Q; ++q) {
-          const S t = S(L::w[q]) * smu[ring(p + L::cz[q], NR)][(i + 1 + L::cx[q]) + WM * (j + 1 + L::cy[q])];
+          const S t = S(L::w[q]) * smu[ring(p - 2 + L::cz[q], 3)][e + L::cx[q] + WM * L::cy[q]];
           if (L::cx[q]) gm[0] += L::cx[q] * t;
           if (L::cy[q]) gm[1] += L::cy[q] * t;
           if (L::cz[q]) gm[2] += L::cz[q] * t;
         }
-        const S ph = sphi[slot][(i + 2) + WP * (j + 2)];
+        const S ph = so[k].c[0];  // phi(p-2)
 #pragma unroll
         for (int c = 0; c < D; ++c) sJ[c][e] = -uv[k][c] * ph + a.c.M * (S(3) * gm[c]);
       }
     }
-  };
-  // Fold J of one plane into the partial sums of G for the planes at offsets
-  // -1, 0, +1 from it (a tap with z-velocity cz reaches G at plane p - cz).
-  S gpart[3] = {0, 0, 0};  // G(p-1), G(p), G(p+1)
-  auto fold_J = [&]() {
 #pragma unroll
-    for (int q = 1; q < Q; ++q) {
-      const int e = (tx + 1 + L::cx[q]) + WJ * (ty + 1 + L::cy[q]);
-      S v = 0;
-      if (L::cx[q]) v += L::cx[q] * sJ[0][e];
-      if (L::cy[q]) v += L::cy[q] * sJ[1][e];
-      if (D == 3 && L::cz[q]) v += L::cz[q] * sJ[D - 1][e];
-      gpart[1 - L::cz[q]] += S(L::w[q]) * v;
-    }
-  };
-
-  if constexpr (D == 2) {
-    fetch_phi(0);
-    fetch_u(0);
-    SiteIn<S> sv{};
-    if (live) sv = fetch_site(a, x + g.nx * y);
-    store_phi(0);
+    for (int k = 0; k < NE; ++k) so[k].roll();
     __syncthreads();
-    comp_mu(0);
-    __syncthreads();
-    comp_J(0);
-    __syncthreads();
-    fold_J();
-    if (live) combine_in(a, x + g.nx * y, S(3) * gpart[1] + sv.noise, sv);
-  } else {
-    fetch_phi(z0 - 3);
-    for (int t = z0 - 6; t < z1; ++t) {
-      // Iteration t: phi(t+3) stored, mu(t+2), J(t+1) folded, G(t) emitted.
-      store_phi(t + 3);
-      if (t + 1 < z1) fetch_phi(t + 4);
-      const bool do_mu = t + 2 >= z0 - 2, do_J = t + 1 >= z0 - 1, do_G = t >= z0 && live;
-      const int s = x + g.nx * (y + g.ny * t);
-      SiteIn<S> sv{};
-      if (do_G) sv = fetch_site(a, s);
-      __syncthreads();
-      if (do_mu) comp_mu(t + 2);
-      if (do_J) fetch_u(t + 1);
-      __syncthreads();
-      if (do_J) comp_J(t + 1);
-      __syncthreads();
-      if (do_J) {
-        fold_J();  // J(t+1) -> G(t), G(t+1), G(t+2)
-        if (do_G) combine_in(a, s, S(3) * gpart[0] + sv.noise, sv);
-        gpart[0] = gpart[1];
-        gpart[1] = gpart[2];
-        gpart[2] = 0;
+    // Gamma . J(p-2) into the G partials; G(p-3) complete.
+    if (do_J) {
+#pragma unroll
+      for (int q = 1; q < Q; ++q) {
+        const int e = (tx + 2 + L::cx[q]) + WM * (ty + 2 + L::cy[q]);
+        S v = 0;
+        if (L::cx[q]) v += L::cx[q] * sJ[0][e];
+        if (L::cy[q]) v += L::cy[q] * sJ[1][e];
+        if (L::cz[q]) v += L::cz[q] * sJ[2][e];
+        gpart[1 - L::cz[q]] += S(L::w[q]) * v;
       }
+      if (do_G) combine_in(a, s, S(3) * gpart[0] + sv.noise, sv);
+      gpart[0] = gpart[1];
+      gpart[1] = gpart[2];
+      gpart[2] = 0;
     }
   }
+}
+
+template <typename S, int Q>
+__device__ __forceinline__ void stage_fv_body(const StageArgs<S>& a, int bx, int by, int bz) {
+  if constexpr (Lat<Q>::D == 3)
+    stage_fv3_body<S, Q>(a, bx, by, bz);
+  else
+    stage_fv2_body<S, Q>(a, bx, by);
 }
 
 template <typename S, int Q>
