@@ -224,13 +224,15 @@ int lbl_timing_read(lbl_sim *sim, lbl_kernel_time *out, int max_entries, int *n_
  * xcd_swizzle, bit 0: the LB blocks, bit 1: the SMOL tiles are ordered so
  * that each of the 8 XCDs sweeps one contiguous eighth of them (reads across
  * block edges then hit the same L2); zc: planes per block of the z-marching SMOL kernels of a 3-D
- * lattice (0 keeps the current value, larger than nz is clamped); overlap:
+ * lattice, stage and preparation kernels alike (0 keeps the current values,
+ * larger than nz is clamped; lbl_get_schedule reports the stage's); overlap:
  * 1 runs the first Runge-Kutta stage on a second stream of the library's
  * own (default priority), concurrently with the velocity pass of the
  * streamed populations that only the later stages read (full coupling, 2 or
  * 4 stages); 0 runs everything on the simulation's stream.  Default: the
- * widest width up to 256 that fits nx, no swizzle, zc for >= 2048 tiles,
- * overlap 0.  Errors: LBL_E_INVAL (NULL, unsupported width, zc < 0,
+ * widest width up to 256 that fits nx, no swizzle, zc per kernel from its
+ * occupancy (the stage's blocks fill the device's resident slots in one
+ * round, the preparation kernel's in two; at least 8 planes), overlap 0.  Errors: LBL_E_INVAL (NULL, unsupported width, zc < 0,
  * overlap not 0 or 1). */
 typedef struct lbl_schedule {
   int32_t lb_width;

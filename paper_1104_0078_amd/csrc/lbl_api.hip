@@ -62,7 +62,8 @@ struct lbl_sim {
   int64_t step = 0;
   int64_t nsamples = 0;
   uint32_t k0 = 0, k1 = 0;
-  int zc = 1;  // planes per block of the z-marching kernels
+  int zc = 1;       // planes per block of the z-marching SMOL stage kernels
+  int zc_prep = 1;  // planes per block of the z-marching preparation kernel
   int lb_lw = 6;       // log2 of the LB block width along x
   int lb_swizzle = 0;  // XCD-contiguous block order: bit 0 LB kernels, bit 1 tile kernels
   int overlap = 0;     // first RK stage on `aux`, concurrent with the velocity pass
@@ -296,7 +297,46 @@ struct Impl {
     return hip_check(s, hipGetLastError(), what);
   }
 
+  // Default z-chunks of the tiled SMOL kernels (3-D): as many chunks as fill
+  // the device's resident block slots of each kernel in whole rounds, one
+  // round for the stage kernel, two for the preparation kernel (measured best
+  // on 256^3), and never fewer than 8 planes per chunk.
+  static int default_chunks(lbl_sim* s) {
+    if (Lat<Q>::D != 3) return LBL_OK;
+    int cus = 0, nb_stage = 0, nb_prep = 0;
+    int rc = hip_check(s, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                                s->device), "CU count");
+    if (!rc) {
+      if (SMOL == kFV) {
+        rc = hip_check(s, hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb_stage, k_stage_fv<S, Q>,
+                                                                       kTX * kTY, 0), "occupancy");
+        if (!rc)
+          rc = hip_check(s, hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb_prep, k_prep_fv<S, Q>,
+                                                                         kTX * kTY, 0), "occupancy");
+      } else {
+        rc = hip_check(s, hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb_stage, k_stage_fd<S, Q>,
+                                                                       kTX * kTY, 0), "occupancy");
+        if (!rc)
+          rc = hip_check(s, hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb_prep, k_prep_fd<S, Q>,
+                                                                         kTX * kTY, 0), "occupancy");
+      }
+    }
+    if (rc) return rc;
+    const int nz = s->p.nz;
+    const long bxy = static_cast<long>((s->p.nx + kTX - 1) / kTX) * ((s->p.ny + kTY - 1) / kTY);
+    auto pick = [&](int per_cu, int rounds) {
+      const long slots = static_cast<long>(std::max(1, per_cu)) * std::max(1, cus) * rounds;
+      const long chunks = std::max(1L, (slots + bxy - 1) / bxy);
+      const int zc = static_cast<int>((nz + chunks - 1) / chunks);
+      return std::min(nz, std::max(8, zc));
+    };
+    s->zc = pick(nb_stage, 1);
+    s->zc_prep = pick(nb_prep, 2);
+    return LBL_OK;
+  }
+
   static int init(lbl_sim* s, const lbl_init* in) {
+    if (int rc = default_chunks(s)) return rc;
     const Geom g = geom(s);
     const int grid = grid_for(s->N);
     S* f = static_cast<S*>(s->f[0]);
@@ -420,7 +460,10 @@ struct Impl {
     const TileMap tm = make_tile_map(s->p.nx, s->p.ny,
                                      Lat<Q>::D == 3 ? (s->p.nz + s->zc - 1) / s->zc : 1,
                                      (s->lb_swizzle & 2) != 0);
-    const dim3 tg(tile_map_blocks(tm)), tb(kTX, kTY);
+    const TileMap tmp = make_tile_map(s->p.nx, s->p.ny,
+                                      Lat<Q>::D == 3 ? (s->p.nz + s->zc_prep - 1) / s->zc_prep : 1,
+                                      (s->lb_swizzle & 2) != 0);
+    const dim3 tg(tile_map_blocks(tm)), tgp(tile_map_blocks(tmp)), tb(kTX, kTY);
     const bool want_noise = cpl != LBL_LB_ONLY && s->p.kT > 0;
     const bool want_mu = cpl == LBL_FULL;
     if (want_noise || want_mu) {
@@ -431,15 +474,15 @@ struct Impl {
       pa.k0 = s->k0;
       pa.k1 = s->k1;
       pa.step = n;
-      pa.zc = s->zc;
+      pa.zc = s->zc_prep;
       pa.psi = psin;
       pa.noise = want_noise ? noise : nullptr;
       pa.mu = want_mu ? static_cast<S*>(s->mu) : nullptr;
       int rc;
       if (SMOL == kFV)
-        rc = launch(s, "k_prep", [&] { k_prep_fv<S, Q><<<tg, tb, 0, s->stream>>>(pa, tm); });
+        rc = launch(s, "k_prep", [&] { k_prep_fv<S, Q><<<tgp, tb, 0, s->stream>>>(pa, tmp); });
       else
-        rc = launch(s, "k_prep", [&] { k_prep_fd<S, Q><<<tg, tb, 0, s->stream>>>(pa, tm); });
+        rc = launch(s, "k_prep", [&] { k_prep_fd<S, Q><<<tgp, tb, 0, s->stream>>>(pa, tmp); });
       if (rc) return rc;
     }
     if (cpl != LBL_SMOL_ONLY) {
@@ -845,13 +888,8 @@ int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* e
 
   const size_t N = static_cast<size_t>(s->N);
   const size_t sz = s->ssize;
-  // z-chunk of the tiled SMOL kernels: at least ~2048 blocks when possible.
-  {
-    const int bxy = ((params->nx + kTX - 1) / kTX) * ((params->ny + kTY - 1) / kTY);
-    int zc = params->nz;
-    while (zc > 8 && bxy * ((params->nz + zc - 1) / zc) < 2048) zc = (zc + 1) / 2;
-    s->zc = std::max(1, zc);
-  }
+  // z-chunks of the tiled SMOL kernels: set from their occupancy at init.
+  s->zc = s->zc_prep = params->nz;
   // LB blocks: the widest power of two up to 256 that fits along x (whole
   // rows where possible, so that pulls shifted along x stay inside a block).
   s->lb_lw = 5;
@@ -1421,7 +1459,7 @@ int lbl_set_schedule(lbl_sim* sim, const lbl_schedule* sch) {
   sim->lb_lw = lw;
   sim->lb_swizzle = sch->xcd_swizzle & 3;
   sim->overlap = sch->overlap;
-  if (sch->zc > 0) sim->zc = std::min(sch->zc, sim->p.nz);
+  if (sch->zc > 0) sim->zc = sim->zc_prep = std::min(sch->zc, sim->p.nz);
   return LBL_OK;
 }
 
