@@ -278,6 +278,17 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
   const Nbr nb(g, x, y, z);
   const int s = nb.at(0, 0, 0);
 
+  // The Q pulls go out first, the gathers of mu for the force behind them.
+  S fv[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const S* src = &a.f_in[static_cast<size_t>(i) * g.N + nb.at(-L::cx[i], -L::cy[i], -L::cz[i])];
+    if constexpr (NT)
+      fv[i] = __builtin_nontemporal_load(src);
+    else
+      fv[i] = *src;
+  }
+
   // Force density F = -psi grad mu: FD central difference (Sec. IV) or the FV
   // gradient (1/c_s^2) sum_i w_i c_i mu(x + c_i) (Eq. fvgrad).
   S F[3] = {0, 0, 0};
@@ -304,16 +315,6 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
     F[0] = -ps * gx;
     F[1] = -ps * gy;
     F[2] = -ps * gz;
-  }
-
-  S fv[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const S* src = &a.f_in[static_cast<size_t>(i) * g.N + nb.at(-L::cx[i], -L::cy[i], -L::cz[i])];
-    if constexpr (NT)
-      fv[i] = __builtin_nontemporal_load(src);
-    else
-      fv[i] = *src;
   }
 
   // Noise of the non-conserved modes, n_k = sigma_k z_k, with

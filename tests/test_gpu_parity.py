@@ -187,3 +187,28 @@ def test_resume_is_bitwise(lattice, smol, precision):
         sim.step(6)
         np.testing.assert_array_equal(sim.observe(lbl.LBL_OBS_POP), f15)
         np.testing.assert_array_equal(sim.observe(lbl.LBL_OBS_PSI), p15)
+
+
+@pytest.mark.parametrize("lattice", [H.D3Q15, H.D3Q19])
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
+def test_wide_lattice_ragged_tiles(lattice, precision):
+    """A lattice wider than the LB rows' 64-site blocks and the SMOL tiles,
+    with ragged tiles in x (70 = 2 x 32 + 6) and y (21 = 2 x 8 + 5)."""
+    c = H.config(lattice=lattice, smol=H.FV, precision=precision, shape=(70, 21, 9), a=-0.04,
+                 b=0.04, kappa=0.05, init=1, kT=1e-5)
+    _check(c, 15)
+
+
+def test_wide_lattice_schedules_do_not_change_results():
+    from paper_1104_0078_amd import lbl
+    c = H.config(lattice=H.D3Q19, smol=H.FV, shape=(70, 21, 13), init=0, a=-0.04, b=0.04)
+    ini = lbl.make_init(kind=0, psi_std=1e-3)
+    out = []
+    for swz, zc, ov in ((0, 0, 0), (2, 4, 0), (0, 5, 1), (3, 13, 0)):
+        with lbl.Sim(H.lbl_params(c), ini) as sim:
+            sim.set_schedule(lb_width=64, xcd_swizzle=swz, zc=zc, overlap=ov)
+            sim.step(6)
+            out.append((sim.observe(lbl.LBL_OBS_POP), sim.observe(lbl.LBL_OBS_PSI)))
+    for f, p in out[1:]:
+        np.testing.assert_array_equal(f, out[0][0])
+        np.testing.assert_array_equal(p, out[0][1])

@@ -41,6 +41,9 @@ MIX = [
     (H.config(lattice=H.D2Q9, smol=H.FV, coupling=H.SMOL_ONLY, shape=(40, 40, 1), seed=16,
               u_imposed=(0.02, 0.01, 0)), 19),
     (H.config(lattice=H.D3Q15, smol=H.FD, shape=(12, 18, 10), seed=17), 21),
+    # ragged SMOL tiles in x and y, LB rows longer than 64 sites
+    (H.config(lattice=H.D3Q19, smol=H.FV, shape=(70, 21, 9), seed=18, a=-0.04, b=0.04,
+              init=1), 13),
 ]
 
 
