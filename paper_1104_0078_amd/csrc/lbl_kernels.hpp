@@ -501,16 +501,31 @@ struct PsiPlane {
   S v[RS];
 };
 
+// Wrapped in-plane offsets of the elements e = tid + k kTX kTY (k < NK) of a
+// W-wide region whose corner is (x0 + ox, y0 + oy), computed once per block so
+// that the z-marching loops do no modulo arithmetic (planes advance by one).
+template <int W, int NK>
+__device__ __forceinline__ void region_offsets(const Geom& g, int x0, int y0, int ox, int oy,
+                                               bool near, int tid, int (&xy)[NK]) {
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int e = tid + k * kTX * kTY;
+    xy[k] = wrap_r(x0 + ox + e % W, g.nx, near) + g.nx * wrap_r(y0 + oy + e / W, g.ny, near);
+  }
+}
+
+__device__ __forceinline__ int next_plane(int z, int nz) { return z + 1 == nz ? 0 : z + 1; }
+
+// psi plane at offset zoff into the region with halo 1 (offsets from
+// region_offsets with corner (-1, -1)).
 template <typename S>
-__device__ __forceinline__ void prep_load_psi(PsiPlane<S>& r, const PrepArgs<S>& a, int p,
-                                              int x0, int y0, bool near, int tid) {
-  using R = PsiPlane<S>;
-  const Geom& g = a.g;
-  const int pz = wrap_any(p, g.nz);
-  for (int e = tid; e < R::RS; e += kTX * kTY) {
-    const int i = e % R::W, j = e / R::W;
-    const int gx = wrap_r(x0 - 1 + i, g.nx, near), gy = wrap_r(y0 - 1 + j, g.ny, near);
-    r.v[e] = a.psi[gx + g.nx * (gy + g.ny * pz)];
+__device__ __forceinline__ void prep_load_psi(PsiPlane<S>& r, const S* __restrict__ psi,
+                                              const int (&xy)[2], int zoff, int tid) {
+  static_assert(PsiPlane<S>::RS <= 2 * kTX * kTY, "two elements per thread");
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int e = tid + k * kTX * kTY;
+    if (e < PsiPlane<S>::RS) r.v[e] = psi[xy[k] + zoff];
   }
 }
 
@@ -543,12 +558,15 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
   const int z0 = D == 3 ? bz * a.zc : 0, z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
   const int x = x0 + tx, y = y0 + ty;
   const bool live = x < g.nx && y < g.ny;
-  auto gen = [&](int p) {  // xi on plane p, region with halo 1
-    const int pz = wrap_any(p, g.nz);
-    for (int e = tid; e < RS; e += NT) {
-      const int i = e % W, j = e / W;
-      const int gx = wrap_r(x0 - 1 + i, g.nx, near), gy = wrap_r(y0 - 1 + j, g.ny, near);
-      const uint32_t site = static_cast<uint32_t>(gx + g.nx * (gy + g.ny * pz));
+  static_assert(RS <= 2 * NT, "two region elements per thread");
+  int rxy[2];
+  region_offsets<W>(g, x0, y0, -1, -1, near, tid, rxy);
+  auto gen = [&](int zoff) {  // xi on the plane at zoff, region with halo 1
+#pragma unroll 1
+    for (int k = 0; k < 2; ++k) {  // not unrolled: one copy of the normal generator
+      const int e = tid + k * NT;
+      if (e >= RS) break;
+      const uint32_t site = static_cast<uint32_t>((k ? rxy[1] : rxy[0]) + zoff);
       S zz[4];
       if constexpr (D == 2)
         Normal4<S>::gen2(site, a.step, 0, kTagSMOL, a.k0, a.k1, zz);
@@ -573,7 +591,7 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
   };
   if constexpr (D == 2) {
     if (a.noise) gen(0);
-    if (a.mu) prep_load_psi(spsi, a, 0, x0, y0, near, tid);
+    if (a.mu) prep_load_psi(spsi, a.psi, rxy, 0, tid);
     __syncthreads();
     if (a.noise) {
       fold();
@@ -582,9 +600,11 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
     if (a.mu && live) a.mu[x + g.nx * y] = prep_mu2(spsi, a.c, tx, ty);
   } else {
     // Iteration p: xi(p) and psi(p) staged; N(p-1) and mu(p-1) emitted.
-    for (int p = z0 - 1; p <= z1; ++p) {
-      if (a.noise) gen(p);
-      if (a.mu) prep_load_psi(spsi, a, p, x0, y0, near, tid);
+    const int plane = g.nx * g.ny;
+    int pz = wrap_any(z0 - 1, g.nz);
+    for (int p = z0 - 1; p <= z1; ++p, pz = next_plane(pz, g.nz)) {
+      if (a.noise) gen(plane * pz);
+      if (a.mu) prep_load_psi(spsi, a.psi, rxy, plane * pz, tid);
       __syncthreads();
       const bool emit = p - 1 >= z0 && p - 1 < z1;
       if (a.noise) {
@@ -637,15 +657,21 @@ __device__ __forceinline__ void prep_fd_body(const PrepArgs<S>& a, int bx, int b
     constexpr double r = ce_sqrt(L::lw[l]);
     A[l] = a.amp * S(r);
   });
+  static_assert(RS <= 2 * kTX * kTY, "two region elements per thread");
+  int zxy[2], pxy[2];
+  region_offsets<W>(g, x0, y0, -1, -1, near, tid, zxy);
+  region_offsets<PsiPlane<S>::W>(g, x0, y0, -1, -1, near, tid, pxy);
   S nm = 0, n0 = 0, np = 0;  // partial N for planes p-1, p, p+1
   const int pbeg = D == 3 ? z0 - 1 : 0, pend = D == 3 ? z1 : 0;
-  for (int p = pbeg; p <= pend; ++p) {
-    const int pz = wrap_any(p, g.nz);
+  const int plane = g.nx * g.ny;
+  int pz = wrap_any(pbeg, g.nz);
+  for (int p = pbeg; p <= pend; ++p, pz = next_plane(pz, g.nz)) {
     if (a.noise) {
-      for (int e = tid; e < RS; e += kTX * kTY) {
-        const int i = e % W, j = e / W;
-        const int gx = wrap_r(x0 - 1 + i, g.nx, near), gy = wrap_r(y0 - 1 + j, g.ny, near);
-        const uint32_t site = static_cast<uint32_t>(gx + g.nx * (gy + g.ny * pz));
+#pragma unroll 1
+      for (int k = 0; k < 2; ++k) {  // not unrolled: one copy of the normal generator
+        const int e = tid + k * kTX * kTY;
+        if (e >= RS) break;
+        const uint32_t site = static_cast<uint32_t>((k ? zxy[1] : zxy[0]) + plane * pz);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           S zz[4];
@@ -656,7 +682,7 @@ __device__ __forceinline__ void prep_fd_body(const PrepArgs<S>& a, int bx, int b
         }
       }
     }
-    if (a.mu) prep_load_psi(pr, a, p, x0, y0, near, tid);
+    if (a.mu) prep_load_psi(pr, a.psi, pxy, plane * pz, tid);
     __syncthreads();
     if (a.mu && live) {
       if constexpr (D == 2) {
@@ -888,18 +914,19 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
     pxy[k] = wrap_r(x0 - 2 + i, g.nx, near) + g.nx * wrap_r(y0 - 2 + j, g.ny, near);
   }
 
-  S pf[NPF];
-  auto fetch_phi = [&](int p) {
-    const int pz = wrap_any(p, g.nz);
+  // In-plane offsets of the phi elements this thread loads; the planes are
+  // tracked incrementally, so the loop does no modulo arithmetic.
+  int fxy[NPF];
 #pragma unroll
-    for (int k = 0; k < NPF; ++k) {
-      const int e = tid + k * NT;
-      if (e < WP * HP) {
-        const int i = e % WP, j = e / WP;
-        const int gx = wrap_r(x0 - 3 + i, g.nx, near), gy = wrap_r(y0 - 3 + j, g.ny, near);
-        pf[k] = a.phi[gx + g.nx * (gy + g.ny * pz)];
-      }
-    }
+  for (int k = 0; k < NPF; ++k) {
+    const int e = tid + k * NT;
+    fxy[k] = wrap_r(x0 - 3 + e % WP, g.nx, near) + g.nx * wrap_r(y0 - 3 + e / WP, g.ny, near);
+  }
+  S pf[NPF];
+  auto fetch_phi = [&](int zoff) {
+#pragma unroll
+    for (int k = 0; k < NPF; ++k)
+      if (tid + k * NT < WP * HP) pf[k] = a.phi[fxy[k] + zoff];
   };
 
   SoPlanes<S> so[NE];                  // phi planes p-2, p-1, p
@@ -910,18 +937,21 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
 #pragma unroll
     for (int c = 0; c < D; ++c) uv[k][c] = 0;
 
-  fetch_phi(z0 - 3);
+  int zf = wrap_any(z0 - 3, g.nz);  // plane of the phi fetch
+  int zu = wrap_any(z0 - 5, g.nz);  // plane p - 2 of the velocity at iteration p
+  fetch_phi(plane * zf);
   for (int p = z0 - 3; p <= z1 + 2; ++p) {
     const bool do_mu = p >= z0 - 1, do_J = p >= z0 + 1, do_G = p >= z0 + 3 && live;
 #pragma unroll
     for (int k = 0; k < NPF; ++k)
       if (tid + k * NT < WP * HP) sphi[tid + k * NT] = pf[k];
-    if (p < z1 + 2) fetch_phi(p + 1);
+    zf = next_plane(zf, g.nz);
+    if (p < z1 + 2) fetch_phi(plane * zf);
     const int s = x + g.nx * (y + g.ny * (p - 3));
     SiteIn<S> sv{};
     if (do_G) sv = fetch_site(a, s);
     if (do_J) {
-      const int zo = plane * wrap_any(p - 2, g.nz);
+      const int zo = plane * zu;
 #pragma unroll
       for (int k = 0; k < NE; ++k)
         if (jon[k]) {
@@ -929,6 +959,7 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
           for (int c = 0; c < D; ++c) uv[k][c] = uval(a, c, pxy[k] + zo);
         }
     }
+    zu = next_plane(zu, g.nz);
     __syncthreads();
     // Plane sums of phi(p); mu(p-1) from planes p-2, p-1, p.
     const int mslot = ring(p - 1, 3);
@@ -1014,12 +1045,16 @@ __device__ __forceinline__ void stage_fd_body(const StageArgs<S>& a, int bx, int
   const int z0 = D == 3 ? bz * a.zc : 0;
   const int z1 = D == 3 ? min(z0 + a.zc, g.nz) : 1;
 
-  auto load_phi = [&](int p) {
-    const int slot = ring(p, NP), pz = wrap_any(p, g.nz);
-    for (int e = tid; e < WP * HP; e += NT) {
-      const int i = e % WP, j = e / WP;
-      const int gx = wrap_r(x0 - 2 + i, g.nx, near), gy = wrap_r(y0 - 2 + j, g.ny, near);
-      sphi[slot][e] = a.phi[gx + g.nx * (gy + g.ny * pz)];
+  static_assert(WP * HP <= 2 * NT, "two region elements per thread");
+  int fxy[2];
+  region_offsets<WP>(g, x0, y0, -2, -2, near, tid, fxy);
+  const int plane = g.nx * g.ny;
+  auto load_phi = [&](int p, int pz) {
+    const int slot = ring(p, NP);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = tid + k * NT;
+      if (e < WP * HP) sphi[slot][e] = a.phi[fxy[k] + plane * pz];
     }
   };
   auto comp_mu = [&](int p) {
@@ -1053,14 +1088,15 @@ __device__ __forceinline__ void stage_fd_body(const StageArgs<S>& a, int bx, int
   };
 
   if constexpr (D == 2) {
-    load_phi(0);
+    load_phi(0, 0);
     __syncthreads();
     comp_mu(0);
     __syncthreads();
     comp_G(0);
   } else {
-    for (int t = z0 - 4; t < z1; ++t) {
-      load_phi(t + 2);
+    int pz = wrap_any(z0 - 2, g.nz);
+    for (int t = z0 - 4; t < z1; ++t, pz = next_plane(pz, g.nz)) {
+      load_phi(t + 2, pz);
       __syncthreads();
       if (t + 1 >= z0 - 1) comp_mu(t + 1);
       __syncthreads();
