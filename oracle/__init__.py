@@ -21,6 +21,7 @@ FD, FV = 0, 1
 FULL, SMOL_ONLY, LB_ONLY = 0, 1, 2
 D2Q9, D3Q15, D3Q19 = 9, 15, 19
 TAG_LB, TAG_SMOL, TAG_INIT = 0, 1, 2
+FDNOISE_LINK, FDNOISE_FOURIER = 0, 1
 
 
 class Params(ctypes.Structure):
@@ -28,7 +29,7 @@ class Params(ctypes.Structure):
         ("lattice", ctypes.c_int32), ("smol", ctypes.c_int32),
         ("coupling", ctypes.c_int32), ("rk_stages", ctypes.c_int32),
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-        ("pad0", ctypes.c_int32),
+        ("fd_noise", ctypes.c_int32),
         ("rho0", ctypes.c_double), ("eta", ctypes.c_double), ("M", ctypes.c_double),
         ("a", ctypes.c_double), ("b", ctypes.c_double), ("kappa", ctypes.c_double),
         ("kT", ctypes.c_double), ("omega_bulk", ctypes.c_double),
@@ -69,6 +70,7 @@ def lib():
             "orc_force": (None, [P, dp, dp]),
             "orc_velocity": (None, [P, dp, dp, dp]),
             "orc_fd_noise_divergence": (None, [P, dp, dp]),
+            "orc_fd_noise_fourier": (None, [P, dp, dp]),
             "orc_smol_noise": (None, [P, ctypes.c_uint32, dp]),
             "orc_collide": (None, [P, dp, dp, dp, dp]),
             "orc_smol_rhs": (None, [P, dp, dp, dp, dp]),
@@ -93,10 +95,12 @@ def _dp(a):
 
 def make_params(lattice=D2Q9, smol=FD, coupling=FULL, rk_stages=2, shape=(16, 16, 1),
                 rho0=1.0, eta=0.1, M=0.1, a=0.04, b=0.1, kappa=0.05, kT=1e-5,
-                omega_bulk=1.0, omega_ghost=1.0, u_imposed=(0.0, 0.0, 0.0), seed=1234):
+                omega_bulk=1.0, omega_ghost=1.0, u_imposed=(0.0, 0.0, 0.0), seed=1234,
+                fd_noise=FDNOISE_LINK):
     nx, ny, nz = (tuple(shape) + (1, 1, 1))[:3]
     p = Params()
     p.lattice, p.smol, p.coupling, p.rk_stages = lattice, smol, coupling, rk_stages
+    p.fd_noise = fd_noise
     p.nx, p.ny, p.nz = nx, ny, nz
     p.rho0, p.eta, p.M, p.a, p.b, p.kappa, p.kT = rho0, eta, M, a, b, kappa, kT
     p.omega_bulk, p.omega_ghost = omega_bulk, omega_ghost
@@ -190,6 +194,11 @@ def velocity(p, f, F):
 
 def fd_noise_divergence(p, zeta):
     return _unary("orc_fd_noise_divergence", p, zeta, (nsites(p),))
+
+
+def fd_noise_fourier(p, w):
+    """FD noise built in Fourier space from the white field w (Sec. V.A)."""
+    return _unary("orc_fd_noise_fourier", p, w, (nsites(p),))
 
 
 def smol_noise(p, step):

@@ -432,15 +432,111 @@ void orc_fd_noise_divergence(const orc_params *p, const double *zeta, double *ou
   }
 }
 
+/* Plain discrete Fourier transform along one axis of a complex field (re,
+ * im), every line separately: X(k) = sum_j x(j) exp(sign i 2 pi j k / L),
+ * sign -1 forward, +1 inverse (unscaled).  O(L) per output, no fast
+ * algorithm: the oracle only runs on small lattices. */
+static void dft_axis(const orc_params *p, double *re, double *im, int ax, int sign) {
+  const int n[3] = {p->nx, p->ny, p->nz};
+  const int L = n[ax];
+  if (L == 1) return;
+  const int64_t N = nsites(p);
+  const int64_t stride = ax == 0 ? 1 : (ax == 1 ? p->nx : (int64_t)p->nx * p->ny);
+  const int64_t nlines = N / L;
+  double *cs = (double *)malloc(sizeof(double) * L);
+  double *sn = (double *)malloc(sizeof(double) * L);
+  for (int k = 0; k < L; k++) {
+    cs[k] = cos(2.0 * M_PI * k / L);
+    sn[k] = sign * sin(2.0 * M_PI * k / L);
+  }
+#pragma omp parallel
+  {
+    double *tr = (double *)malloc(sizeof(double) * L);
+    double *ti = (double *)malloc(sizeof(double) * L);
+#pragma omp for schedule(static)
+    for (int64_t line = 0; line < nlines; line++) {
+      int64_t base;
+      if (ax == 0) base = line * p->nx;
+      else if (ax == 1) base = line % p->nx + (line / p->nx) * (int64_t)p->nx * p->ny;
+      else base = line;
+      for (int k = 0; k < L; k++) {
+        double ar = 0.0, ai = 0.0;
+        for (int j = 0; j < L; j++) {
+          const int m = (int)(((int64_t)j * k) % L);
+          const double xr = re[base + j * stride], xi = im[base + j * stride];
+          ar += xr * cs[m] - xi * sn[m];
+          ai += xr * sn[m] + xi * cs[m];
+        }
+        tr[k] = ar;
+        ti[k] = ai;
+      }
+      for (int k = 0; k < L; k++) {
+        re[base + k * stride] = tr[k];
+        im[base + k * stride] = ti[k];
+      }
+    }
+    free(tr);
+    free(ti);
+  }
+  free(cs);
+  free(sn);
+}
+
+static void dft(const orc_params *p, double *re, double *im, int sign) {
+  for (int ax = 0; ax < 3; ax++) dft_axis(p, re, im, ax, sign);
+}
+
+/* FD noise built in Fourier space as Sec. V.A states it: eta(q) with
+ * covariance -2 kT M L(q) (Eq. etafdt), L the Fourier symbol of the lattice
+ * Laplacian (Eq. solapft; its 2-D analogue).  Realisation from a real white
+ * field w(x) ~ N(0, 1): N = F^-1[ sqrt(-2 kT M L(q)) F[w] ], whose covariance
+ * is the operator -2 kT M L_SO.  L(q) is taken as the transform of the
+ * Laplacian stencil itself (orc_laplacian applied to a unit impulse). */
+void orc_fd_noise_fourier(const orc_params *p, const double *w, double *out) {
+  const int64_t N = nsites(p);
+  double *re = (double *)calloc(N, sizeof(double));
+  double *im = (double *)calloc(N, sizeof(double));
+  double *lr = (double *)calloc(N, sizeof(double));
+  double *li = (double *)calloc(N, sizeof(double));
+  double *delta = (double *)calloc(N, sizeof(double));
+  for (int64_t s = 0; s < N; s++) re[s] = w[s];
+  delta[0] = 1.0;
+  orc_laplacian(p, delta, lr);
+  dft(p, lr, li, -1);  /* L(q), real up to rounding (symmetric stencil) */
+  dft(p, re, im, -1);
+  for (int64_t s = 0; s < N; s++) {
+    const double v = -2.0 * p->kT * p->M * lr[s];
+    const double A = v > 0.0 ? sqrt(v) : 0.0;
+    re[s] *= A;
+    im[s] *= A;
+  }
+  dft(p, re, im, +1);
+  for (int64_t s = 0; s < N; s++) out[s] = re[s] / (double)N;
+  free(re);
+  free(im);
+  free(lr);
+  free(li);
+  free(delta);
+}
+
 /* The noise term N^n of the SMOL right-hand side at step n, frozen over the
  * Runge-Kutta stages (Sec. V).  FD: link fluxes above, zeta_l(x) = normal
- * slot l.  FV: Eqs. (fvdiff), (noiseflux): node noise xi(x) with covariance
+ * slot l, or (fd_noise == ORC_FDNOISE_FOURIER) the Fourier construction
+ * above with w(x) = normal slot 0.  FV: Eqs. (fvdiff), (noiseflux): node noise xi(x) with covariance
  * 2 kT M delta (Eq. fdt_orderpara), xi_a = sqrt(2 kT M) normal slot a, and
  * N = Gamma . xi. */
 void orc_smol_noise(const orc_params *p, uint32_t step, double *out) {
   int64_t N = nsites(p);
   int d = orc_d(p->lattice);
-  if (p->smol == ORC_FD) {
+  if (p->smol == ORC_FD && p->fd_noise == ORC_FDNOISE_FOURIER) {
+    /* white field: normal slot 0 of each site */
+    double *w = (double *)malloc(sizeof(double) * N);
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < N; s++)
+      w[s] = orc_normal(p->seed, (uint32_t)s, step, ORC_TAG_SMOL, 0);
+    orc_fd_noise_fourier(p, w, out);
+    free(w);
+  } else if (p->smol == ORC_FD) {
     int nl = orc_nlinks(p->lattice);
     double *zeta = (double *)malloc(sizeof(double) * N * nl);
 #pragma omp parallel for schedule(static)

@@ -31,6 +31,7 @@ enum { ORC_D2Q9 = 9, ORC_D3Q15 = 15, ORC_D3Q19 = 19 };
 enum { ORC_FD = 0, ORC_FV = 1 };
 enum { ORC_FULL = 0, ORC_SMOL_ONLY = 1, ORC_LB_ONLY = 2 };
 enum { ORC_TAG_LB = 0, ORC_TAG_SMOL = 1, ORC_TAG_INIT = 2 };
+enum { ORC_FDNOISE_LINK = 0, ORC_FDNOISE_FOURIER = 1 };
 
 typedef struct orc_params {
   int32_t lattice;     /* ORC_D2Q9, ORC_D3Q15 or ORC_D3Q19 */
@@ -38,7 +39,7 @@ typedef struct orc_params {
   int32_t coupling;    /* ORC_FULL, ORC_SMOL_ONLY, ORC_LB_ONLY */
   int32_t rk_stages;   /* 1 (Euler), 2 (Heun), 4 (classical RK4) */
   int32_t nx, ny, nz;
-  int32_t pad0;
+  int32_t fd_noise;    /* FD noise construction: ORC_FDNOISE_LINK or ORC_FDNOISE_FOURIER */
   double rho0;         /* mean density, also the density in the noise amplitudes */
   double eta;          /* shear viscosity; shear rate omega_s = 1/(1/2 + eta/(rho0 c_s^2)) */
   double M;            /* mobility */
@@ -72,6 +73,7 @@ void orc_velocity(const orc_params *p, const double *f, const double *F, double 
 
 /* Noise fields. */
 void orc_fd_noise_divergence(const orc_params *p, const double *zeta /* nlinks*N */, double *out);
+void orc_fd_noise_fourier(const orc_params *p, const double *w /* N */, double *out);
 void orc_smol_noise(const orc_params *p, uint32_t step, double *out);
 
 /* One site's collision (App. B): fbar (q) -> fstar (q) given force density F

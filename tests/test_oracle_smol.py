@@ -108,6 +108,36 @@ def test_fd_link_noise_covariance(lattice, shape):
     np.testing.assert_allclose(E.sum(axis=0), 0.0, atol=1e-14)
 
 
+@pytest.mark.parametrize("lattice,shape", [(O.D2Q9, (6, 5, 1)), (O.D3Q15, (4, 3, 5)),
+                                           (O.D3Q19, (5, 4, 3))])
+def test_fd_fourier_noise_covariance(lattice, shape):
+    """The literal Fourier-space FD noise of Sec. V.A (Eq. etafdt): the linear
+    map K from the white field to N must have covariance K K^T = -2 kT M L_SO
+    with L_SO the oracle's real-space stencil, be symmetric, and conserve psi.
+    Non-cubic sides catch transposed axes; a missing square root, scale or
+    sign of the transform breaks the covariance."""
+    p = O.make_params(lattice=lattice, smol=O.FD, shape=shape, kT=0.7, M=0.3,
+                      fd_noise=O.FDNOISE_FOURIER)
+    N = O.nsites(p)
+    K = _matrix(lambda w: O.fd_noise_fourier(p, w), N, N)
+    Lso = _matrix(lambda v: O.laplacian(p, v), N, N)
+    np.testing.assert_allclose(K @ K.T, -2 * p.kT * p.M * Lso, atol=1e-13)
+    np.testing.assert_allclose(K, K.T, atol=1e-14)
+    np.testing.assert_allclose(K.sum(axis=0), 0.0, atol=1e-13)
+
+
+def test_fd_fourier_noise_drives_the_step():
+    """With fd_noise = Fourier the step's N^n is the Fourier map applied to the
+    white field of normal slot 0 (same Philox stream as the link fluxes)."""
+    p = O.make_params(lattice=O.D2Q9, smol=O.FD, shape=(7, 6, 1), kT=0.2, M=0.3,
+                      fd_noise=O.FDNOISE_FOURIER)
+    N = O.nsites(p)
+    w = np.array([O.normal(p.seed, s, 11, O.TAG_SMOL, 0) for s in range(N)])
+    np.testing.assert_allclose(O.smol_noise(p, 11), O.fd_noise_fourier(p, w), atol=1e-15)
+    p_link = O.make_params(lattice=O.D2Q9, smol=O.FD, shape=(7, 6, 1), kT=0.2, M=0.3)
+    assert np.abs(O.smol_noise(p_link, 11) - O.smol_noise(p, 11)).max() > 1e-3
+
+
 @pytest.mark.parametrize("lattice,shape", [(O.D2Q9, (5, 4, 1)), (O.D3Q15, (4, 4, 3)),
                                            (O.D3Q19, (4, 4, 3))])
 def test_fv_noise_covariance(lattice, shape):
