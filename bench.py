@@ -142,7 +142,8 @@ def make_sim_params(lbl, w, precision=None, seed=1234):
     return lbl.make_params(lattice=w["lattice"], smol=w["smol"],
                            precision=w["precision"] if precision is None else precision,
                            shape=w["shape"], rho=1.0, eta=w["eta"], M=w["M"], a=w["a"],
-                           b=w["b"], kappa=w["kappa"], kT=w["kT"], seed=seed)
+                           b=w["b"], kappa=w["kappa"], kT=w["kT"], seed=seed,
+                           fd_noise=w.get("fd_noise", 0))
 
 
 def run_single(lbl, torch, w, wname, steps, warmup, tune, precision=None, schedule=None):
@@ -340,6 +341,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-fp32", action="store_true",
                     help="skip the FP32-deviation run of the same lattice")
+    ap.add_argument("--no-fd-noise", action="store_true",
+                    help="skip the FD variant of the same lattice (link vs Fourier noise)")
     ap.add_argument("--no-tune", action="store_true", help="no autotuning of the pool legs")
     ap.add_argument("--tune-single", action="store_true",
                     help="autotune the single-run schedule too (default: the library's own)")
@@ -436,6 +439,21 @@ def main():
                                        "ms_per_step": round(r32["ms_per_step"], 4),
                                        "schedule": r32["schedule"]}
         print("fp32 run done: %.1f MLUPS" % r32["mlups"], file=sys.stderr, flush=True)
+    if not args.no_fd_noise:
+        # The FD variant of the same workload with its conserved noise built
+        # both ways: link fluxes in-kernel, and the paper's Fourier-space
+        # construction (a hipFFT pair per step).
+        legs = {}
+        for fdn, name in ((0, "link"), (1, "fourier")):
+            wf = dict(w, smol=0, fd_noise=fdn)
+            rf = run_single(lbl, torch, wf, args.workload, min(args.steps, 30), args.warmup, False)
+            legs[name] = {"value": round(rf["mlups"], 2), "unit": "MLUPS",
+                          "ms_per_step": round(rf["ms_per_step"], 4),
+                          "kernels_ms_per_step": {t[0]: round(t[2] / min(args.steps, 30), 4)
+                                                  for t in rf["ktimes"]}}
+        out["fd_noise_same_lattice"] = legs
+        print("fd noise legs done: link %.1f, Fourier %.1f MLUPS" % (
+            legs["link"]["value"], legs["fourier"]["value"]), file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = {}
         for prec, name in ((1, "fp32"), (0, "fp64")):

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LBL_ABI_VERSION 2
+#define LBL_ABI_VERSION 3
 
 typedef struct lbl_sim lbl_sim;
 
@@ -102,8 +102,21 @@ typedef struct lbl_params {
   double u_imposed[3];
   uint64_t seed;
   int32_t sample_every;
-  int32_t reserved; /* must be 0 */
+  int32_t fd_noise; /* enum lbl_fd_noise; LBL_FDNOISE_LINK unless smol == LBL_SMOL_FD */
 } lbl_params;
+
+/* How the FD variant builds its conserved noise N^n (Sec. V.A), both with
+ * covariance -2 kT M L_SO (Eq. etafdt):
+ *  LINK (default): one Gaussian flux per undirected link of the
+ *    Shinozaki-Oono stencil, amplitude sqrt(2 kT M lambda_l), N = the
+ *    divergence of the fluxes; real space, in-kernel, no transform;
+ *  FOURIER: the paper's own construction, N = F^-1[ sqrt(-2 kT M L(q)) F[w] ]
+ *    with w(x) the white field of normal slot 0 (site x, step n, SMOL
+ *    stream) and L(q) the stencil's symbol (Eq. solapft; its 2-D analogue);
+ *    one real-to-complex and one complex-to-real hipFFT transform per step.
+ *    Single simulations only (a pool refuses such a request); the FFT plans
+ *    hold work memory of hipFFT's own beyond lbl_sim_bytes. */
+enum lbl_fd_noise { LBL_FDNOISE_LINK = 0, LBL_FDNOISE_FOURIER = 1 };
 
 enum lbl_init_kind {
   LBL_INIT_REST = 0,     /* fbar = equilibrium at (rho, boost_u); psi = psi_std * z */

@@ -20,7 +20,7 @@ def sources():
 def build(verbose: bool = False) -> str:
     cmd = (["hipcc"] + HIPFLAGS + ["-I", os.path.join(ROOT, "include"),
                                    "-I", os.path.join(HERE, "csrc")]
-           + sources() + ["-o", LIB + ".tmp"])
+           + sources() + ["-lhipfft", "-o", LIB + ".tmp"])
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

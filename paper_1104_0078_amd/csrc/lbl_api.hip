@@ -3,6 +3,7 @@
 // launch sequence of the coupled FLBE + SMOL sweep, observables, launch
 // schedules, and the pool that batches independent simulations.
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <chrono>
@@ -51,6 +52,9 @@ struct lbl_sim {
   void* u = nullptr;
   void* u_end = nullptr;  // velocity of the streamed populations (stages at t_{n+1})
   void* noise = nullptr;
+  void* fspec = nullptr;  // FD noise in Fourier space: half spectrum (interleaved re, im)
+  void* famp = nullptr;   // and its amplitude table sqrt(-2 kT M L(q)) / N
+  hipfftHandle fft_fwd = nullptr, fft_inv = nullptr;
   double* part = nullptr;
   int nparts = 0;
   double* tot = nullptr;
@@ -133,11 +137,20 @@ void dev_release(lbl_sim* s, void* ptr) {
 void release_all(lbl_sim* s) {
   if (!s) return;
   if (!s->owned.empty()) (void)hipStreamSynchronize(s->stream);
+  if (s->fft_fwd) (void)hipfftDestroy(s->fft_fwd);
+  if (s->fft_inv) (void)hipfftDestroy(s->fft_inv);
+  s->fft_fwd = s->fft_inv = nullptr;
   for (void* ptr : s->owned) dev_free(s, ptr);
   s->owned.clear();
 }
 
 inline int grid_for(int n) { return (n + kBlock - 1) / kBlock; }
+
+// Values of the real-to-complex half spectrum: nz x ny x (nx/2 + 1).
+size_t half_spectrum(const lbl_params& p) {
+  return static_cast<size_t>(p.nx / 2 + 1) * p.ny * p.nz;
+}
+
 
 hipEvent_t take_event(lbl_sim* s) {
   if (!s->event_pool.empty()) {
@@ -266,8 +279,11 @@ int validate(const lbl_params* p, const lbl_init* in) {
   if (!(ws > 0 && ws < 2)) return fail(nullptr, LBL_E_INVAL, "shear rate outside (0, 2)");
   if (!(p->omega_bulk > 0 && p->omega_bulk <= 2) || !(p->omega_ghost > 0 && p->omega_ghost <= 2))
     return fail(nullptr, LBL_E_INVAL, "omega_bulk and omega_ghost must lie in (0, 2]");
-  if (p->sample_every < 0 || p->reserved != 0)
-    return fail(nullptr, LBL_E_INVAL, "sample_every must be >= 0 and reserved 0");
+  if (p->sample_every < 0) return fail(nullptr, LBL_E_INVAL, "sample_every must be >= 0");
+  if (p->fd_noise != LBL_FDNOISE_LINK && p->fd_noise != LBL_FDNOISE_FOURIER)
+    return fail(nullptr, LBL_E_INVAL, "fd_noise must be LBL_FDNOISE_LINK or LBL_FDNOISE_FOURIER");
+  if (p->fd_noise == LBL_FDNOISE_FOURIER && p->smol != LBL_SMOL_FD)
+    return fail(nullptr, LBL_E_INVAL, "Fourier-space noise is an option of the FD variant");
   if (in->kind < LBL_INIT_REST || in->kind > LBL_INIT_USER)
     return fail(nullptr, LBL_E_INVAL, "unknown init kind");
   if (in->kind == LBL_INIT_TANH_2IF && !(p->a < 0 && p->b > 0 && p->kappa > 0))
@@ -335,8 +351,81 @@ struct Impl {
     return LBL_OK;
   }
 
+  static bool fourier(const lbl_sim* s) {
+    return SMOL == kFD && s->p.fd_noise == LBL_FDNOISE_FOURIER;
+  }
+
+  static int fft_check(lbl_sim* s, hipfftResult r, const char* what) {
+    if (r == HIPFFT_SUCCESS) return LBL_OK;
+    return fail(s, LBL_E_DEVICE, std::string(what) + ": hipFFT error " + std::to_string(r));
+  }
+
+  // FD noise in Fourier space: plans of the real-to-complex pair on the
+  // simulation's stream and the amplitude table, once per simulation.
+  static int fourier_setup(lbl_sim* s) {
+    if (!fourier(s)) return LBL_OK;
+    constexpr bool dbl = sizeof(S) == 8;
+    const hipfftType tf = dbl ? HIPFFT_D2Z : HIPFFT_R2C, ti = dbl ? HIPFFT_Z2D : HIPFFT_C2R;
+    const lbl_params& p = s->p;
+    for (int k = 0; k < 2; ++k) {
+      hipfftHandle& h = k == 0 ? s->fft_fwd : s->fft_inv;
+      const hipfftType t = k == 0 ? tf : ti;
+      // x varies fastest: the transform's dimensions are (nz, ny, nx).
+      const hipfftResult r = Lat<Q>::D == 3 ? hipfftPlan3d(&h, p.nz, p.ny, p.nx, t)
+                                            : hipfftPlan2d(&h, p.ny, p.nx, t);
+      if (r != HIPFFT_SUCCESS) h = nullptr;
+      if (int rc = fft_check(s, r, "hipfftPlan")) return rc;
+      if (int rc = fft_check(s, hipfftSetStream(h, s->stream), "hipfftSetStream")) return rc;
+    }
+    const int nh = static_cast<int>(half_spectrum(p));
+    const Geom g = geom(s);
+    const double two_kT_M = 2.0 * p.kT * p.M;
+    S* amp = static_cast<S*>(s->famp);
+    k_fourier_amp<S, Lat<Q>::D><<<(nh + 255) / 256, 256, 0, s->stream>>>(g, two_kT_M, amp);
+    return launched(s, "k_fourier_amp");
+  }
+
+  // N^n = F^-1[ amp F[w] ] into s->noise.
+  static int fourier_noise(lbl_sim* s, uint32_t step) {
+    S* w = static_cast<S*>(s->noise);
+    S* spec = static_cast<S*>(s->fspec);
+    const int nh = static_cast<int>(half_spectrum(s->p));
+    const hipStream_t st = s->stream;
+    if (int rc = launch(s, "k_white", [&] {
+          k_white<S><<<(s->N + 255) / 256, 256, 0, st>>>(s->N, step, s->k0, s->k1, w);
+        }))
+      return rc;
+    hipfftResult r = HIPFFT_SUCCESS;
+    if (int rc = launch(s, "fft", [&] {
+          if constexpr (sizeof(S) == 8)
+            r = hipfftExecD2Z(s->fft_fwd, reinterpret_cast<hipfftDoubleReal*>(w),
+                              reinterpret_cast<hipfftDoubleComplex*>(spec));
+          else
+            r = hipfftExecR2C(s->fft_fwd, reinterpret_cast<hipfftReal*>(w),
+                              reinterpret_cast<hipfftComplex*>(spec));
+        }))
+      return rc;
+    if (int rc = fft_check(s, r, "forward FFT")) return rc;
+    if (int rc = launch(s, "k_fourier_scale", [&] {
+          k_fourier_scale<S><<<(nh + 255) / 256, 256, 0, st>>>(
+              nh, static_cast<const S*>(s->famp), spec);
+        }))
+      return rc;
+    if (int rc = launch(s, "fft", [&] {
+          if constexpr (sizeof(S) == 8)
+            r = hipfftExecZ2D(s->fft_inv, reinterpret_cast<hipfftDoubleComplex*>(spec),
+                              reinterpret_cast<hipfftDoubleReal*>(w));
+          else
+            r = hipfftExecC2R(s->fft_inv, reinterpret_cast<hipfftComplex*>(spec),
+                              reinterpret_cast<hipfftReal*>(w));
+        }))
+      return rc;
+    return fft_check(s, r, "inverse FFT");
+  }
+
   static int init(lbl_sim* s, const lbl_init* in) {
     if (int rc = default_chunks(s)) return rc;
+    if (int rc = fourier_setup(s)) return rc;
     const Geom g = geom(s);
     const int grid = grid_for(s->N);
     S* f = static_cast<S*>(s->f[0]);
@@ -465,8 +554,11 @@ struct Impl {
                                       (s->lb_swizzle & 2) != 0);
     const dim3 tg(tile_map_blocks(tm)), tgp(tile_map_blocks(tmp)), tb(kTX, kTY);
     const bool want_noise = cpl != LBL_LB_ONLY && s->p.kT > 0;
+    const bool prep_noise = want_noise && !fourier(s);
     const bool want_mu = cpl == LBL_FULL;
-    if (want_noise || want_mu) {
+    if (want_noise && !prep_noise)
+      if (int rc = fourier_noise(s, n)) return rc;
+    if (prep_noise || want_mu) {
       PrepArgs<S> pa;
       pa.g = g;
       pa.c = coef(s);
@@ -476,7 +568,7 @@ struct Impl {
       pa.step = n;
       pa.zc = s->zc_prep;
       pa.psi = psin;
-      pa.noise = want_noise ? noise : nullptr;
+      pa.noise = prep_noise ? noise : nullptr;
       pa.mu = want_mu ? static_cast<S*>(s->mu) : nullptr;
       int rc;
       if (SMOL == kFV)
@@ -813,7 +905,10 @@ std::vector<size_t> alloc_plan(const lbl_params& p) {
           sz * N * d, sz * N, sizeof(double) * 10 * nparts, sizeof(double) * 16,
           sizeof(double) * kMaxFields * 3 * Lmax,
           sizeof(double) * kMaxFields * static_cast<size_t>(p.nz) * p.nx,
-          sizeof(double) * 2 * d * Lmax, sizeof(double) * 2 * d * d * Lmax, sz * N * d};
+          sizeof(double) * 2 * d * Lmax, sizeof(double) * 2 * d * d * Lmax, sz * N * d,
+          // FD noise in Fourier space: half spectrum (complex) and amplitude table
+          p.fd_noise == LBL_FDNOISE_FOURIER ? 2 * sz * half_spectrum(p) : 0,
+          p.fd_noise == LBL_FDNOISE_FOURIER ? sz * half_spectrum(p) : 0};
 }
 
 size_t obs_bytes(const lbl_sim* s, int what) {
@@ -921,6 +1016,8 @@ int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* e
     s->sk = static_cast<double*>(bufs[14]);
     s->uk = static_cast<double*>(bufs[15]);
     s->u_end = bufs[16];
+    s->fspec = bufs[17];
+    s->famp = bufs[18];
   }
   if (!ok) {
     std::string msg = "device allocation failed";
@@ -1555,6 +1652,8 @@ int lbl_pool_submit(lbl_pool* pl, const lbl_params* params, const lbl_init* init
   if (int rc = validate(params, init)) return pool_fail(pl, rc, g_create_error);
   if (params->sample_every != 0)
     return pool_fail(pl, LBL_E_INVAL, "pool requests report the final state (sample_every 0)");
+  if (params->fd_noise != LBL_FDNOISE_LINK)
+    return pool_fail(pl, LBL_E_INVAL, "Fourier-space FD noise runs in single simulations only");
   PoolReq r;
   r.id = pl->next_id++;
   r.p = *params;

@@ -723,6 +723,57 @@ __global__ __launch_bounds__(kTX* kTY) void k_prep_fd(PrepArgs<S> a, TileMap m) 
 }
 
 // ---------------------------------------------------------------------------
+// FD noise built in Fourier space (Sec. V.A, Eq. etafdt):
+//   N = F^-1[ sqrt(-2 kT M L_SO(q)) F[w] ],  w(x) = normal slot 0 (SMOL stream).
+// The transforms are hipFFT's real-to-complex pair (half spectrum of
+// nz x ny x (nx/2 + 1) values, x fastest); these kernels draw w, build the
+// amplitude table once (the 1/N of the unnormalised inverse folded in) and
+// apply it to the spectrum.
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(256) void k_white(int n, uint32_t step, uint32_t k0, uint32_t k1,
+                                               S* __restrict__ w) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= n) return;
+  S z[4];
+  Normal4<S>::gen2(static_cast<uint32_t>(s), step, 0, kTagSMOL, k0, k1, z);
+  w[s] = z[0];
+}
+
+// Symbol of the Shinozaki-Oono Laplacian: Eq. (solapft) in 3-D,
+// cos q_x + cos q_y + cos q_x cos q_y - 3 in 2-D.
+template <typename S, int D>
+__global__ __launch_bounds__(256) void k_fourier_amp(Geom g, double two_kT_M,
+                                                     S* __restrict__ amp) {
+  const int hx = g.nx / 2 + 1;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= hx * g.ny * g.nz) return;
+  const int kx = i % hx, ky = (i / hx) % g.ny, kz = i / (hx * g.ny);
+  const double cx = cospi(2.0 * kx / g.nx), cy = cospi(2.0 * ky / g.ny);
+  double L;
+  if constexpr (D == 3) {
+    const double cz = cospi(2.0 * kz / g.nz);
+    L = (12.0 * (cx + cy + cz) + 12.0 * (cx * cy + cx * cz + cy * cz) + 8.0 * cx * cy * cz -
+         80.0) / 22.0;
+  } else {
+    L = cx + cy + cx * cy - 3.0;
+  }
+  const double v = -two_kT_M * L;
+  amp[i] = S((v > 0.0 ? sqrt(v) : 0.0) / static_cast<double>(g.N));
+}
+
+// spec[i] *= amp[i] on the interleaved (re, im) half spectrum.
+template <typename S>
+__global__ __launch_bounds__(256) void k_fourier_scale(int nh, const S* __restrict__ amp,
+                                                       S* __restrict__ spec) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nh) return;
+  const S a = amp[i];
+  spec[2 * i] *= a;
+  spec[2 * i + 1] *= a;
+}
+
+// ---------------------------------------------------------------------------
 // One SMOL Runge-Kutta stage with frozen u^n and N^n (Sec. V):
 //   G(phi) = -Div(u phi) + M L_out mu(phi) + N.
 // Combination: mode kComb: out = psi_n + cnext G (and acc update when

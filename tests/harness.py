@@ -40,7 +40,7 @@ def lbl_params(c, sample_every=0):
                            rho=c["rho"], eta=c["eta"], M=c["M"], a=c["a"], b=c["b"],
                            kappa=c["kappa"], kT=c["kT"], omega_bulk=c["omega_bulk"],
                            omega_ghost=c["omega_ghost"], u_imposed=c["u_imposed"],
-                           seed=c["seed"], sample_every=sample_every)
+                           seed=c["seed"], sample_every=sample_every, fd_noise=c["fd_noise"])
 
 
 def oracle_run(c, nsteps, f=None, psi=None):

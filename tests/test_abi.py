@@ -57,7 +57,7 @@ int main(void) {
 
 
 def test_constants_and_strings():
-    assert lbl.lbl_abi_version() == 2
+    assert lbl.lbl_abi_version() == 3
     assert lbl.lbl_strerror(0) == "ok"
     assert "buffer" in lbl.lbl_strerror(lbl.LBL_E_BUFSIZE)
     assert lbl.lbl_strerror(12345) == "unknown status"
@@ -66,7 +66,8 @@ def test_constants_and_strings():
 @pytest.mark.parametrize("field,value", [
     ("lattice", 27), ("lattice", 0), ("smol", 2), ("precision", 3), ("coupling", 7), ("rk_stages", 3),
     ("nx", 3), ("nz", 2), ("eta", -1.0), ("rho", 0.0), ("kT", -1e-5), ("omega_bulk", 2.5),
-    ("omega_ghost", 0.0), ("M", float("nan")), ("reserved", 1), ("sample_every", -2),
+    ("omega_ghost", 0.0), ("M", float("nan")), ("fd_noise", 2), ("fd_noise", -1),
+    ("sample_every", -2),
 ])
 def test_invalid_parameters_rejected(field, value):
     p = lbl.make_params(lattice=lbl.LBL_D3Q19, shape=(8, 8, 8))
@@ -75,6 +76,14 @@ def test_invalid_parameters_rejected(field, value):
     assert rc == lbl.LBL_E_INVAL
     assert not h.value
     assert lbl.lbl_last_error(None)
+
+
+def test_fourier_noise_is_an_fd_option():
+    p = lbl.make_params(lattice=lbl.LBL_D3Q19, smol=lbl.LBL_SMOL_FV, shape=(8, 8, 8),
+                        fd_noise=lbl.LBL_FDNOISE_FOURIER)
+    rc, h = lbl.lbl_create(p, lbl.make_init(), lbl.lbl_env())
+    assert rc == lbl.LBL_E_INVAL and not h.value
+    assert "FD" in lbl.lbl_last_error(None)
 
 
 def test_invalid_init_rejected():

@@ -136,10 +136,12 @@ DIAGS = ((1, 1, 1), (1, 1, -1), (1, -1, 1), (-1, 1, 1))
 
 # Fig. test1a / test1upsi / test1b ------------------------------------------
 
-@pytest.mark.parametrize("coupling,smol", [(H.SMOL_ONLY, H.FD), (H.SMOL_ONLY, H.FV),
-                                           (H.FULL, H.FD), (H.FULL, H.FV)])
-def test_quadratic_free_energy_equilibrium_ratio(coupling, smol):
-    c = _paper(smol=smol, coupling=coupling, a=0.625, kappa=0.0, M=0.095)
+@pytest.mark.parametrize("coupling,smol,fd_noise", [(H.SMOL_ONLY, H.FD, 0), (H.SMOL_ONLY, H.FV, 0),
+                                                    (H.FULL, H.FD, 0), (H.FULL, H.FV, 0),
+                                                    (H.SMOL_ONLY, H.FD, 1), (H.FULL, H.FD, 1)])
+def test_quadratic_free_energy_equilibrium_ratio(coupling, smol, fd_noise):
+    """fd_noise = 1 runs the FD noise as the paper builds it, in Fourier space."""
+    c = _paper(smol=smol, coupling=coupling, a=0.625, kappa=0.0, M=0.095, fd_noise=fd_noise)
     print("ER case", c, flush=True)
     Q = _qgrid(SHAPE)
     s_th, absR, oz = _stationary(c, Q)

@@ -212,3 +212,19 @@ def test_wide_lattice_schedules_do_not_change_results():
     for f, p in out[1:]:
         np.testing.assert_array_equal(f, out[0][0])
         np.testing.assert_array_equal(p, out[0][1])
+
+
+@pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q15, H.D3Q19])
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
+def test_fd_fourier_noise(lattice, precision):
+    """FD noise built in Fourier space (hipFFT on the GPU, a plain DFT in the
+    oracle) on lattices with odd sides, full coupling, two-phase."""
+    c = H.config(lattice=lattice, smol=H.FD, precision=precision, shape=SHAPES[lattice],
+                 a=-0.04, b=0.04, init=1, kT=1e-4, fd_noise=1)
+    _check(c, 12)
+
+
+def test_fd_fourier_noise_smol_only_rk4():
+    c = H.config(lattice=H.D3Q19, smol=H.FD, coupling=H.SMOL_ONLY, rk=4, shape=(15, 12, 9),
+                 kT=1e-4, u_imposed=(0.02, -0.01, 0.03), fd_noise=1)
+    _check(c, 10)

@@ -100,6 +100,28 @@ def test_smol_static_structure_factor(lattice, smol, shape, precision):
     assert np.all(np.abs(r - 1) < 0.25)
 
 
+@pytest.mark.parametrize("lattice,shape", [(H.D2Q9, (64, 48, 1)), (H.D3Q19, (24, 20, 16))])
+def test_fd_fourier_noise_structure_factor(lattice, shape):
+    """The paper-literal Fourier-space FD noise and the link-flux realisation
+    (R5) give the same static S(k), the exact discrete-time form."""
+    from paper_1104_0078_amd import lbl
+    d = 2 if lattice == H.D2Q9 else 3
+    means = {}
+    for fdn in (1, 0):
+        c = H.config(lattice=lattice, smol=H.FD, coupling=H.SMOL_ONLY, shape=shape, kT=1e-4,
+                     a=0.5, b=0.0, kappa=0.1, M=0.2, psi_std=0.0, fd_noise=fdn)
+        with _sim(c, sample_every=3) as sim:
+            sim.step(30000)
+            sk = sim.observe(lbl.LBL_OBS_SK_AXES)
+        r = _sk_compare(sk, _sk_theory(c, shape), shape, d)
+        means[fdn] = r.mean()
+        print("  fd_noise %d: S/S_theory mean %.4f min %.3f max %.3f" % (fdn, r.mean(), r.min(),
+                                                                        r.max()), flush=True)
+        assert abs(r.mean() - 1) < 0.03
+        assert np.all(np.abs(r - 1) < 0.25)
+    assert abs(means[1] / means[0] - 1) < 0.03
+
+
 @pytest.mark.parametrize("smol", [H.FD, H.FV])
 def test_galilean_invariance_ma008(smol):
     from paper_1104_0078_amd import lbl
