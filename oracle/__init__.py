@@ -22,6 +22,7 @@ FULL, SMOL_ONLY, LB_ONLY = 0, 1, 2
 D2Q9, D3Q15, D3Q19 = 9, 15, 19
 TAG_LB, TAG_SMOL, TAG_INIT = 0, 1, 2
 FDNOISE_LINK, FDNOISE_FOURIER = 0, 1
+FORCE_PSI_GRAD_MU, FORCE_STRESS = 0, 1
 
 
 class Params(ctypes.Structure):
@@ -35,6 +36,7 @@ class Params(ctypes.Structure):
         ("kT", ctypes.c_double), ("omega_bulk", ctypes.c_double),
         ("omega_ghost", ctypes.c_double), ("u_imposed", ctypes.c_double * 3),
         ("seed", ctypes.c_uint64),
+        ("force_form", ctypes.c_int32), ("pad1", ctypes.c_int32),
     ]
 
 
@@ -71,6 +73,7 @@ def lib():
             "orc_velocity": (None, [P, dp, dp, dp]),
             "orc_fd_noise_divergence": (None, [P, dp, dp]),
             "orc_fd_noise_fourier": (None, [P, dp, dp]),
+            "orc_stress": (None, [P, dp, dp]),
             "orc_smol_noise": (None, [P, ctypes.c_uint32, dp]),
             "orc_collide": (None, [P, dp, dp, dp, dp]),
             "orc_smol_rhs": (None, [P, dp, dp, dp, dp]),
@@ -96,11 +99,12 @@ def _dp(a):
 def make_params(lattice=D2Q9, smol=FD, coupling=FULL, rk_stages=2, shape=(16, 16, 1),
                 rho0=1.0, eta=0.1, M=0.1, a=0.04, b=0.1, kappa=0.05, kT=1e-5,
                 omega_bulk=1.0, omega_ghost=1.0, u_imposed=(0.0, 0.0, 0.0), seed=1234,
-                fd_noise=FDNOISE_LINK):
+                fd_noise=FDNOISE_LINK, force_form=FORCE_PSI_GRAD_MU):
     nx, ny, nz = (tuple(shape) + (1, 1, 1))[:3]
     p = Params()
     p.lattice, p.smol, p.coupling, p.rk_stages = lattice, smol, coupling, rk_stages
     p.fd_noise = fd_noise
+    p.force_form = force_form
     p.nx, p.ny, p.nz = nx, ny, nz
     p.rho0, p.eta, p.M, p.a, p.b, p.kappa, p.kT = rho0, eta, M, a, b, kappa, kT
     p.omega_bulk, p.omega_ghost = omega_bulk, omega_ghost
@@ -182,6 +186,12 @@ def chemical_potential(p, psi):
 
 def force(p, psi):
     return _unary("orc_force", p, psi, (d_of(p), nsites(p)))
+
+
+def stress(p, psi):
+    """Order-parameter stress of Eq. (muf), full d x d tensor per site."""
+    d = d_of(p)
+    return _unary("orc_stress", p, psi, (d, d, nsites(p)))
 
 
 def velocity(p, f, F):

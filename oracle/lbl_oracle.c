@@ -372,9 +372,56 @@ void orc_chemical_potential(const orc_params *p, const double *psi, double *mu) 
  * minus sign; only the minus sign makes free energy plus kinetic energy
  * non-increasing at kT = 0.  The gradient is the variant's own (Sec. IV for
  * FD; Eq. (fvgrad) for FV). */
+/* Order-parameter stress of Eq. (muf), with the variant's own gradient g of
+ * psi (orc_gradient) and the Shinozaki-Oono Laplacian:
+ *   sigma_ab = K g_a g_b + delta_ab [psi f'(psi) - f - K psi L psi - K/2 |g|^2],
+ * f = A psi^2/2 + B psi^4/4, so psi f' - f = A psi^2/2 + 3 B psi^4/4.  Stored
+ * as the full d x d tensor, sig[(a*d + b)*N + s]. */
+void orc_stress(const orc_params *p, const double *psi, double *sig) {
+  int64_t N = nsites(p);
+  int d = orc_d(p->lattice);
+  double *g = (double *)malloc(sizeof(double) * N * d);
+  double *lap = (double *)malloc(sizeof(double) * N);
+  orc_gradient(p, psi, g);
+  orc_laplacian(p, psi, lap);
+  for (int64_t s = 0; s < N; s++) {
+    const double ps = psi[s];
+    double g2 = 0.0;
+    for (int c = 0; c < d; c++) g2 += g[c * N + s] * g[c * N + s];
+    const double iso = 0.5 * p->a * ps * ps + 0.75 * p->b * ps * ps * ps * ps -
+                       p->kappa * ps * lap[s] - 0.5 * p->kappa * g2;
+    for (int a = 0; a < d; a++)
+      for (int b = 0; b < d; b++)
+        sig[(a * d + b) * N + s] = p->kappa * g[a * N + s] * g[b * N + s] + (a == b ? iso : 0.0);
+  }
+  free(g);
+  free(lap);
+}
+
+/* Force density on the fluid.  ORC_FORCE_PSI_GRAD_MU (Sec. IV, the paper's
+ * discretisation): F = -psi grad mu with the variant's gradient.
+ * ORC_FORCE_STRESS: F_a = -sum_b G_b sigma_ab, the divergence of the stress
+ * of Eq. (muf) taken with the same gradient operator; equal to -psi grad mu
+ * in the continuum, and its sum over the lattice vanishes exactly for any B
+ * (every term is a difference of shifted copies). */
 void orc_force(const orc_params *p, const double *psi, double *F) {
   int64_t N = nsites(p);
   int d = orc_d(p->lattice);
+  if (p->force_form == ORC_FORCE_STRESS) {
+    double *sig = (double *)malloc(sizeof(double) * N * d * d);
+    double *gs = (double *)malloc(sizeof(double) * N * d);
+    orc_stress(p, psi, sig);
+    for (int64_t k = 0; k < N * d; k++) F[k] = 0.0;
+    for (int a = 0; a < d; a++) {
+      for (int b = 0; b < d; b++) {
+        orc_gradient(p, sig + (int64_t)(a * d + b) * N, gs); /* gs[c] = G_c sigma_ab */
+        for (int64_t s = 0; s < N; s++) F[a * N + s] -= gs[b * N + s];
+      }
+    }
+    free(sig);
+    free(gs);
+    return;
+  }
   double *mu = (double *)malloc(sizeof(double) * N);
   double *g = (double *)malloc(sizeof(double) * N * d);
   orc_chemical_potential(p, psi, mu);

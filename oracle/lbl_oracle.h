@@ -32,6 +32,7 @@ enum { ORC_FD = 0, ORC_FV = 1 };
 enum { ORC_FULL = 0, ORC_SMOL_ONLY = 1, ORC_LB_ONLY = 2 };
 enum { ORC_TAG_LB = 0, ORC_TAG_SMOL = 1, ORC_TAG_INIT = 2 };
 enum { ORC_FDNOISE_LINK = 0, ORC_FDNOISE_FOURIER = 1 };
+enum { ORC_FORCE_PSI_GRAD_MU = 0, ORC_FORCE_STRESS = 1 };
 
 typedef struct orc_params {
   int32_t lattice;     /* ORC_D2Q9, ORC_D3Q15 or ORC_D3Q19 */
@@ -49,6 +50,8 @@ typedef struct orc_params {
   double omega_ghost;  /* relaxation rate of every ghost mode */
   double u_imposed[3]; /* uniform advecting velocity used when coupling == ORC_SMOL_ONLY */
   uint64_t seed;
+  int32_t force_form;  /* ORC_FORCE_PSI_GRAD_MU or ORC_FORCE_STRESS */
+  int32_t pad1;
 } orc_params;
 
 /* Lattice tables and mode basis. */
@@ -69,6 +72,7 @@ void orc_gradient(const orc_params *p, const double *in, double *out /* d*N */);
 void orc_divergence(const orc_params *p, const double *in /* d*N */, double *out);
 void orc_chemical_potential(const orc_params *p, const double *psi, double *mu);
 void orc_force(const orc_params *p, const double *psi, double *F /* d*N */);
+void orc_stress(const orc_params *p, const double *psi, double *sig /* d*d*N */);
 void orc_velocity(const orc_params *p, const double *f, const double *F, double *u /* d*N */);
 
 /* Noise fields. */

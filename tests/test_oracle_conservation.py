@@ -57,6 +57,53 @@ def test_momentum_conserved_without_quartic_term(lattice, smol, shape):
         np.testing.assert_allclose(P1, P0, atol=1e-14 * np.abs(_momentum(p, f)).sum())
 
 
+@pytest.mark.parametrize("lattice,smol,shape", CASES)
+def test_stress_force_conserves_momentum_with_quartic_term(lattice, smol, shape):
+    """The divergence of the stress of Eq. (muf) sums to zero over the lattice
+    for any B (every term is a difference of shifted copies), where -psi grad
+    mu does not; the momentum of a two-phase run is then constant."""
+    kw = dict(lattice=lattice, smol=smol, shape=shape, a=-0.04, b=0.04, kappa=0.05, kT=1e-4,
+              M=0.1)
+    p = O.make_params(force_form=O.FORCE_STRESS, **kw)
+    pg = O.make_params(**kw)
+    f, psi = O.init(p, 0, 0.3)
+    F, Fg = O.force(p, psi), O.force(pg, psi)
+    assert np.abs(F.sum(axis=1)).max() <= 1e-15 * np.abs(F).sum()
+    assert np.abs(Fg.sum(axis=1)).max() > 1e-9 * np.abs(Fg).sum()
+    sig = O.stress(p, psi)
+    np.testing.assert_allclose(sig, sig.transpose(1, 0, 2), rtol=1e-15, atol=1e-18)
+    for n in range(8):
+        P0 = _momentum(p, f).sum(axis=1)
+        O.step(p, f, psi, n)
+        P1 = _momentum(p, f).sum(axis=1)
+        np.testing.assert_allclose(P1, P0, atol=1e-14 * np.abs(_momentum(p, f)).sum())
+
+
+@pytest.mark.parametrize("lattice,smol", [(O.D2Q9, O.FD), (O.D2Q9, O.FV), (O.D3Q19, O.FD),
+                                          (O.D3Q19, O.FV), (O.D3Q15, O.FV)])
+def test_stress_force_is_psi_grad_mu_in_the_continuum(lattice, smol):
+    """On a smooth field the two discrete forces differ by O(h^2): doubling
+    the resolution of the same profile cuts their difference about 4x
+    (Eq. muf: div sigma = psi grad mu in the continuum)."""
+    errs = []
+    for L in (24, 48):
+        d = 2 if lattice == O.D2Q9 else 3
+        shape = (L, L, 1) if d == 2 else (L, L, 8)
+        kw = dict(lattice=lattice, smol=smol, shape=shape, a=-0.3, b=0.5, kappa=0.8)
+        p, pg = O.make_params(force_form=O.FORCE_STRESS, **kw), O.make_params(**kw)
+        N = O.nsites(p)
+        x = np.arange(N) % L
+        y = (np.arange(N) // L) % L
+        h = 2 * np.pi / L
+        psi = 0.6 * np.sin(h * x) + 0.4 * np.cos(h * y) * np.sin(h * x + 0.3)
+        # the same physical field at twice the resolution: gradients scale by h
+        F, Fg = O.force(p, psi), O.force(pg, psi)
+        errs.append(np.abs(F - Fg).max() / np.abs(Fg).max())
+    ratio = errs[0] / errs[1]
+    assert errs[0] < 0.08
+    assert 3.2 < ratio < 4.8, (errs, ratio)
+
+
 def _energy(p, f, psi):
     F = O.force(p, psi)
     rho = f.sum(axis=0)
