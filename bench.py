@@ -143,7 +143,7 @@ def make_sim_params(lbl, w, precision=None, seed=1234):
                            precision=w["precision"] if precision is None else precision,
                            shape=w["shape"], rho=1.0, eta=w["eta"], M=w["M"], a=w["a"],
                            b=w["b"], kappa=w["kappa"], kT=w["kT"], seed=seed,
-                           fd_noise=w.get("fd_noise", 0))
+                           fd_noise=w.get("fd_noise", 0), force_form=w.get("force_form", 0))
 
 
 def run_single(lbl, torch, w, wname, steps, warmup, tune, precision=None, schedule=None):
@@ -343,6 +343,8 @@ def main():
                     help="skip the FP32-deviation run of the same lattice")
     ap.add_argument("--no-fd-noise", action="store_true",
                     help="skip the FD variant of the same lattice (link vs Fourier noise)")
+    ap.add_argument("--no-stress", action="store_true",
+                    help="skip the run of the same workload with the stress-divergence force")
     ap.add_argument("--no-tune", action="store_true", help="no autotuning of the pool legs")
     ap.add_argument("--tune-single", action="store_true",
                     help="autotune the single-run schedule too (default: the library's own)")
@@ -454,6 +456,16 @@ def main():
         out["fd_noise_same_lattice"] = legs
         print("fd noise legs done: link %.1f, Fourier %.1f MLUPS" % (
             legs["link"]["value"], legs["fourier"]["value"]), file=sys.stderr, flush=True)
+    if not args.no_stress:
+        # The same workload with the force as the divergence of the stress of
+        # Eq. (muf) (momentum conserved exactly; two more per-site passes).
+        nst = min(args.steps, 30)
+        rs_ = run_single(lbl, torch, dict(w, force_form=1), args.workload, nst, args.warmup, False)
+        out["stress_force_same_workload"] = {
+            "value": round(rs_["mlups"], 2), "unit": "MLUPS",
+            "ms_per_step": round(rs_["ms_per_step"], 4),
+            "kernels_ms_per_step": {t[0]: round(t[2] / nst, 4) for t in rs_["ktimes"]}}
+        print("stress force leg done: %.1f MLUPS" % rs_["mlups"], file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = {}
         for prec, name in ((1, "fp32"), (0, "fp64")):

@@ -102,8 +102,23 @@ typedef struct lbl_params {
   double u_imposed[3];
   uint64_t seed;
   int32_t sample_every;
-  int32_t fd_noise; /* enum lbl_fd_noise; LBL_FDNOISE_LINK unless smol == LBL_SMOL_FD */
+  int32_t fd_noise;   /* enum lbl_fd_noise; LBL_FDNOISE_LINK unless smol == LBL_SMOL_FD */
+  int32_t force_form; /* enum lbl_force_form */
+  int32_t reserved;   /* must be 0 */
 } lbl_params;
+
+/* Force density of the order parameter on the fluid (full coupling):
+ *  PSI_GRAD_MU (default, the paper's discretisation, Sec. IV): F = -psi G mu
+ *    with the variant's gradient G (FD central difference, FV Gamma).  Its
+ *    lattice sum vanishes when B = 0 but not otherwise;
+ *  STRESS: F_a = -sum_b G_b sigma_ab with sigma the stress of Eq. (muf),
+ *    sigma_ab = K g_a g_b + delta_ab [A psi^2/2 + 3 B psi^4/4 - K psi L psi
+ *    - K/2 |g|^2], g = G psi, L the Shinozaki-Oono Laplacian.  Equal to the
+ *    default in the continuum (to second order in the lattice spacing); its
+ *    lattice sum vanishes for any B, so momentum is conserved exactly.  Two
+ *    extra per-site passes per step; single simulations only (a pool refuses
+ *    such a request). */
+enum lbl_force_form { LBL_FORCE_PSI_GRAD_MU = 0, LBL_FORCE_STRESS = 1 };
 
 /* How the FD variant builds its conserved noise N^n (Sec. V.A), both with
  * covariance -2 kT M L_SO (Eq. etafdt):
@@ -180,8 +195,9 @@ int lbl_step(lbl_sim *sim, int64_t nsteps);
 enum lbl_observable {
   LBL_OBS_PSI = 0,      /* N FP64: psi */
   LBL_OBS_RHO = 1,      /* N FP64: rho = sum_i fbar_i */
-  LBL_OBS_U = 2,        /* d*N FP64: u = (sum_i fbar_i c_i + F/2)/rho, F = -psi grad mu
-                           (F = 0 for LB_ONLY; u_imposed for SMOL_ONLY) */
+  LBL_OBS_U = 2,        /* d*N FP64: u = (sum_i fbar_i c_i + F/2)/rho, F the force
+                           density of lbl_params.force_form (F = 0 for LB_ONLY;
+                           u_imposed for SMOL_ONLY) */
   LBL_OBS_POP = 3,      /* Q*N FP64: fbar, canonical order */
   LBL_OBS_TOTALS = 4,   /* 10 FP64: mass, Px, Py, Pz, Psi, then the L1 norms
                            sum|rho|, sum|jx|, sum|jy|, sum|jz|, sum|psi|,

@@ -55,6 +55,8 @@ struct lbl_sim {
   void* fspec = nullptr;  // FD noise in Fourier space: half spectrum (interleaved re, im)
   void* famp = nullptr;   // and its amplitude table sqrt(-2 kT M L(q)) / N
   hipfftHandle fft_fwd = nullptr, fft_inv = nullptr;
+  void* sig = nullptr;      // force_form STRESS: order-parameter stress, d(d+1)/2 components
+  void* fstress = nullptr;  // and its divergence, the force density (d*N)
   double* part = nullptr;
   int nparts = 0;
   double* tot = nullptr;
@@ -284,6 +286,10 @@ int validate(const lbl_params* p, const lbl_init* in) {
     return fail(nullptr, LBL_E_INVAL, "fd_noise must be LBL_FDNOISE_LINK or LBL_FDNOISE_FOURIER");
   if (p->fd_noise == LBL_FDNOISE_FOURIER && p->smol != LBL_SMOL_FD)
     return fail(nullptr, LBL_E_INVAL, "Fourier-space noise is an option of the FD variant");
+  if (p->force_form != LBL_FORCE_PSI_GRAD_MU && p->force_form != LBL_FORCE_STRESS)
+    return fail(nullptr, LBL_E_INVAL,
+                "force_form must be LBL_FORCE_PSI_GRAD_MU or LBL_FORCE_STRESS");
+  if (p->reserved != 0) return fail(nullptr, LBL_E_INVAL, "reserved must be 0");
   if (in->kind < LBL_INIT_REST || in->kind > LBL_INIT_USER)
     return fail(nullptr, LBL_E_INVAL, "unknown init kind");
   if (in->kind == LBL_INIT_TANH_2IF && !(p->a < 0 && p->b > 0 && p->kappa > 0))
@@ -494,6 +500,8 @@ struct Impl {
     a.k1 = s->k1;
     a.step = step;
     a.force = force;
+    a.Fext = force && s->p.force_form == LBL_FORCE_STRESS ? static_cast<const S*>(s->fstress)
+                                                          : nullptr;
     a.noise = s->p.kT > 0;
     a.nt = 2.0 * sizeof(S) * s->q * static_cast<double>(s->N) > kStreamBytes;
     return a;
@@ -528,6 +536,22 @@ struct Impl {
     });
   }
 
+  // Force density as the divergence of the order-parameter stress of psi
+  // into s->fstress (force_form STRESS).
+  static int stress_force(lbl_sim* s, const S* psi) {
+    const dim3 grid = site_grid(s), block(kBX, kBY);
+    const Geom g = geom(s);
+    const Coef<S> c = coef(s);
+    S* sig = static_cast<S*>(s->sig);
+    if (int rc = launch(s, "k_stress", [&] {
+          k_stress<S, Q, SMOL><<<grid, block, 0, s->stream>>>(g, c, psi, sig);
+        }))
+      return rc;
+    return launch(s, "k_force_stress", [&] {
+      k_force_stress<S, Q, SMOL><<<grid, block, 0, s->stream>>>(g, sig, static_cast<S*>(s->fstress));
+    });
+  }
+
   static int launch_mu(lbl_sim* s, const S* phi, S* mu) {
     const dim3 grid = site_grid(s), block(kBX, kBY);
     const Geom g = geom(s);
@@ -555,7 +579,10 @@ struct Impl {
     const dim3 tg(tile_map_blocks(tm)), tgp(tile_map_blocks(tmp)), tb(kTX, kTY);
     const bool want_noise = cpl != LBL_LB_ONLY && s->p.kT > 0;
     const bool prep_noise = want_noise && !fourier(s);
-    const bool want_mu = cpl == LBL_FULL;
+    const bool stress = cpl == LBL_FULL && s->p.force_form == LBL_FORCE_STRESS;
+    const bool want_mu = cpl == LBL_FULL && !stress;
+    if (stress)
+      if (int rc = stress_force(s, psin)) return rc;
     if (want_noise && !prep_noise)
       if (int rc = fourier_noise(s, n)) return rc;
     if (prep_noise || want_mu) {
@@ -826,8 +853,11 @@ struct Impl {
         if (s->p.coupling == LBL_SMOL_ONLY) return LBL_E_UNSUPPORTED;
         S* ubuf = static_cast<S*>(s->u);
         const int full = s->p.coupling == LBL_FULL;
-        if (full)
+        if (full && s->p.force_form == LBL_FORCE_STRESS) {
+          if (int rc = stress_force(s, psi)) return rc;
+        } else if (full) {
           if (int rc = launch_mu(s, psi, static_cast<S*>(s->mu))) return rc;
+        }
         const LBArgs<S> a = lb_args(s, f, nullptr, psi, ubuf, full, 0);
         if (int rc = launch_lb(s, a, false, "k_lb_u")) return rc;
         k_to_f64<S><<<grid_for(s->d * s->N), kBlock, 0, s->stream>>>(s->d * s->N, ubuf, dst);
@@ -908,7 +938,10 @@ std::vector<size_t> alloc_plan(const lbl_params& p) {
           sizeof(double) * 2 * d * Lmax, sizeof(double) * 2 * d * d * Lmax, sz * N * d,
           // FD noise in Fourier space: half spectrum (complex) and amplitude table
           p.fd_noise == LBL_FDNOISE_FOURIER ? 2 * sz * half_spectrum(p) : 0,
-          p.fd_noise == LBL_FDNOISE_FOURIER ? sz * half_spectrum(p) : 0};
+          p.fd_noise == LBL_FDNOISE_FOURIER ? sz * half_spectrum(p) : 0,
+          // force_form STRESS: the stress components and the force density
+          p.force_form == LBL_FORCE_STRESS ? sz * N * d * (d + 1) / 2 : 0,
+          p.force_form == LBL_FORCE_STRESS ? sz * N * d : 0};
 }
 
 size_t obs_bytes(const lbl_sim* s, int what) {
@@ -1018,6 +1051,8 @@ int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* e
     s->u_end = bufs[16];
     s->fspec = bufs[17];
     s->famp = bufs[18];
+    s->sig = bufs[19];
+    s->fstress = bufs[20];
   }
   if (!ok) {
     std::string msg = "device allocation failed";
@@ -1654,6 +1689,8 @@ int lbl_pool_submit(lbl_pool* pl, const lbl_params* params, const lbl_init* init
     return pool_fail(pl, LBL_E_INVAL, "pool requests report the final state (sample_every 0)");
   if (params->fd_noise != LBL_FDNOISE_LINK)
     return pool_fail(pl, LBL_E_INVAL, "Fourier-space FD noise runs in single simulations only");
+  if (params->force_form != LBL_FORCE_PSI_GRAD_MU)
+    return pool_fail(pl, LBL_E_INVAL, "the stress-divergence force runs in single simulations only");
   PoolReq r;
   r.id = pl->next_id++;
   r.p = *params;

@@ -105,6 +105,7 @@ __global__ __launch_bounds__(kSiteBlock) void kb_lb(const Replica<S>* __restrict
   a.k1 = r.k1;
   a.step = rs.step;
   a.force = r.coupling == kCplFull;
+  a.Fext = nullptr;
   a.noise = r.noise_on;
   a.nt = NT;
   int x, y;
@@ -132,6 +133,7 @@ __global__ __launch_bounds__(kSiteBlock) void kb_uend(const Replica<S>* __restri
   a.u_out = r.u_end;
   a.rho0 = r.rho0;
   a.force = 1;
+  a.Fext = nullptr;
   a.noise = 0;
   a.nt = NT;
   int x, y;

@@ -242,6 +242,108 @@ __global__ __launch_bounds__(kBX* kBY) void k_mu(Geom g, Coef<S> c, const S* __r
 }
 
 // ---------------------------------------------------------------------------
+// Force as the divergence of the order-parameter stress (Eq. muf):
+//   sigma_ab = K g_a g_b + delta_ab [A psi^2/2 + 3 B psi^4/4 - K psi L psi - K/2 |g|^2],
+//   F_a = -sum_b G_b sigma_ab,
+// with g = G psi, G the variant's gradient (FD: central difference; FV:
+// (1/c_s^2) sum_i w_i c_i (.)(x + c_i)) and L the Shinozaki-Oono Laplacian.
+// Every term of F is a difference of shifted copies, so the sum of F over the
+// lattice vanishes for any B.  sigma is stored by its d(d+1)/2 independent
+// components: xx, yy, (zz,) xy(, xz, yz).
+// ---------------------------------------------------------------------------
+template <int D>
+__host__ __device__ constexpr int sym_idx(int a, int b) {
+  return a == b ? a : (D == 2 ? 2 : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5)));
+}
+
+template <typename S, int Q, int SMOL>
+__device__ __forceinline__ void grad_at(const Nbr& nb, const S* __restrict__ v, S (&gr)[3]) {
+  using L = Lat<Q>;
+  gr[0] = gr[1] = gr[2] = S(0);
+  if constexpr (SMOL == kFD) {
+    gr[0] = S(0.5) * (v[nb.at(1, 0, 0)] - v[nb.at(-1, 0, 0)]);
+    gr[1] = S(0.5) * (v[nb.at(0, 1, 0)] - v[nb.at(0, -1, 0)]);
+    if (L::D == 3) gr[2] = S(0.5) * (v[nb.at(0, 0, 1)] - v[nb.at(0, 0, -1)]);
+  } else {
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const S t = S(L::w[i]) * v[nb.at(L::cx[i], L::cy[i], L::cz[i])];
+      if (L::cx[i]) gr[0] += L::cx[i] * t;
+      if (L::cy[i]) gr[1] += L::cy[i] * t;
+      if (L::cz[i]) gr[2] += L::cz[i] * t;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gr[a] *= S(3);
+  }
+}
+
+template <typename S, int Q, int SMOL>
+__global__ __launch_bounds__(kBX* kBY) void k_stress(Geom g, Coef<S> c, const S* __restrict__ psi,
+                                                     S* __restrict__ sig) {
+  constexpr int D = Lat<Q>::D;
+  const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const Nbr nb(g, x, y, z);
+  const int s = nb.at(0, 0, 0);
+  S gr[3];
+  grad_at<S, Q, SMOL>(nb, psi, gr);
+  const S ps = psi[s];
+  const S lap = lap_so<S, D>([&](int dx, int dy, int dz) { return psi[nb.at(dx, dy, dz)]; });
+  const S g2 = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+  const S iso = S(0.5) * c.a * ps * ps + S(0.75) * c.b * ps * ps * ps * ps - c.kappa * ps * lap -
+                S(0.5) * c.kappa * g2;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = a; b < D; ++b)
+      sig[static_cast<size_t>(sym_idx<D>(a, b)) * g.N + s] =
+          c.kappa * gr[a] * gr[b] + (a == b ? iso : S(0));
+}
+
+template <typename S, int Q, int SMOL>
+__global__ __launch_bounds__(kBX* kBY) void k_force_stress(Geom g, const S* __restrict__ sig,
+                                                           S* __restrict__ F) {
+  using L = Lat<Q>;
+  constexpr int D = L::D, NS = D * (D + 1) / 2;
+  const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const Nbr nb(g, x, y, z);
+  S f[3] = {0, 0, 0};
+  auto comp = [&](int k, int site) { return sig[static_cast<size_t>(k) * g.N + site]; };
+  if constexpr (SMOL == kFD) {
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      const int p = nb.at(b == 0, b == 1, b == 2), m = nb.at(-(b == 0), -(b == 1), -(b == 2));
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        f[a] -= S(0.5) * (comp(sym_idx<D>(a, b), p) - comp(sym_idx<D>(a, b), m));
+    }
+  } else {
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int site = nb.at(L::cx[i], L::cy[i], L::cz[i]);
+      S sv[NS];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) sv[k] = comp(k, site);
+      const int ci[3] = {L::cx[i], L::cy[i], L::cz[i]};
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        S acc = 0;
+#pragma unroll
+        for (int b = 0; b < D; ++b)
+          if (ci[b]) acc += ci[b] * sv[sym_idx<D>(a, b)];
+        f[a] -= S(3) * S(L::w[i]) * acc;
+      }
+    }
+  }
+  const int s = nb.at(0, 0, 0);
+#pragma unroll
+  for (int a = 0; a < D; ++a) F[static_cast<size_t>(a) * g.N + s] = f[a];
+}
+
+// ---------------------------------------------------------------------------
 // FLBE: pull, moments, force, MRT collision with noise (App. B).
 // ---------------------------------------------------------------------------
 template <typename S>
@@ -257,6 +359,7 @@ struct LBArgs {
   S sigma_s, sigma_b, sigma_g;
   uint32_t k0, k1, step;
   int force;  // 0: F = 0 (LB_ONLY)
+  const S* Fext;  // force density given per site (d*N), else computed from mu
   int noise;  // 0: kT == 0
   int nt;     // host's choice of the NT kernel variant (see kStreamBytes)
 };
@@ -292,7 +395,10 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
   // Force density F = -psi grad mu: FD central difference (Sec. IV) or the FV
   // gradient (1/c_s^2) sum_i w_i c_i mu(x + c_i) (Eq. fvgrad).
   S F[3] = {0, 0, 0};
-  if (a.force) {
+  if (a.Fext) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) F[c] = a.Fext[static_cast<size_t>(c) * g.N + s];
+  } else if (a.force) {
     const S* __restrict__ mu = a.mu;
     S gx = 0, gy = 0, gz = 0;
     if constexpr (SMOL == kFD) {

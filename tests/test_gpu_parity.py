@@ -228,3 +228,52 @@ def test_fd_fourier_noise_smol_only_rk4():
     c = H.config(lattice=H.D3Q19, smol=H.FD, coupling=H.SMOL_ONLY, rk=4, shape=(15, 12, 9),
                  kT=1e-4, u_imposed=(0.02, -0.01, 0.03), fd_noise=1)
     _check(c, 10)
+
+
+@pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q15, H.D3Q19])
+@pytest.mark.parametrize("smol", [H.FD, H.FV])
+def test_stress_force(lattice, smol):
+    """Force as the divergence of the stress of Eq. (muf), two-phase (B != 0)."""
+    c = H.config(lattice=lattice, smol=smol, shape=SHAPES[lattice], a=-0.04, b=0.04,
+                 kappa=0.05, init=1, kT=1e-5, force_form=1)
+    _check(c, 20)
+
+
+@pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q19])
+def test_stress_force_fp32dev(lattice):
+    c = H.config(lattice=lattice, smol=H.FV, precision=H.FP32DEV, shape=SHAPES[lattice],
+                 a=-0.04, b=0.04, init=1, force_form=1)
+    _check(c, 20)
+
+
+@pytest.mark.parametrize("lattice,smol", [(H.D2Q9, H.FD), (H.D3Q19, H.FV), (H.D3Q15, H.FD)])
+def test_stress_force_conserves_momentum_on_gpu(lattice, smol):
+    """With B != 0 the total momentum is constant to rounding under the
+    stress-divergence force and drifts under -psi grad mu."""
+    from paper_1104_0078_amd import lbl
+    drift = {}
+    for ff in (1, 0):
+        c = H.config(lattice=lattice, smol=smol, shape=SHAPES[lattice], a=-0.04, b=0.04,
+                     kappa=0.05, init=1, kT=1e-5, force_form=ff)
+        with lbl.Sim(H.lbl_params(c), lbl.make_init(kind=1, psi_std=1e-2)) as sim:
+            t0 = sim.observe(lbl.LBL_OBS_TOTALS)
+            sim.step(200)
+            t1 = sim.observe(lbl.LBL_OBS_TOTALS)
+        scale = t1[6:9].sum()
+        drift[ff] = np.abs(t1[1:4] - t0[1:4]).max() / scale
+    print("  momentum drift / sum|j|: stress %.2e, psi grad mu %.2e" % (drift[1], drift[0]))
+    assert drift[1] < 1e-12
+    assert drift[0] > 100 * drift[1]
+
+
+def test_stress_force_velocity_observable():
+    from paper_1104_0078_amd import lbl
+    import oracle as O
+    c = H.config(lattice=H.D3Q19, smol=H.FD, shape=SHAPES[H.D3Q19], a=-0.04, b=0.04, init=1,
+                 force_form=1)
+    p = H.oracle_params(c)
+    with lbl.Sim(H.lbl_params(c), lbl.make_init(kind=1, psi_std=1e-3)) as sim:
+        sim.step(5)
+        u = sim.observe(lbl.LBL_OBS_U)
+    f, psi = H.oracle_run(c, 5)
+    assert H.rel_err(u, O.velocity(p, f, O.force(p, psi))) < 1e-11

@@ -201,6 +201,21 @@ def test_shear_wave_decay(lattice, shape):
     assert abs(rate / (nu * k * k) - 1) < 0.01
 
 
+def test_coupled_structure_factor_stress_force():
+    """The stress-divergence force leaves the coupled static S(k) at the
+    exact discrete form, as the default force does."""
+    from paper_1104_0078_amd import lbl
+    shape = (24, 20, 16)
+    c = H.config(lattice=H.D3Q19, smol=H.FV, shape=shape, kT=1e-4, a=0.5, b=0.0, kappa=0.1,
+                 M=0.2, psi_std=0.0, force_form=1)
+    with _sim(c, sample_every=3) as sim:
+        sim.step(30000)
+        sk = sim.observe(lbl.LBL_OBS_SK_AXES)
+    r = _sk_compare(sk, _sk_theory(c, shape), shape, 3)
+    print("  coupled S/S_theory with the stress force: mean %.4f" % r.mean(), flush=True)
+    assert abs(r.mean() - 1) < 0.04
+
+
 def test_coupled_structure_factor_fp32_vs_fp64():
     from paper_1104_0078_amd import lbl
     shape = (24, 20, 16)
