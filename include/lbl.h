@@ -253,8 +253,9 @@ int lbl_timing_read(lbl_sim *sim, lbl_kernel_time *out, int max_entries, int *n_
  * xcd_swizzle, bit 0: the LB blocks, bit 1: the SMOL tiles are ordered so
  * that each of the 8 XCDs sweeps one contiguous eighth of them (reads across
  * block edges then hit the same L2); zc: planes per block of the z-marching SMOL kernels of a 3-D
- * lattice, stage and preparation kernels alike (0 keeps the current values,
- * larger than nz is clamped; lbl_get_schedule reports the stage's); overlap:
+ * lattice, stage and preparation kernels alike (0 restores the library's
+ * per-kernel defaults below, larger than nz is clamped; lbl_get_schedule
+ * reports the stage's); overlap:
  * 1 runs the first Runge-Kutta stage on a second stream of the library's
  * own (default priority), concurrently with the velocity pass of the
  * streamed populations that only the later stages read (full coupling, 2 or

@@ -55,9 +55,9 @@ def sim_key(params):
 def sim_candidates(params):
     widths = [w for w in (32, 64, 128, 256) if w <= max(32, params.nx)]
     widths = widths[-3:]
-    zcs = [0]
+    zcs = [0]  # 0: the library's per-kernel defaults (from occupancy)
     if params.nz > 1:
-        zcs = sorted({z for z in (8, 16, 32, 64) if z <= params.nz} or {params.nz})
+        zcs = [0] + sorted({z for z in (8, 16, 32, 64) if z <= params.nz} or {params.nz})
     swz = (0, 1, 2, 3) if params.nz > 1 else (0, 1)
     return [dict(lb_width=w, xcd_swizzle=s, zc=z, overlap=0) for w in widths for s in swz
             for z in zcs]

@@ -895,9 +895,12 @@ using TablesFn = void (*)(const std::vector<lbl_sim*>&, int, int, void*, std::ve
 using EnqueueFn = int (*)(hipStream_t, const void*, RepState*, int, const Work*, int, int,
                           const Work*, int, int, bool, int, int64_t);
 
+using ChunkFn = int (*)(lbl_sim*);
+
 struct Table {
   StepFn step;
   InitFn init;
+  ChunkFn chunks;
   ObsFn observe;
   TablesFn tables;
   EnqueueFn enqueue;
@@ -907,7 +910,8 @@ struct Table {
 template <typename S, bool DEV, int Q, int SMOL>
 Table table_for() {
   using I = Impl<S, DEV, Q, SMOL>;
-  return Table{&I::steps, &I::init, &I::observe, &I::tables, &I::enqueue_group, I::replica_bytes()};
+  return Table{&I::steps, &I::init, &I::default_chunks, &I::observe, &I::tables,
+               &I::enqueue_group, I::replica_bytes()};
 }
 
 template <typename S, bool DEV>
@@ -1591,7 +1595,12 @@ int lbl_set_schedule(lbl_sim* sim, const lbl_schedule* sch) {
   sim->lb_lw = lw;
   sim->lb_swizzle = sch->xcd_swizzle & 3;
   sim->overlap = sch->overlap;
-  if (sch->zc > 0) sim->zc = sim->zc_prep = std::min(sch->zc, sim->p.nz);
+  if (sch->zc > 0) {
+    sim->zc = sim->zc_prep = std::min(sch->zc, sim->p.nz);
+  } else {
+    if (int rc = hip_check(sim, hipSetDevice(sim->device), "hipSetDevice")) return rc;
+    if (int rc = select(sim->p).chunks(sim)) return rc;
+  }
   return LBL_OK;
 }
 

@@ -277,3 +277,14 @@ def test_stress_force_velocity_observable():
         u = sim.observe(lbl.LBL_OBS_U)
     f, psi = H.oracle_run(c, 5)
     assert H.rel_err(u, O.velocity(p, f, O.force(p, psi))) < 1e-11
+
+
+def test_zero_zc_restores_default_chunks():
+    from paper_1104_0078_amd import lbl
+    c = H.config(lattice=H.D3Q19, smol=H.FV, shape=(24, 20, 40))
+    with lbl.Sim(H.lbl_params(c), lbl.make_init()) as sim:
+        zc0 = sim.schedule()["zc"]
+        sim.set_schedule(lb_width=64, xcd_swizzle=0, zc=5, overlap=0)
+        assert sim.schedule()["zc"] == 5
+        sim.set_schedule(lb_width=64, xcd_swizzle=0, zc=0, overlap=0)
+        assert sim.schedule()["zc"] == zc0
