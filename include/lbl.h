@@ -104,7 +104,8 @@ typedef struct lbl_params {
   int32_t sample_every;
   int32_t fd_noise;   /* enum lbl_fd_noise; LBL_FDNOISE_LINK unless smol == LBL_SMOL_FD */
   int32_t force_form; /* enum lbl_force_form */
-  int32_t reserved;   /* must be 0 */
+  int32_t sample_full_k; /* 0 or 1: at every sample (sample_every > 0) also
+                            accumulate the whole-zone spectrum LBL_OBS_SK_FULL */
 } lbl_params;
 
 /* Force density of the order parameter on the fluid (full coupling):
@@ -216,7 +217,15 @@ enum lbl_observable {
                            k = 2 pi m / L_alpha, element [(alpha*Lmax + m)*2 + {0: re, 1: im}] */
   LBL_OBS_SK2_AXES = 10, /* d*Lmax FP64: mean over samples of the square of each
                            SK_AXES sample (its variance is SK2 - SK^2) */
-  LBL_OBS_UK2_AXES = 11  /* d*d*Lmax FP64: the same for UK_AXES */
+  LBL_OBS_UK2_AXES = 11, /* d*d*Lmax FP64: the same for UK_AXES */
+  LBL_OBS_SK_FULL = 12   /* nz*ny*(nx/2+1) FP64: mean over samples of
+                            |sum_x psi e^{-i q.x}|^2 / N over the whole zone,
+                            q = 2 pi (kx/nx, ky/ny, kz/nz), kx in [0, nx/2] (the
+                            other half follows from S(-q) = S(q)), element
+                            [kx + (nx/2+1)(ky + ny kz)]; one real-to-complex
+                            hipFFT transform per sample.  LBL_E_UNSUPPORTED
+                            unless lbl_params.sample_full_k (Figs. test1b, test2a,
+                            test2: the spectrum over wave-vector planes) */
 };
 
 /* Copy an observable of the current state into dst (host memory, or device

@@ -55,6 +55,9 @@ struct lbl_sim {
   void* fspec = nullptr;  // FD noise in Fourier space: half spectrum (interleaved re, im)
   void* famp = nullptr;   // and its amplitude table sqrt(-2 kT M L(q)) / N
   hipfftHandle fft_fwd = nullptr, fft_inv = nullptr;
+  hipfftHandle fft_obs = nullptr;  // sample_full_k: psi -> half spectrum
+  void* fk_spec = nullptr;         // its output (interleaved re, im)
+  double* fk_acc = nullptr;        // sum over samples of |psi_q|^2 / N
   void* sig = nullptr;      // force_form STRESS: order-parameter stress, d(d+1)/2 components
   void* fstress = nullptr;  // and its divergence, the force density (d*N)
   double* part = nullptr;
@@ -141,7 +144,8 @@ void release_all(lbl_sim* s) {
   if (!s->owned.empty()) (void)hipStreamSynchronize(s->stream);
   if (s->fft_fwd) (void)hipfftDestroy(s->fft_fwd);
   if (s->fft_inv) (void)hipfftDestroy(s->fft_inv);
-  s->fft_fwd = s->fft_inv = nullptr;
+  if (s->fft_obs) (void)hipfftDestroy(s->fft_obs);
+  s->fft_fwd = s->fft_inv = s->fft_obs = nullptr;
   for (void* ptr : s->owned) dev_free(s, ptr);
   s->owned.clear();
 }
@@ -289,7 +293,8 @@ int validate(const lbl_params* p, const lbl_init* in) {
   if (p->force_form != LBL_FORCE_PSI_GRAD_MU && p->force_form != LBL_FORCE_STRESS)
     return fail(nullptr, LBL_E_INVAL,
                 "force_form must be LBL_FORCE_PSI_GRAD_MU or LBL_FORCE_STRESS");
-  if (p->reserved != 0) return fail(nullptr, LBL_E_INVAL, "reserved must be 0");
+  if (p->sample_full_k != 0 && p->sample_full_k != 1)
+    return fail(nullptr, LBL_E_INVAL, "sample_full_k must be 0 or 1");
   if (in->kind < LBL_INIT_REST || in->kind > LBL_INIT_USER)
     return fail(nullptr, LBL_E_INVAL, "unknown init kind");
   if (in->kind == LBL_INIT_TANH_2IF && !(p->a < 0 && p->b > 0 && p->kappa > 0))
@@ -429,9 +434,54 @@ struct Impl {
     return fft_check(s, r, "inverse FFT");
   }
 
+  // Whole-zone spectrum of psi at every sample (sample_full_k): a
+  // real-to-complex plan of psi's storage type and a cleared FP64 accumulator.
+  static int full_k_setup(lbl_sim* s) {
+    if (!s->p.sample_full_k) return LBL_OK;
+    constexpr hipfftType t = sizeof(S) == 8 ? HIPFFT_D2Z : HIPFFT_R2C;
+    const lbl_params& p = s->p;
+    const hipfftResult r = Lat<Q>::D == 3 ? hipfftPlan3d(&s->fft_obs, p.nz, p.ny, p.nx, t)
+                                          : hipfftPlan2d(&s->fft_obs, p.ny, p.nx, t);
+    if (r != HIPFFT_SUCCESS) s->fft_obs = nullptr;
+    if (int rc = fft_check(s, r, "hipfftPlan")) return rc;
+    if (int rc = fft_check(s, hipfftSetStream(s->fft_obs, s->stream), "hipfftSetStream"))
+      return rc;
+    return hip_check(s, hipMemsetAsync(s->fk_acc, 0, sizeof(double) * half_spectrum(p), s->stream),
+                     "clear full-k accumulator");
+  }
+
+  // Add |psi_q|^2 / N of the current psi to the whole-zone accumulator.  psi
+  // is copied into a Runge-Kutta stage buffer first (dead between steps), so
+  // that the transform cannot touch the state.
+  static int full_k_sample(lbl_sim* s) {
+    const size_t bytes = sizeof(S) * static_cast<size_t>(s->N);
+    S* work = static_cast<S*>(s->phi[0]);
+    if (int rc = hip_check(s, hipMemcpyAsync(work, s->psi[s->pcur], bytes, hipMemcpyDeviceToDevice,
+                                             s->stream), "copy psi"))
+      return rc;
+    hipfftResult r = HIPFFT_SUCCESS;
+    if (int rc = launch(s, "fft", [&] {
+          if constexpr (sizeof(S) == 8)
+            r = hipfftExecD2Z(s->fft_obs, reinterpret_cast<hipfftDoubleReal*>(work),
+                              reinterpret_cast<hipfftDoubleComplex*>(s->fk_spec));
+          else
+            r = hipfftExecR2C(s->fft_obs, reinterpret_cast<hipfftReal*>(work),
+                              reinterpret_cast<hipfftComplex*>(s->fk_spec));
+        }))
+      return rc;
+    if (int rc = fft_check(s, r, "full-k FFT")) return rc;
+    const int nh = static_cast<int>(half_spectrum(s->p));
+    const double scale = 1.0 / static_cast<double>(s->N);
+    return launch(s, "k_sample", [&] {
+      k_power_acc<S><<<(nh + 255) / 256, 256, 0, s->stream>>>(
+          nh, static_cast<const S*>(s->fk_spec), scale, s->fk_acc);
+    });
+  }
+
   static int init(lbl_sim* s, const lbl_init* in) {
     if (int rc = default_chunks(s)) return rc;
     if (int rc = fourier_setup(s)) return rc;
+    if (int rc = full_k_setup(s)) return rc;
     const Geom g = geom(s);
     const int grid = grid_for(s->N);
     S* f = static_cast<S*>(s->f[0]);
@@ -676,6 +726,8 @@ struct Impl {
     s->step += 1;
     if (s->p.sample_every > 0 && s->step % s->p.sample_every == 0) {
       if (int rc = sample(s, true, nullptr)) return rc;
+      if (s->p.sample_full_k)
+        if (int rc = full_k_sample(s)) return rc;
       if (int rc = totals(s, s->tot)) return rc;
       s->tot_pending = true;
       s->nsamples += 1;
@@ -865,6 +917,13 @@ struct Impl {
       }
       case LBL_OBS_TOTALS:
         return totals(s, dst);
+      case LBL_OBS_SK_FULL: {
+        if (!s->p.sample_full_k) return LBL_E_UNSUPPORTED;
+        const int n = static_cast<int>(half_spectrum(s->p));
+        const double inv = 1.0 / static_cast<double>(s->nsamples > 0 ? s->nsamples : 1);
+        k_scale<<<grid_for(n), kBlock, 0, s->stream>>>(n, inv, s->fk_acc, dst);
+        return launched(s, "k_scale");
+      }
       case LBL_OBS_PSIK_AXES:
         return sample(s, false, dst);
       case LBL_OBS_SK_AXES:
@@ -945,7 +1004,10 @@ std::vector<size_t> alloc_plan(const lbl_params& p) {
           p.fd_noise == LBL_FDNOISE_FOURIER ? sz * half_spectrum(p) : 0,
           // force_form STRESS: the stress components and the force density
           p.force_form == LBL_FORCE_STRESS ? sz * N * d * (d + 1) / 2 : 0,
-          p.force_form == LBL_FORCE_STRESS ? sz * N * d : 0};
+          p.force_form == LBL_FORCE_STRESS ? sz * N * d : 0,
+          // sample_full_k: the half spectrum of psi and its FP64 accumulator
+          p.sample_full_k ? 2 * sz * half_spectrum(p) : 0,
+          p.sample_full_k ? sizeof(double) * half_spectrum(p) : 0};
 }
 
 size_t obs_bytes(const lbl_sim* s, int what) {
@@ -971,6 +1033,8 @@ size_t obs_bytes(const lbl_sim* s, int what) {
     case LBL_OBS_STEP:
     case LBL_OBS_NSAMPLES:
       return 8;
+    case LBL_OBS_SK_FULL:
+      return s->p.sample_full_k ? 8 * half_spectrum(s->p) : 0;
     default:
       return 0;
   }
@@ -1057,6 +1121,8 @@ int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* e
     s->famp = bufs[18];
     s->sig = bufs[19];
     s->fstress = bufs[20];
+    s->fk_spec = bufs[21];
+    s->fk_acc = static_cast<double*>(bufs[22]);
   }
   if (!ok) {
     std::string msg = "device allocation failed";
@@ -1700,6 +1766,8 @@ int lbl_pool_submit(lbl_pool* pl, const lbl_params* params, const lbl_init* init
     return pool_fail(pl, LBL_E_INVAL, "Fourier-space FD noise runs in single simulations only");
   if (params->force_form != LBL_FORCE_PSI_GRAD_MU)
     return pool_fail(pl, LBL_E_INVAL, "the stress-divergence force runs in single simulations only");
+  if (params->sample_full_k != 0)
+    return pool_fail(pl, LBL_E_INVAL, "pool requests report the final state (sample_full_k 0)");
   PoolReq r;
   r.id = pl->next_id++;
   r.p = *params;

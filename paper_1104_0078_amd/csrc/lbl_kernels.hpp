@@ -868,6 +868,16 @@ __global__ __launch_bounds__(256) void k_fourier_amp(Geom g, double two_kT_M,
   amp[i] = S((v > 0.0 ? sqrt(v) : 0.0) / static_cast<double>(g.N));
 }
 
+// acc[i] += |spec[i]|^2 * scale in FP64 (whole-zone structure factor).
+template <typename S>
+__global__ __launch_bounds__(256) void k_power_acc(int nh, const S* __restrict__ spec,
+                                                   double scale, double* __restrict__ acc) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nh) return;
+  const double re = spec[2 * i], im = spec[2 * i + 1];
+  acc[i] += (re * re + im * im) * scale;
+}
+
 // spec[i] *= amp[i] on the interleaved (re, im) half spectrum.
 template <typename S>
 __global__ __launch_bounds__(256) void k_fourier_scale(int nh, const S* __restrict__ amp,

@@ -30,7 +30,7 @@ LBL_FDNOISE_LINK, LBL_FDNOISE_FOURIER = 0, 1
 LBL_FORCE_PSI_GRAD_MU, LBL_FORCE_STRESS = 0, 1
 (LBL_OBS_PSI, LBL_OBS_RHO, LBL_OBS_U, LBL_OBS_POP, LBL_OBS_TOTALS, LBL_OBS_SK_AXES,
  LBL_OBS_UK_AXES, LBL_OBS_STEP, LBL_OBS_NSAMPLES, LBL_OBS_PSIK_AXES, LBL_OBS_SK2_AXES,
- LBL_OBS_UK2_AXES) = range(12)
+ LBL_OBS_UK2_AXES, LBL_OBS_SK_FULL) = range(13)
 
 
 class lbl_params(ctypes.Structure):
@@ -44,7 +44,7 @@ class lbl_params(ctypes.Structure):
         ("omega_ghost", ctypes.c_double), ("u_imposed", ctypes.c_double * 3),
         ("seed", ctypes.c_uint64), ("sample_every", ctypes.c_int32),
         ("fd_noise", ctypes.c_int32), ("force_form", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("sample_full_k", ctypes.c_int32),
     ]
 
 
@@ -220,7 +220,7 @@ def make_params(lattice=LBL_D2Q9, smol=LBL_SMOL_FD, precision=LBL_FP64, coupling
                 rk_stages=2, shape=(64, 64, 1), rho=1.0, eta=0.1, M=0.1, a=0.04, b=0.1,
                 kappa=0.05, kT=1e-5, omega_bulk=1.0, omega_ghost=1.0, u_imposed=(0, 0, 0),
                 seed=1234, sample_every=0, fd_noise=LBL_FDNOISE_LINK,
-                force_form=LBL_FORCE_PSI_GRAD_MU):
+                force_form=LBL_FORCE_PSI_GRAD_MU, sample_full_k=0):
     nx, ny, nz = (tuple(shape) + (1, 1, 1))[:3]
     p = lbl_params()
     p.lattice, p.smol, p.precision, p.coupling, p.rk_stages = (lattice, smol, precision,
@@ -234,7 +234,7 @@ def make_params(lattice=LBL_D2Q9, smol=LBL_SMOL_FD, precision=LBL_FP64, coupling
     p.sample_every = sample_every
     p.fd_noise = fd_noise
     p.force_form = force_form
-    p.reserved = 0
+    p.sample_full_k = sample_full_k
     return p
 
 
@@ -347,6 +347,9 @@ class Sim:
         if what == LBL_OBS_PSIK_AXES:
             o = out.reshape(self.d, L, 2)
             return o[..., 0] + 1j * o[..., 1]
+        if what == LBL_OBS_SK_FULL:
+            p = self.params
+            return out.reshape(p.nz, p.ny, p.nx // 2 + 1)
         return out
 
     def observe_into(self, what, tensor):

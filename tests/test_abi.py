@@ -67,7 +67,7 @@ def test_constants_and_strings():
     ("lattice", 27), ("lattice", 0), ("smol", 2), ("precision", 3), ("coupling", 7), ("rk_stages", 3),
     ("nx", 3), ("nz", 2), ("eta", -1.0), ("rho", 0.0), ("kT", -1e-5), ("omega_bulk", 2.5),
     ("omega_ghost", 0.0), ("M", float("nan")), ("fd_noise", 2), ("fd_noise", -1),
-    ("force_form", 2), ("reserved", 1), ("sample_every", -2),
+    ("force_form", 2), ("sample_full_k", 2), ("sample_every", -2),
 ])
 def test_invalid_parameters_rejected(field, value):
     p = lbl.make_params(lattice=lbl.LBL_D3Q19, shape=(8, 8, 8))

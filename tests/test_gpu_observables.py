@@ -76,3 +76,36 @@ def test_nonfinite_state_is_reported():
         with pytest.raises(lbl.LblError) as e:
             sim.observe(lbl.LBL_OBS_PSI)
         assert e.value.code == lbl.LBL_E_NONFINITE
+
+
+@pytest.mark.parametrize("lattice,shape,precision", [(H.D2Q9, (21, 13, 1), H.FP64),
+                                                     (H.D3Q19, (12, 9, 7), H.FP64),
+                                                     (H.D3Q15, (10, 8, 6), H.FP32DEV)])
+def test_full_k_structure_factor(lattice, shape, precision):
+    """LBL_OBS_SK_FULL (hipFFT of psi at every sample) against numpy's real
+    FFT of the same psi snapshots; on the axes it equals SK_AXES."""
+    from paper_1104_0078_amd import lbl
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    c = H.config(lattice=lattice, smol=H.FV, precision=precision, shape=shape, kT=1e-4,
+                 a=-0.04, b=0.04, init=1)
+    params = H.lbl_params(c, sample_every=1)
+    params.sample_full_k = 1
+    acc = np.zeros((nz, ny, nx // 2 + 1))
+    with lbl.Sim(params, lbl.make_init(kind=1, psi_std=1e-2)) as sim:
+        for _ in range(4):
+            sim.step(1)
+            psi = sim.observe(lbl.LBL_OBS_PSI).reshape(nz, ny, nx)
+            acc += np.abs(np.fft.rfftn(psi)) ** 2 / N
+        sk = sim.observe(lbl.LBL_OBS_SK_FULL)
+        axes = sim.observe(lbl.LBL_OBS_SK_AXES)
+        assert sim.observe(lbl.LBL_OBS_NSAMPLES) == 4
+    acc /= 4
+    tol = 1e-12 if precision == H.FP64 else 2e-5
+    np.testing.assert_allclose(sk, acc, rtol=tol, atol=tol * acc.max())
+    m = np.arange(nx // 2 + 1)
+    np.testing.assert_allclose(sk[0, 0, m], axes[0, m], rtol=tol, atol=tol * acc.max())
+    c2 = H.config(lattice=H.D2Q9, smol=H.FD, shape=(8, 8, 1))
+    with lbl.Sim(H.lbl_params(c2, sample_every=1), lbl.make_init()) as sim:
+        with pytest.raises(lbl.LblError):
+            sim.observe(lbl.LBL_OBS_SK_FULL)
