@@ -10,11 +10,16 @@
 //               writes f*^n and u^n                          one thread/site
 //   k_lb (no collision, "k_uend")  velocity of the streamed populations,
 //               (jbar^{n+1} + F^n/2)/rho^{n+1}, for the stages at t_{n+1}
-//   k_stage_*   one Runge-Kutta stage: phi -> mu(phi) -> fluxes -> divergence,
-//               in LDS rings (z-marching tiles); once per stage
-// k_mu (mu alone) serves the velocity observable.  Populations are
-// structure-of-arrays f[i*N + s]; the stored buffer holds the post-collision
-// values f*^{n-1} and step n pulls fbar^n(x) = f*^{n-1}(x - c_i).
+//   k_stage_*   one Runge-Kutta stage: phi -> mu(phi) -> fluxes -> divergence
+//               (z-marching tiles, per-plane stencil sums carried in
+//               registers); once per stage
+// Options: the FD noise built in Fourier space (k_white, a hipFFT pair,
+// k_fourier_scale) in place of the link fluxes of k_prep_fd; the force as the
+// divergence of the order-parameter stress (k_stress, k_force_stress), read
+// by k_lb in place of -psi grad mu.  k_mu (mu alone) serves the velocity
+// observable.  Populations are structure-of-arrays f[i*N + s]; the stored
+// buffer holds the post-collision values f*^{n-1} and step n pulls
+// fbar^n(x) = f*^{n-1}(x - c_i).
 #pragma once
 
 #include "lbl_device.hpp"
@@ -571,13 +576,11 @@ __global__ __launch_bounds__(kSiteBlock) void k_lb(LBArgs<S> a, SiteMap m) {
 // ---------------------------------------------------------------------------
 // z-marching tiles.  A block of kTX x kTY threads owns the columns
 // [x0, x0+kTX) x [y0, y0+kTY) and the planes [z0, z1); plane-sized regions
-// with an xy halo live in LDS rings indexed by plane.  Every global access
-// is to a wrapped (periodic) coordinate.
+// with an xy halo live in LDS (one plane, or a ring indexed by plane), and
+// stencils that span three planes are carried from plane to plane as
+// partial sums in registers.  Every global access is to a wrapped (periodic)
+// coordinate; the in-plane offsets are computed once per block.
 // ---------------------------------------------------------------------------
-template <int W, int H>
-struct Region {
-  static constexpr int size = W * H;
-};
 
 __device__ __forceinline__ int ring(int p, int n) { return ((p % n) + n) % n; }
 

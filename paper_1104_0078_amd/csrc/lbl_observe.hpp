@@ -6,7 +6,9 @@
 // accumulated in FP64 over samples together with their squares (for the
 // sampling error).  A Fourier mode on an axis only needs the
 // plane sums of the field along that axis, so each sample is: plane sums
-// (coalesced, fixed-order reductions) and a length-L DFT per axis.
+// (coalesced, fixed-order reductions) and a length-L DFT per axis.  The
+// whole-zone spectrum (an option) is a hipFFT transform per sample instead,
+// accumulated by k_power_acc.
 #pragma once
 
 #include "lbl_device.hpp"
