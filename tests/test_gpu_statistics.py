@@ -246,21 +246,32 @@ def _interface_heights(psi, nx, ny, lo, hi):
     return lo + idx + z0 / (z0 - z1)
 
 
-@pytest.mark.parametrize("smol", [H.FD, H.FV])
-def test_capillary_spectrum(smol):
+@pytest.mark.parametrize("smol,kT,force_form,nsamp,bar", [
+    (H.FD, 1.0 / 3000, 0, 2000, 0.1), (H.FV, 1.0 / 3000, 0, 2000, 0.1),
+    # the paper's second temperature
+    (H.FD, 1e-7, 0, 4000, 0.15), (H.FV, 1e-7, 0, 4000, 0.15),
+    # the force as the divergence of the stress of Eq. (muf): measured 1.09-1.20
+    # (FD) and 1.03-1.10 (FV) over runs; the discrete stress divergence is not
+    # the exact adjoint of the advection, so the reversible coupling is no
+    # longer energy-neutral on the lattice and the interface spectrum is
+    # slightly enhanced (the default -psi grad mu form is)
+    (H.FD, 1.0 / 3000, 1, 4000, 0.3), (H.FV, 1.0 / 3000, 1, 4000, 0.3)])
+def test_capillary_spectrum(smol, kT, force_form, nsamp, bar):
     """The paper's capillary set-up (Sec. VI.C): a 1024 x 128 D2Q9 lattice with
     two flat interfaces 64 sites apart, -A = B = 0.05, K = 0.2, M = 0.1,
-    kT = 1/3000, nu = c_s^2 tau with tau = 0.45.  The height spectrum of the
-    longest modes follows <|h_q|^2>/L = kT/(gamma q^2) (Eq. flucinterf) with
-    gamma from Eq. (st)."""
+    kT = 1/3000 or 1e-7 (Fig. flucinterf), nu = c_s^2 tau with tau = 0.45.
+    The height spectrum of the longest modes follows <|h_q|^2>/L =
+    kT/(gamma q^2) (Eq. flucinterf) with gamma from Eq. (st).  The bar is about
+    3 standard errors of the mean over the 16 longest modes (run-to-run spread
+    ~0.04 at 4000 samples)."""
     from paper_1104_0078_amd import lbl
     nx, ny = 1024, 128
-    a, b, kappa, kT = -0.05, 0.05, 0.2, 1.0 / 3000
+    a, b, kappa = -0.05, 0.05, 0.2
     c = H.config(lattice=H.D2Q9, smol=smol, precision=H.FP64, shape=(nx, ny, 1), a=a, b=b,
-                 kappa=kappa, M=0.1, kT=kT, eta=0.15, init=1, psi_std=1e-3, seed=77)
+                 kappa=kappa, M=0.1, kT=kT, eta=0.15, init=1, psi_std=1e-3, seed=77,
+                 force_form=force_form)
     print("capillary case", c, flush=True)
     gamma = 2 * np.sqrt(2) / 3 * np.sqrt(kappa * abs(a) ** 3) / b
-    nsamp = 2000
     acc = np.zeros(nx)
     with _sim(c) as sim:
         sim.step(20000)
@@ -276,4 +287,4 @@ def test_capillary_spectrum(smol):
     ratio = S[m] * gamma * q ** 2 / kT
     print("  capillary <|h_q|^2> gamma q^2/(L kT), m = 1..16: mean %.3f" % ratio.mean(),
           flush=True)
-    assert abs(ratio.mean() - 1) < 0.1
+    assert abs(ratio.mean() - 1) < bar
