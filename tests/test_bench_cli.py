@@ -1,0 +1,46 @@
+"""Host-side checks of bench.py's contract (no GPU): the multi-GPU request is
+refused with a message, and the algorithmic byte counts behind the roofline
+fields are the ones the kernels' data movement gives."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_algorithmic_bytes_of_the_headline_workload():
+    w = bench.WORKLOADS[bench.DEFAULT_WORKLOAD]
+    assert w["lattice"] == 19 and w["precision"] == 0 and w["shape"] == (256, 256, 256)
+    # state read and written once per step: 2 Q b + 2 b
+    assert bench.alg_bytes_per_site(w) == 2 * 19 * 8 + 2 * 8 == 320
+    # k_lb: Q pulls + Q writes + psi + mu + u^n (d = 3)
+    assert bench.kernel_alg_bytes_per_site("k_lb", w) == (2 * 19 + 2 + 3) * 8 == 344
+    # k_uend: Q pulls + psi + mu + the stage velocity
+    assert bench.kernel_alg_bytes_per_site("k_uend", w) == (19 + 2 + 3) * 8
+    assert bench.kernel_alg_bytes_per_site("k_prep", w) == 3 * 8
+    assert bench.kernel_alg_bytes_per_site("k_stage", w) == (3 + 3) * 8 + 4
+    w32 = dict(w, precision=1)
+    assert bench.alg_bytes_per_site(w32) == 160
+    assert bench.kernel_alg_bytes_per_site("k_white", w) is None
+
+
+def test_committed_traffic_entries_are_self_consistent():
+    """Each entry of profiles/traffic.json scales the counters by the copy
+    calibration it records; the bench reports it only for matching sources."""
+    import json
+    entries = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    assert {e["kernel"] for e in entries} >= {"k_lb", "k_uend", "k_prep", "k_stage"}
+    for e in entries:
+        scaled = (e["fetch_kib"] * 1024 * e["fetch_factor"] + e["write_kib"] * 1024 *
+                  e["write_factor"])
+        assert abs(scaled / e["bytes_per_launch"] - 1) < 1e-12
+        assert e["bytes_per_launch"] > e["alg_bytes_per_launch"] * 0.9
