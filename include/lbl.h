@@ -6,13 +6,15 @@
  * by the hybrid scheme of Sumesh, Pagonabarraga & Adhikari (arXiv:1104.0078):
  *   - momentum: fluctuating lattice Boltzmann (FLBE, Sec. IV and App. B),
  *     multiple-relaxation-time collision with the force density
- *     F = -psi grad mu and Landau-Lifshitz noise on every non-conserved mode;
+ *     F = -psi grad mu (or, as an option, the divergence of the stress of
+ *     Eq. muf) and Landau-Lifshitz noise on every non-conserved mode;
  *   - order parameter psi: stochastic method of lines (SMOL, Sec. V) with the
  *     Landau chemical potential mu = A psi + B psi^3 - K lap psi (Sec. II.A),
  *     advection by the LB velocity, diffusion M lap mu and a conserved
- *     Langevin flux, in the finite-difference (Sec. V.A) or finite-volume
- *     (Sec. V.B) variant, integrated by Runge-Kutta with the noise held
- *     constant through the step.
+ *     Langevin flux, in the finite-difference (Sec. V.A; noise from link
+ *     fluxes, or built in Fourier space as the paper states it) or
+ *     finite-volume (Sec. V.B) variant, integrated by Runge-Kutta with the
+ *     noise held constant through the step.
  * Lattice units: dx = dt = 1, c_s^2 = 1/3 (Sec. VI).
  *
  * Conventions shared by every entry point:
