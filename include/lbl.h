@@ -199,8 +199,9 @@ enum lbl_observable {
   LBL_OBS_PSI = 0,      /* N FP64: psi */
   LBL_OBS_RHO = 1,      /* N FP64: rho = sum_i fbar_i */
   LBL_OBS_U = 2,        /* d*N FP64: u = (sum_i fbar_i c_i + F/2)/rho, F the force
-                           density of lbl_params.force_form (F = 0 for LB_ONLY;
-                           u_imposed for SMOL_ONLY) */
+                           density of lbl_params.force_form (F = 0 for LB_ONLY).
+                           LBL_E_UNSUPPORTED for SMOL_ONLY, which has no flow
+                           field (its velocity is lbl_params.u_imposed) */
   LBL_OBS_POP = 3,      /* Q*N FP64: fbar, canonical order */
   LBL_OBS_TOTALS = 4,   /* 10 FP64: mass, Px, Py, Pz, Psi, then the L1 norms
                            sum|rho|, sum|jx|, sum|jy|, sum|jz|, sum|psi|,
@@ -225,8 +226,9 @@ enum lbl_observable {
                             q = 2 pi (kx/nx, ky/ny, kz/nz), kx in [0, nx/2] (the
                             other half follows from S(-q) = S(q)), element
                             [kx + (nx/2+1)(ky + ny kz)]; one real-to-complex
-                            hipFFT transform per sample.  LBL_E_UNSUPPORTED
-                            unless lbl_params.sample_full_k (Figs. test1b, test2a,
+                            hipFFT transform per sample.  Only with
+                            lbl_params.sample_full_k: otherwise its size is 0 and
+                            lbl_observe gives LBL_E_INVAL (Figs. test1b, test2a,
                             test2: the spectrum over wave-vector planes) */
 };
 
@@ -237,7 +239,8 @@ enum lbl_observable {
  * deferred error of earlier steps. */
 int lbl_observe(lbl_sim *sim, int what, void *dst, size_t bytes, int dst_is_device);
 
-/* Size in bytes of an observable for this simulation (0 for unknown `what`). */
+/* Size in bytes of an observable for this simulation (0 for unknown `what`,
+ * and for LBL_OBS_SK_FULL without lbl_params.sample_full_k). */
 size_t lbl_observable_bytes(const lbl_sim *sim, int what);
 
 /* Release the simulation's device memory through the injected allocator
