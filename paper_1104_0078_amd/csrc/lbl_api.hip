@@ -73,6 +73,7 @@ struct lbl_sim {
   uint32_t k0 = 0, k1 = 0;
   int zc = 1;       // planes per block of the z-marching SMOL stage kernels
   int zc_prep = 1;  // planes per block of the z-marching preparation kernel
+  int zc_stress = 1;  // planes per block of the z-marching FV stress kernels (3-D)
   int lb_lw = 6;       // log2 of the LB block width along x
   int lb_swizzle = 0;  // XCD-contiguous block order: bit 0 LB kernels, bit 1 tile kernels
   int overlap = 0;     // first RK stage on `aux`, concurrent with the velocity pass
@@ -348,6 +349,19 @@ struct Impl {
                                                                          kTX * kTY, 0), "occupancy");
       }
     }
+    int nb_stress = 0;
+    if constexpr (SMOL == kFV && Lat<Q>::D == 3) {
+      int nb_sig = 0;
+      if (!rc)
+        rc = hip_check(s, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &nb_stress, k_force_stress_fv3<S, Q>, kTX * kTY, 0),
+                       "occupancy");
+      if (!rc)
+        rc = hip_check(s, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &nb_sig, k_stress_fv3<S, Q>, kTX * kTY, 0),
+                       "occupancy");
+      nb_stress = std::min(nb_stress, nb_sig);
+    }
     if (rc) return rc;
     const int nz = s->p.nz;
     const long bxy = static_cast<long>((s->p.nx + kTX - 1) / kTX) * ((s->p.ny + kTY - 1) / kTY);
@@ -359,6 +373,7 @@ struct Impl {
     };
     s->zc = pick(nb_stage, 1);
     s->zc_prep = pick(nb_prep, 2);
+    s->zc_stress = pick(nb_stress, 2);
     return LBL_OK;
   }
 
@@ -593,12 +608,27 @@ struct Impl {
     const Geom g = geom(s);
     const Coef<S> c = coef(s);
     S* sig = static_cast<S*>(s->sig);
+    S* F = static_cast<S*>(s->fstress);
+    if constexpr (SMOL == kFV && Lat<Q>::D == 3) {
+      // z-marching tiles (the FV gradient spans 18 neighbours)
+      const TileMap tm = make_tile_map(s->p.nx, s->p.ny, (s->p.nz + s->zc_stress - 1) / s->zc_stress,
+                                       (s->lb_swizzle & 2) != 0);
+      const dim3 tg(tile_map_blocks(tm)), tb(kTX, kTY);
+      const int zc = s->zc_stress;
+      if (int rc = launch(s, "k_stress", [&] {
+            k_stress_fv3<S, Q><<<tg, tb, 0, s->stream>>>(g, c, psi, sig, zc, tm);
+          }))
+        return rc;
+      return launch(s, "k_force_stress", [&] {
+        k_force_stress_fv3<S, Q><<<tg, tb, 0, s->stream>>>(g, sig, F, zc, tm);
+      });
+    }
     if (int rc = launch(s, "k_stress", [&] {
           k_stress<S, Q, SMOL><<<grid, block, 0, s->stream>>>(g, c, psi, sig);
         }))
       return rc;
     return launch(s, "k_force_stress", [&] {
-      k_force_stress<S, Q, SMOL><<<grid, block, 0, s->stream>>>(g, sig, static_cast<S*>(s->fstress));
+      k_force_stress<S, Q, SMOL><<<grid, block, 0, s->stream>>>(g, sig, F);
     });
   }
 

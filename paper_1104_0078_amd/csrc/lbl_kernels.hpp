@@ -217,13 +217,17 @@ struct SoPlanes {
     f[2] = (P[-1] + P[1]) + (P[-W] + P[W]);
     k[2] = (P[-W - 1] + P[-W + 1]) + (P[W - 1] + P[W + 1]);
   }
-  __device__ __forceinline__ S mu(const Coef<S>& co) const {
-    const S ph = c[1];
+  // L_SO phi at the middle plane.
+  __device__ __forceinline__ S lap() const {
     const S F = f[1] + (c[0] + c[2]);
     const S E = k[1] + (f[0] + f[2]);
     const S C = k[0] + k[2];
-    const S lap = S(6.0 / 22.0) * F + S(3.0 / 22.0) * E + S(1.0 / 22.0) * C - S(80.0 / 22.0) * ph;
-    return co.a * ph + co.b * ph * ph * ph - co.kappa * lap;
+    return S(6.0 / 22.0) * F + S(3.0 / 22.0) * E + S(1.0 / 22.0) * C - S(80.0 / 22.0) * c[1];
+  }
+  __device__ __forceinline__ S mu(const Coef<S>& co) const {
+    const S ph = c[1];
+    const S lp = lap();
+    return co.a * ph + co.b * ph * ph * ph - co.kappa * lp;
   }
   __device__ __forceinline__ void roll() {
     c[0] = c[1];
@@ -737,6 +741,150 @@ template <typename S, int Q>
 __global__ __launch_bounds__(kTX* kTY) void k_prep_fv(PrepArgs<S> a, TileMap m) {
   int bx, by, bz;
   if (tile_of(m, bx, by, bz)) prep_fv_body<S, Q>(a, bx, by, bz);
+}
+
+// Stress-divergence force of the FV variant in 3-D, z-marching:
+// F_a = -sum_b G_b sigma_ab with G = 3 sum_i w_i c_i (.)(x + c_i).  One plane
+// of sigma (halo 1) lives in LDS at a time; sigma at (x + c_ix, y + c_iy, p)
+// feeds F at plane p - c_iz, so each plane is folded into register partial
+// sums of F for the planes below, at and above it (the per-site form gathers
+// all components at every neighbour instead).
+template <typename S, int Q>
+__global__ __launch_bounds__(kTX* kTY) void k_force_stress_fv3(Geom g, const S* __restrict__ sig,
+                                                             S* __restrict__ F, int zc,
+                                                             TileMap m) {
+  using L = Lat<Q>;
+  static_assert(L::D == 3, "3-D lattices");
+  constexpr int NS = 6;
+  constexpr int W = kTX + 2, H = kTY + 2, RS = W * H;
+  constexpr int NT = kTX * kTY;
+  static_assert(RS <= 2 * NT, "two region elements per thread");
+  __shared__ S sp[NS][RS];
+  int bx, by, bz;
+  if (!tile_of(m, bx, by, bz)) return;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
+  const int x0 = bx * kTX, y0 = by * kTY;
+  const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
+  const int z0 = bz * zc, z1 = min(z0 + zc, g.nz);
+  const int x = x0 + tx, y = y0 + ty;
+  const bool live = x < g.nx && y < g.ny;
+  int rxy[2];
+  region_offsets<W>(g, x0, y0, -1, -1, near, tid, rxy);
+  S fp[3][3];  // F at planes p-1, p, p+1
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) fp[j][a] = S(0);
+  const int plane = g.nx * g.ny;
+  int pz = wrap_any(z0 - 1, g.nz);
+  for (int p = z0 - 1; p <= z1; ++p, pz = next_plane(pz, g.nz)) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = tid + k * NT;
+      if (e < RS) {
+        const int site = (k ? rxy[1] : rxy[0]) + plane * pz;
+#pragma unroll
+        for (int c = 0; c < NS; ++c) sp[c][e] = sig[static_cast<size_t>(c) * g.N + site];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int e = (tx + 1 + L::cx[i]) + W * (ty + 1 + L::cy[i]);
+      const int ci[3] = {L::cx[i], L::cy[i], L::cz[i]};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        S acc = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          if (ci[b]) acc += ci[b] * sp[sym_idx<3>(a, b)][e];
+        fp[1 - L::cz[i]][a] -= S(3) * S(L::w[i]) * acc;
+      }
+    }
+    if (p - 1 >= z0 && p - 1 < z1 && live) {
+      const int s = x + g.nx * (y + g.ny * (p - 1));
+#pragma unroll
+      for (int a = 0; a < 3; ++a) F[static_cast<size_t>(a) * g.N + s] = fp[0][a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      fp[0][a] = fp[1][a];
+      fp[1][a] = fp[2][a];
+      fp[2][a] = S(0);
+    }
+    __syncthreads();
+  }
+}
+
+// The order-parameter stress of the FV variant in 3-D, z-marching: one plane
+// of psi (halo 1) in LDS at a time; the gradient g = 3 sum_i w_i c_i psi(x + c_i)
+// is carried as register partial sums for the planes below, at and above the
+// newest one, and L_SO psi from the per-plane sums of SoPlanes.  sigma is
+// written for the middle plane, with the same formula as the per-site form.
+template <typename S, int Q>
+__global__ __launch_bounds__(kTX* kTY) void k_stress_fv3(Geom g, Coef<S> co,
+                                                       const S* __restrict__ psi,
+                                                       S* __restrict__ sig, int zc, TileMap m) {
+  using L = Lat<Q>;
+  static_assert(L::D == 3, "3-D lattices");
+  using R = PsiPlane<S>;
+  constexpr int W = R::W;
+  __shared__ R sp;
+  int bx, by, bz;
+  if (!tile_of(m, bx, by, bz)) return;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
+  const int x0 = bx * kTX, y0 = by * kTY;
+  const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
+  const int z0 = bz * zc, z1 = min(z0 + zc, g.nz);
+  const int x = x0 + tx, y = y0 + ty;
+  const bool live = x < g.nx && y < g.ny;
+  int rxy[2];
+  region_offsets<W>(g, x0, y0, -1, -1, near, tid, rxy);
+  SoPlanes<S> so;
+  S gp[3][3];  // gradient partial sums at planes p-1, p, p+1
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gp[j][a] = S(0);
+  const int plane = g.nx * g.ny;
+  int pz = wrap_any(z0 - 1, g.nz);
+  for (int p = z0 - 1; p <= z1; ++p, pz = next_plane(pz, g.nz)) {
+    prep_load_psi(sp, psi, rxy, plane * pz, tid);
+    __syncthreads();
+    so.template push<W>(sp.v + (tx + 1) + W * (ty + 1));
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const S t = S(L::w[i]) * sp.v[(tx + 1 + L::cx[i]) + W * (ty + 1 + L::cy[i])];
+      if (L::cx[i]) gp[1 - L::cz[i]][0] += L::cx[i] * t;
+      if (L::cy[i]) gp[1 - L::cz[i]][1] += L::cy[i] * t;
+      if (L::cz[i]) gp[1 - L::cz[i]][2] += L::cz[i] * t;
+    }
+    if (p - 1 >= z0 && p - 1 < z1 && live) {
+      const int s = x + g.nx * (y + g.ny * (p - 1));
+      S gr[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gr[a] = gp[0][a] * S(3);
+      const S ps = so.c[1];
+      const S lap = so.lap();
+      const S g2 = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+      const S iso = S(0.5) * co.a * ps * ps + S(0.75) * co.b * ps * ps * ps * ps -
+                    co.kappa * ps * lap - S(0.5) * co.kappa * g2;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b)
+          sig[static_cast<size_t>(sym_idx<3>(a, b)) * g.N + s] =
+              co.kappa * gr[a] * gr[b] + (a == b ? iso : S(0));
+    }
+    so.roll();
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      gp[0][a] = gp[1][a];
+      gp[1][a] = gp[2][a];
+      gp[2][a] = S(0);
+    }
+    __syncthreads();
+  }
 }
 
 // FD noise (Sec. V.A, reading): one flux zeta_l per undirected Laplacian link,

@@ -191,17 +191,21 @@ def test_resume_is_bitwise(lattice, smol, precision):
 
 @pytest.mark.parametrize("lattice", [H.D3Q15, H.D3Q19])
 @pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
-def test_wide_lattice_ragged_tiles(lattice, precision):
+@pytest.mark.parametrize("force_form", [0, 1])
+def test_wide_lattice_ragged_tiles(lattice, precision, force_form):
     """A lattice wider than the LB rows' 64-site blocks and the SMOL tiles,
-    with ragged tiles in x (70 = 2 x 32 + 6) and y (21 = 2 x 8 + 5)."""
+    with ragged tiles in x (70 = 2 x 32 + 6) and y (21 = 2 x 8 + 5), and
+    z-chunks of 8 and 1 planes in the stress-force kernel."""
     c = H.config(lattice=lattice, smol=H.FV, precision=precision, shape=(70, 21, 9), a=-0.04,
-                 b=0.04, kappa=0.05, init=1, kT=1e-5)
+                 b=0.04, kappa=0.05, init=1, kT=1e-5, force_form=force_form)
     _check(c, 15)
 
 
-def test_wide_lattice_schedules_do_not_change_results():
+@pytest.mark.parametrize("force_form", [0, 1])
+def test_wide_lattice_schedules_do_not_change_results(force_form):
     from paper_1104_0078_amd import lbl
-    c = H.config(lattice=H.D3Q19, smol=H.FV, shape=(70, 21, 13), init=0, a=-0.04, b=0.04)
+    c = H.config(lattice=H.D3Q19, smol=H.FV, shape=(70, 21, 13), init=0, a=-0.04, b=0.04,
+                 force_form=force_form)
     ini = lbl.make_init(kind=0, psi_std=1e-3)
     out = []
     for swz, zc, ov in ((0, 0, 0), (2, 4, 0), (0, 5, 1), (3, 13, 0)):
