@@ -20,6 +20,7 @@ completion latency and aggregate MLUPS).
 """
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -89,12 +90,19 @@ def kernel_alg_bytes_per_site(name, w, rk=2):
 
 
 def source_hash():
+    """Hash of the kernel sources with comments and white space removed: the
+    committed counter summary stays valid across edits of comments alone and
+    is dropped by any change of code."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1104_0078_amd", "csrc")
     for fn in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, fn), "rb") as fh:
-            h.update(fn.encode())
-            h.update(fh.read())
+        with open(os.path.join(csrc, fn), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        text = " ".join(text.split())
+        h.update(fn.encode())
+        h.update(text.encode())
     return h.hexdigest()[:16]
 
 

@@ -15,8 +15,9 @@
 //               registers); once per stage
 // Options: the FD noise built in Fourier space (k_white, a hipFFT pair,
 // k_fourier_scale) in place of the link fluxes of k_prep_fd; the force as the
-// divergence of the order-parameter stress (k_stress, k_force_stress), read
-// by k_lb in place of -psi grad mu.  k_mu (mu alone) serves the velocity
+// divergence of the order-parameter stress (k_stress, k_force_stress; for FV
+// in 3-D their z-marching forms k_stress_fv3, k_force_stress_fv3), read by
+// k_lb in place of -psi grad mu.  k_mu (mu alone) serves the velocity
 // observable.  Populations are structure-of-arrays f[i*N + s]; the stored
 // buffer holds the post-collision values f*^{n-1} and step n pulls
 // fbar^n(x) = f*^{n-1}(x - c_i).

@@ -44,3 +44,21 @@ def test_committed_traffic_entries_are_self_consistent():
                   e["write_factor"])
         assert abs(scaled / e["bytes_per_launch"] - 1) < 1e-12
         assert e["bytes_per_launch"] > e["alg_bytes_per_launch"] * 0.9
+
+
+def test_source_hash_ignores_comments_only(tmp_path, monkeypatch):
+    """The committed counter summary is keyed by a hash of the kernel sources
+    without comments: a comment edit keeps it, a code edit drops it."""
+    import shutil
+    src = os.path.join(ROOT, "paper_1104_0078_amd", "csrc")
+    dst = tmp_path / "paper_1104_0078_amd" / "csrc"
+    shutil.copytree(src, dst)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.source_hash()
+    k = dst / "lbl_kernels.hpp"
+    text = k.read_text()
+    k.write_text("// an added line comment\n/* and a block\n   comment */\n" +
+                 text.replace(";", ";  // trailing comment", 1))
+    assert bench.source_hash() == h0
+    k.write_text(text + "\nstatic int added_code;\n")
+    assert bench.source_hash() != h0
