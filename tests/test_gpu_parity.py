@@ -147,11 +147,14 @@ def test_schedule_does_not_change_results(lattice):
                                            (H.D3Q15, (4, 4, 4)), (H.D3Q15, (6, 5, 7)),
                                            (H.D3Q19, (33, 9, 5))])
 @pytest.mark.parametrize("smol", [H.FD, H.FV])
-def test_smallest_and_odd_lattices(lattice, shape, smol):
+@pytest.mark.parametrize("force_form", [0, 1])
+def test_smallest_and_odd_lattices(lattice, shape, smol, force_form):
     """Sides at the minimum the ABI accepts (4, where every stencil halo
     wraps onto the lattice itself several times) and odd sides just past one
-    tile, two-phase so that the nonlinear terms are exercised."""
-    c = H.config(lattice=lattice, smol=smol, shape=shape, init=0, a=-0.04, b=0.04)
+    tile, two-phase so that the nonlinear terms are exercised; with either
+    force (the stress kernels' z-chunks then span the whole periodic axis)."""
+    c = H.config(lattice=lattice, smol=smol, shape=shape, init=0, a=-0.04, b=0.04,
+                 force_form=force_form)
     _check(c, 12)
 
 
