@@ -277,8 +277,8 @@ int lbl_timing_read(lbl_sim *sim, lbl_kernel_time *out, int max_entries, int *n_
  * widest width up to 256 that fits nx, no swizzle, zc per kernel from its
  * occupancy (the stage's blocks fill the device's resident slots in one
  * round, the preparation kernel's in two; at least 8 planes), overlap 0.
- * The z-marching stress kernels of force_form STRESS (FV, 3-D) keep their
- * own default (two rounds) whatever zc is.  Errors: LBL_E_INVAL (NULL,
+ * The z-marching stress pass of force_form STRESS (FV, 3-D) keeps its own
+ * default (two rounds) whatever zc is.  Errors: LBL_E_INVAL (NULL,
  * unsupported width, zc < 0, overlap not 0 or 1). */
 typedef struct lbl_schedule {
   int32_t lb_width;

@@ -350,18 +350,11 @@ struct Impl {
       }
     }
     int nb_stress = 0;
-    if constexpr (SMOL == kFV && Lat<Q>::D == 3) {
-      int nb_sig = 0;
+    if constexpr (SMOL == kFV && Lat<Q>::D == 3)
       if (!rc)
         rc = hip_check(s, hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &nb_stress, k_force_stress_fv3<S, Q>, kTX * kTY, 0),
+                              &nb_stress, k_stress_force_fv3<S, Q>, kTX * kTY, 0),
                        "occupancy");
-      if (!rc)
-        rc = hip_check(s, hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &nb_sig, k_stress_fv3<S, Q>, kTX * kTY, 0),
-                       "occupancy");
-      nb_stress = std::min(nb_stress, nb_sig);
-    }
     if (rc) return rc;
     const int nz = s->p.nz;
     const long bxy = static_cast<long>((s->p.nx + kTX - 1) / kTX) * ((s->p.ny + kTY - 1) / kTY);
@@ -610,17 +603,14 @@ struct Impl {
     S* sig = static_cast<S*>(s->sig);
     S* F = static_cast<S*>(s->fstress);
     if constexpr (SMOL == kFV && Lat<Q>::D == 3) {
-      // z-marching tiles (the FV gradient spans 18 neighbours)
+      // one z-marching pass (the FV gradient spans 18 neighbours); sigma
+      // stays on the chip
       const TileMap tm = make_tile_map(s->p.nx, s->p.ny, (s->p.nz + s->zc_stress - 1) / s->zc_stress,
                                        (s->lb_swizzle & 2) != 0);
       const dim3 tg(tile_map_blocks(tm)), tb(kTX, kTY);
       const int zc = s->zc_stress;
-      if (int rc = launch(s, "k_stress", [&] {
-            k_stress_fv3<S, Q><<<tg, tb, 0, s->stream>>>(g, c, psi, sig, zc, tm);
-          }))
-        return rc;
-      return launch(s, "k_force_stress", [&] {
-        k_force_stress_fv3<S, Q><<<tg, tb, 0, s->stream>>>(g, sig, F, zc, tm);
+      return launch(s, "k_stress_force", [&] {
+        k_stress_force_fv3<S, Q><<<tg, tb, 0, s->stream>>>(g, c, psi, F, zc, tm);
       });
     }
     if (int rc = launch(s, "k_stress", [&] {
@@ -1032,8 +1022,11 @@ std::vector<size_t> alloc_plan(const lbl_params& p) {
           // FD noise in Fourier space: half spectrum (complex) and amplitude table
           p.fd_noise == LBL_FDNOISE_FOURIER ? 2 * sz * half_spectrum(p) : 0,
           p.fd_noise == LBL_FDNOISE_FOURIER ? sz * half_spectrum(p) : 0,
-          // force_form STRESS: the stress components and the force density
-          p.force_form == LBL_FORCE_STRESS ? sz * N * d * (d + 1) / 2 : 0,
+          // force_form STRESS: the stress components (not stored by the fused
+          // FV 3-D pass) and the force density
+          p.force_form == LBL_FORCE_STRESS && (p.smol != LBL_SMOL_FV || d == 2)
+              ? sz * N * d * (d + 1) / 2
+              : 0,
           p.force_form == LBL_FORCE_STRESS ? sz * N * d : 0,
           // sample_full_k: the half spectrum of psi and its FP64 accumulator
           p.sample_full_k ? 2 * sz * half_spectrum(p) : 0,

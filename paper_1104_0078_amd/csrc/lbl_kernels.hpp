@@ -16,8 +16,8 @@
 // Options: the FD noise built in Fourier space (k_white, a hipFFT pair,
 // k_fourier_scale) in place of the link fluxes of k_prep_fd; the force as the
 // divergence of the order-parameter stress (k_stress, k_force_stress; for FV
-// in 3-D their z-marching forms k_stress_fv3, k_force_stress_fv3), read by
-// k_lb in place of -psi grad mu.  k_mu (mu alone) serves the velocity
+// in 3-D the single z-marching pass k_stress_force_fv3), read by k_lb in
+// place of -psi grad mu.  k_mu (mu alone) serves the velocity
 // observable.  Populations are structure-of-arrays f[i*N + s]; the stored
 // buffer holds the post-collision values f*^{n-1} and step n pulls
 // fbar^n(x) = f*^{n-1}(x - c_i).
@@ -744,23 +744,29 @@ __global__ __launch_bounds__(kTX* kTY) void k_prep_fv(PrepArgs<S> a, TileMap m) 
   if (tile_of(m, bx, by, bz)) prep_fv_body<S, Q>(a, bx, by, bz);
 }
 
-// Stress-divergence force of the FV variant in 3-D, z-marching:
-// F_a = -sum_b G_b sigma_ab with G = 3 sum_i w_i c_i (.)(x + c_i).  One plane
-// of sigma (halo 1) lives in LDS at a time; sigma at (x + c_ix, y + c_iy, p)
-// feeds F at plane p - c_iz, so each plane is folded into register partial
-// sums of F for the planes below, at and above it (the per-site form gathers
-// all components at every neighbour instead).
+// Stress-divergence force of the FV variant in 3-D (sigma and F = -G.sigma of
+// k_stress and k_force_stress) in one z-marching pass, so that sigma never
+// leaves the chip.  Each iteration stages a psi plane with a two-site halo in
+// LDS and forms sigma, for the plane below it, on the tile with a one-site
+// halo (two region elements per thread): the gradient g = 3 sum_i w_i c_i
+// psi(x + c_i) as register partial sums over three planes, L_SO from the
+// per-plane sums of SoPlanes.  That sigma plane goes to LDS and is folded into
+// register partial sums of F: sigma at (x + c_ix, y + c_iy, q) feeds F at
+// plane q - c_iz.  sigma at plane q needs psi at q-1..q+1 and F at plane z
+// needs sigma at z-1..z+1, so F lags the staged psi plane by two.
 template <typename S, int Q>
-__global__ __launch_bounds__(kTX* kTY) void k_force_stress_fv3(Geom g, const S* __restrict__ sig,
+__global__ __launch_bounds__(kTX* kTY) void k_stress_force_fv3(Geom g, Coef<S> co,
+                                                             const S* __restrict__ psi,
                                                              S* __restrict__ F, int zc,
                                                              TileMap m) {
   using L = Lat<Q>;
   static_assert(L::D == 3, "3-D lattices");
-  constexpr int NS = 6;
-  constexpr int W = kTX + 2, H = kTY + 2, RS = W * H;
-  constexpr int NT = kTX * kTY;
-  static_assert(RS <= 2 * NT, "two region elements per thread");
-  __shared__ S sp[NS][RS];
+  constexpr int NS = 6, NT = kTX * kTY;
+  constexpr int W1 = kTX + 2, H1 = kTY + 2, R1 = W1 * H1;  // sigma: halo 1
+  constexpr int W2 = kTX + 4, H2 = kTY + 4, R2 = W2 * H2;  // psi: halo 2
+  static_assert(R1 <= 2 * NT && R2 <= 2 * NT, "two region elements per thread");
+  __shared__ S sp[R2];
+  __shared__ S ss[NS][R1];
   int bx, by, bz;
   if (!tile_of(m, bx, by, bz)) return;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
@@ -770,121 +776,100 @@ __global__ __launch_bounds__(kTX* kTY) void k_force_stress_fv3(Geom g, const S* 
   const int x = x0 + tx, y = y0 + ty;
   const bool live = x < g.nx && y < g.ny;
   int rxy[2];
-  region_offsets<W>(g, x0, y0, -1, -1, near, tid, rxy);
-  S fp[3][3];  // F at planes p-1, p, p+1
+  region_offsets<W2>(g, x0, y0, -2, -2, near, tid, rxy);
+  // The sigma elements of this thread: e = tid + k NT < R1, centred at c2[k]
+  // in the psi region.
+  const int nk = tid + NT < R1 ? 2 : 1;
+  int c2[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int e = tid + k * NT;
+    c2[k] = (e % W1 + 1) + W2 * (e / W1 + 1);
+  }
+  SoPlanes<S> so[2];
+  S gp[2][3][3];  // gradient partial sums of each element at planes p-1, p, p+1
+  S fp[3][3];     // F partial sums at planes q-1, q, q+1 (q the folded sigma plane)
 #pragma unroll
   for (int j = 0; j < 3; ++j)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) fp[j][a] = S(0);
+    for (int a = 0; a < 3; ++a) {
+      gp[0][j][a] = gp[1][j][a] = S(0);
+      fp[j][a] = S(0);
+    }
   const int plane = g.nx * g.ny;
-  int pz = wrap_any(z0 - 1, g.nz);
-  for (int p = z0 - 1; p <= z1; ++p, pz = next_plane(pz, g.nz)) {
+  int pz = wrap_any(z0 - 2, g.nz);
+  for (int p = z0 - 2; p <= z1 + 1; ++p, pz = next_plane(pz, g.nz)) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int e = tid + k * NT;
-      if (e < RS) {
-        const int site = (k ? rxy[1] : rxy[0]) + plane * pz;
-#pragma unroll
-        for (int c = 0; c < NS; ++c) sp[c][e] = sig[static_cast<size_t>(c) * g.N + site];
-      }
+      if (e < R2) sp[e] = psi[rxy[k] + plane * pz];
     }
     __syncthreads();
+    // psi(p) completes sigma(p - 1) once planes p-2, p-1 are in (p >= z0).
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const int e = (tx + 1 + L::cx[i]) + W * (ty + 1 + L::cy[i]);
-      const int ci[3] = {L::cx[i], L::cy[i], L::cz[i]};
+    for (int k = 0; k < 2; ++k) {
+      if (k >= nk) break;
+      const S* P = sp + c2[k];
+      so[k].template push<W2>(P);
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const S t = S(L::w[i]) * P[L::cx[i] + W2 * L::cy[i]];
+        if (L::cx[i]) gp[k][1 - L::cz[i]][0] += L::cx[i] * t;
+        if (L::cy[i]) gp[k][1 - L::cz[i]][1] += L::cy[i] * t;
+        if (L::cz[i]) gp[k][1 - L::cz[i]][2] += L::cz[i] * t;
+      }
+      if (p >= z0) {
+        const int e = tid + k * NT;
+        S gr[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gr[a] = gp[k][0][a] * S(3);
+        const S ps = so[k].c[1];
+        const S lap = so[k].lap();
+        const S g2 = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+        const S iso = S(0.5) * co.a * ps * ps + S(0.75) * co.b * ps * ps * ps * ps -
+                      co.kappa * ps * lap - S(0.5) * co.kappa * g2;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = a; b < 3; ++b)
+            ss[sym_idx<3>(a, b)][e] = co.kappa * gr[a] * gr[b] + (a == b ? iso : S(0));
+      }
+      so[k].roll();
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        S acc = 0;
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-          if (ci[b]) acc += ci[b] * sp[sym_idx<3>(a, b)][e];
-        fp[1 - L::cz[i]][a] -= S(3) * S(L::w[i]) * acc;
+        gp[k][0][a] = gp[k][1][a];
+        gp[k][1][a] = gp[k][2][a];
+        gp[k][2][a] = S(0);
       }
     }
-    if (p - 1 >= z0 && p - 1 < z1 && live) {
-      const int s = x + g.nx * (y + g.ny * (p - 1));
-#pragma unroll
-      for (int a = 0; a < 3; ++a) F[static_cast<size_t>(a) * g.N + s] = fp[0][a];
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      fp[0][a] = fp[1][a];
-      fp[1][a] = fp[2][a];
-      fp[2][a] = S(0);
-    }
     __syncthreads();
-  }
-}
-
-// The order-parameter stress of the FV variant in 3-D, z-marching: one plane
-// of psi (halo 1) in LDS at a time; the gradient g = 3 sum_i w_i c_i psi(x + c_i)
-// is carried as register partial sums for the planes below, at and above the
-// newest one, and L_SO psi from the per-plane sums of SoPlanes.  sigma is
-// written for the middle plane, with the same formula as the per-site form.
-template <typename S, int Q>
-__global__ __launch_bounds__(kTX* kTY) void k_stress_fv3(Geom g, Coef<S> co,
-                                                       const S* __restrict__ psi,
-                                                       S* __restrict__ sig, int zc, TileMap m) {
-  using L = Lat<Q>;
-  static_assert(L::D == 3, "3-D lattices");
-  using R = PsiPlane<S>;
-  constexpr int W = R::W;
-  __shared__ R sp;
-  int bx, by, bz;
-  if (!tile_of(m, bx, by, bz)) return;
-  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTX + tx;
-  const int x0 = bx * kTX, y0 = by * kTY;
-  const bool near = g.nx >= kTX + 8 && g.ny >= kTY + 8;
-  const int z0 = bz * zc, z1 = min(z0 + zc, g.nz);
-  const int x = x0 + tx, y = y0 + ty;
-  const bool live = x < g.nx && y < g.ny;
-  int rxy[2];
-  region_offsets<W>(g, x0, y0, -1, -1, near, tid, rxy);
-  SoPlanes<S> so;
-  S gp[3][3];  // gradient partial sums at planes p-1, p, p+1
+    if (p >= z0) {
+      // sigma(q), q = p - 1, at (x + c_ix, y + c_iy) feeds F at plane q - c_iz.
 #pragma unroll
-  for (int j = 0; j < 3; ++j)
+      for (int i = 1; i < Q; ++i) {
+        const int e = (tx + 1 + L::cx[i]) + W1 * (ty + 1 + L::cy[i]);
+        const int ci[3] = {L::cx[i], L::cy[i], L::cz[i]};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) gp[j][a] = S(0);
-  const int plane = g.nx * g.ny;
-  int pz = wrap_any(z0 - 1, g.nz);
-  for (int p = z0 - 1; p <= z1; ++p, pz = next_plane(pz, g.nz)) {
-    prep_load_psi(sp, psi, rxy, plane * pz, tid);
-    __syncthreads();
-    so.template push<W>(sp.v + (tx + 1) + W * (ty + 1));
+        for (int a = 0; a < 3; ++a) {
+          S acc = 0;
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const S t = S(L::w[i]) * sp.v[(tx + 1 + L::cx[i]) + W * (ty + 1 + L::cy[i])];
-      if (L::cx[i]) gp[1 - L::cz[i]][0] += L::cx[i] * t;
-      if (L::cy[i]) gp[1 - L::cz[i]][1] += L::cy[i] * t;
-      if (L::cz[i]) gp[1 - L::cz[i]][2] += L::cz[i] * t;
+          for (int b = 0; b < 3; ++b)
+            if (ci[b]) acc += ci[b] * ss[sym_idx<3>(a, b)][e];
+          fp[1 - L::cz[i]][a] -= S(3) * S(L::w[i]) * acc;
+        }
+      }
+      if (p - 2 >= z0 && p - 2 < z1 && live) {
+        const int s = x + g.nx * (y + g.ny * (p - 2));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) F[static_cast<size_t>(a) * g.N + s] = fp[0][a];
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        fp[0][a] = fp[1][a];
+        fp[1][a] = fp[2][a];
+        fp[2][a] = S(0);
+      }
     }
-    if (p - 1 >= z0 && p - 1 < z1 && live) {
-      const int s = x + g.nx * (y + g.ny * (p - 1));
-      S gr[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) gr[a] = gp[0][a] * S(3);
-      const S ps = so.c[1];
-      const S lap = so.lap();
-      const S g2 = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
-      const S iso = S(0.5) * co.a * ps * ps + S(0.75) * co.b * ps * ps * ps * ps -
-                    co.kappa * ps * lap - S(0.5) * co.kappa * g2;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = a; b < 3; ++b)
-          sig[static_cast<size_t>(sym_idx<3>(a, b)) * g.N + s] =
-              co.kappa * gr[a] * gr[b] + (a == b ? iso : S(0));
-    }
-    so.roll();
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      gp[0][a] = gp[1][a];
-      gp[1][a] = gp[2][a];
-      gp[2][a] = S(0);
-    }
-    __syncthreads();
   }
 }
 
