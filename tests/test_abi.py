@@ -103,3 +103,21 @@ def test_null_handles():
     assert lbl.lbl_destroy(None) == 0
     assert lbl.lbl_step(None, 1) == lbl.LBL_E_INVAL
     assert lbl.lbl_observe(None, 0, None, 0, 0) == lbl.LBL_E_INVAL
+
+
+@pytest.mark.parametrize("lattice,smol,shape,sigma_stored",
+                         [(lbl.LBL_D3Q19, lbl.LBL_SMOL_FV, (24, 20, 16), False),
+                          (lbl.LBL_D3Q19, lbl.LBL_SMOL_FD, (24, 20, 16), True),
+                          (lbl.LBL_D2Q9, lbl.LBL_SMOL_FV, (24, 20, 1), True)])
+@pytest.mark.parametrize("precision,b", [(lbl.LBL_FP64, 8), (lbl.LBL_FP32DEV, 4)])
+def test_stress_force_memory(lattice, smol, shape, sigma_stored, precision, b):
+    """The stress-divergence force adds the force density (d N values) and,
+    except in the fused FV pass on 3-D lattices, the d(d+1)/2 stress
+    components; lbl_sim_bytes counts exactly that (host-only call)."""
+    kw = dict(lattice=lattice, smol=smol, precision=precision, shape=shape)
+    base = lbl.lbl_sim_bytes(lbl.make_params(**kw))
+    stress = lbl.lbl_sim_bytes(lbl.make_params(force_form=1, **kw))
+    N = shape[0] * shape[1] * shape[2]
+    d = 2 if lattice == lbl.LBL_D2Q9 else 3
+    assert base > 0
+    assert stress - base == b * N * (d + (d * (d + 1) // 2 if sigma_stored else 0))
