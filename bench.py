@@ -406,10 +406,14 @@ def main():
         if kb is None:
             continue
         achieved = kb * N / avg_s / 1e9
+        traffic = traffic_for(kname, args.workload)
         per_kernel[kname] = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(achieved / HBM_PEAK_GBS, 4),
-                             "traffic": traffic_for(kname, args.workload),
+                             "traffic": traffic,
+                             # the measured HBM bytes moved at this launch time
+                             "traffic_gbs": (round(traffic / avg_s / 1e9, 1)
+                                             if traffic is not None else None),
                              "avg_launch_ms": round(avg_s * 1e3, 4), "launches": klaunch,
                              "alg_bytes_per_site": kb}
     dom = max(r["ktimes"], key=lambda t: t[2])[0]
@@ -437,6 +441,7 @@ def main():
         "alg_bytes_per_site_step": alg_bytes_per_site(w),
         "roofline": roofline,
         "kernel_rooflines": {k: {"frac": v["frac"], "achieved": v["achieved"],
+                                 "traffic_gbs": v["traffic_gbs"],
                                  "avg_launch_ms": v["avg_launch_ms"]}
                              for k, v in per_kernel.items()},
         "kernels_ms_per_step": {t[0]: round(t[2] / max(1, args.steps), 4) for t in r["ktimes"]},
