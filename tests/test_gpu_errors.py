@@ -159,3 +159,22 @@ def test_argument_errors():
         assert "not available" in lbl.lbl_last_error(sim.handle)
         sim.step(1)
         assert sim.observe(lbl.LBL_OBS_STEP) == 1
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("options", [{}, {"force_form": 1}, {"sample_full_k": 1}])
+def test_sim_bytes_match_the_allocations(case, options):
+    """The pool admits requests by lbl_sim_bytes: it must equal what
+    lbl_create takes through the allocator (zero-sized buffers are taken as 8
+    bytes; hipFFT's own work areas are outside the callback)."""
+    from paper_1104_0078_amd import lbl
+    c = H.config(**CASES[case])
+    params = H.lbl_params(c)
+    for k, v in options.items():
+        setattr(params, k, v)
+    mem = CountingMemory()
+    with lbl.Sim(params, lbl.make_init(kind=c["init"], psi_std=1e-3), memory=mem):
+        taken = sum(mem.live.values())
+        n = len(mem.live)
+    want = lbl.lbl_sim_bytes(params)
+    assert want <= taken <= want + 8 * n
