@@ -123,10 +123,14 @@ def traffic_for(kernel, workload):
     return None
 
 
-def cpu_baseline(w, workload_name, min_seconds=10.0, max_steps=200):
+def cpu_baseline(w, workload_name, min_seconds=10.0, max_steps=200, lbl=None):
     """The FP64 oracle, as it stands, on a bounded sample of the same
     workload: steps of the same lattice until at least `min_seconds` of host
-    time have passed (at most `max_steps`), timed on the host cores."""
+    time have passed (at most `max_steps`), timed on the host cores.  With
+    the library given, the GPU then takes the same steps from the same
+    initial state in FP64 and in FP32-deviation storage, and the errors of
+    its psi and populations against the oracle's are reported."""
+    import numpy as np
     import oracle as O
 
     p = O.make_params(lattice=w["lattice"], smol=w["smol"], shape=w["shape"], a=w["a"],
@@ -141,9 +145,23 @@ def cpu_baseline(w, workload_name, min_seconds=10.0, max_steps=200):
         nsteps += 1
         dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": N * nsteps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": "%d step(s) of %s (%d sites), FP64 oracle, %.1f s" % (
-                nsteps, workload_name, N, dt)}
+    out = {"value": N * nsteps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": "%d step(s) of %s (%d sites), FP64 oracle, %.1f s" % (
+               nsteps, workload_name, N, dt)}
+    if lbl is not None:
+        def rel(got, ref):
+            return float(np.abs(got - ref).max() / np.abs(ref).max())
+        err = {"steps": nsteps, "measure": "max |gpu - oracle| / max |oracle| over all sites",
+               "bound": {"fp64": 1e-12, "fp32dev": 1e-5}}
+        for name, prec in (("fp64", 0), ("fp32dev", 1)):
+            init = lbl.make_init(kind=w["init"], psi_std=w["psi_std"])
+            with lbl.Sim(make_sim_params(lbl, w, prec), init, device=0) as sim:
+                sim.step(nsteps)
+                e_psi = rel(sim.observe(lbl.LBL_OBS_PSI), psi)
+                e_pop = rel(sim.observe(lbl.LBL_OBS_POP), f)
+            err[name] = {"psi": e_psi, "pop": e_pop}
+        out["gpu_error_vs_oracle"] = err
+    return out
 
 
 def make_sim_params(lbl, w, precision=None, seed=1234):
@@ -503,7 +521,7 @@ def main():
             print("served (below saturation) done: p50 %.2f s p99 %.2f s" % (
                 sub["p50_s"], sub["p99_s"]), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.workload)
+        out["cpu_baseline"] = cpu_baseline(w, args.workload, lbl=lbl)
     print(json.dumps(out), flush=True)
 
 
