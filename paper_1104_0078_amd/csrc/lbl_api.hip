@@ -152,6 +152,7 @@ void release_all(lbl_sim* s) {
 }
 
 inline int grid_for(int n) { return (n + kBlock - 1) / kBlock; }
+inline int grid_for64(int64_t n) { return static_cast<int>((n + kBlock - 1) / kBlock); }
 
 // Values of the real-to-complex half spectrum: nz x ny x (nx/2 + 1).
 size_t half_spectrum(const lbl_params& p) {
@@ -932,7 +933,8 @@ struct Impl {
         }
         const LBArgs<S> a = lb_args(s, f, nullptr, psi, ubuf, full, 0);
         if (int rc = launch_lb(s, a, false, "k_lb_u")) return rc;
-        k_to_f64<S><<<grid_for(s->d * s->N), kBlock, 0, s->stream>>>(s->d * s->N, ubuf, dst);
+        const int64_t nu = static_cast<int64_t>(s->d) * s->N;
+        k_to_f64<S><<<grid_for64(nu), kBlock, 0, s->stream>>>(nu, ubuf, dst);
         return launched(s, "k_to_f64");
       }
       case LBL_OBS_TOTALS:

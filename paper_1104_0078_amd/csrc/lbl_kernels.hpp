@@ -478,12 +478,12 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
     // Read back only after other passes have streamed through the caches.
     if constexpr (NT) {
       __builtin_nontemporal_store(ux, &a.u_out[s]);
-      __builtin_nontemporal_store(uy, &a.u_out[g.N + s]);
-      if (D == 3) __builtin_nontemporal_store(uz, &a.u_out[2 * g.N + s]);
+      __builtin_nontemporal_store(uy, &a.u_out[static_cast<size_t>(g.N) + s]);
+      if (D == 3) __builtin_nontemporal_store(uz, &a.u_out[2 * static_cast<size_t>(g.N) + s]);
     } else {
       a.u_out[s] = ux;
-      a.u_out[g.N + s] = uy;
-      if (D == 3) a.u_out[2 * g.N + s] = uz;
+      a.u_out[static_cast<size_t>(g.N) + s] = uy;
+      if (D == 3) a.u_out[2 * static_cast<size_t>(g.N) + s] = uz;
     }
   }
   if constexpr (!COLLIDE) return;
@@ -1011,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_power_acc(int nh, const S* __restrict__
                                                    double scale, double* __restrict__ acc) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= nh) return;
-  const double re = spec[2 * i], im = spec[2 * i + 1];
+  const double re = spec[2 * static_cast<size_t>(i)], im = spec[2 * static_cast<size_t>(i) + 1];
   acc[i] += (re * re + im * im) * scale;
 }
 
@@ -1022,8 +1022,8 @@ __global__ __launch_bounds__(256) void k_fourier_scale(int nh, const S* __restri
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= nh) return;
   const S a = amp[i];
-  spec[2 * i] *= a;
-  spec[2 * i + 1] *= a;
+  spec[2 * static_cast<size_t>(i)] *= a;
+  spec[2 * static_cast<size_t>(i) + 1] *= a;
 }
 
 // ---------------------------------------------------------------------------
@@ -1507,17 +1507,19 @@ __global__ __launch_bounds__(256) void k_gather(Geom g, double rho0, const S* __
   if (rho) rho[s] = r;
 }
 
+// Element counts up to d*N exceed 2^31 on the largest lattices: 64-bit
+// indices.
 template <typename S>
-__global__ __launch_bounds__(256) void k_to_f64(int n, const S* __restrict__ in,
+__global__ __launch_bounds__(256) void k_to_f64(int64_t n, const S* __restrict__ in,
                                                 double* __restrict__ out) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s < n) out[s] = static_cast<double>(in[s]);
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void k_from_f64(int n, const double* __restrict__ in,
+__global__ __launch_bounds__(256) void k_from_f64(int64_t n, const double* __restrict__ in,
                                                   S* __restrict__ out) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s < n) out[s] = static_cast<S>(in[s]);
 }
 

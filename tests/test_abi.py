@@ -121,3 +121,30 @@ def test_stress_force_memory(lattice, smol, shape, sigma_stored, precision, b):
     d = 2 if lattice == lbl.LBL_D2Q9 else 3
     assert base > 0
     assert stress - base == b * N * (d + (d * (d + 1) // 2 if sigma_stored else 0))
+
+
+def test_largest_lattices_are_sized_without_overflow():
+    """Lattices whose vector fields hold more than 2^31 values are valid
+    (N < 2^31 sites): an FP32-deviation D3Q19 lattice of 896^3 sites (about
+    147 GB) is sized in 64-bit arithmetic, and N >= 2^31 is refused.  The
+    device code offsets every component of a field by a 64-bit multiple of
+    N (checked in the sources below)."""
+    n = 896
+    N = n ** 3
+    assert 3 * N > 2 ** 31
+    got = lbl.lbl_sim_bytes(lbl.make_params(lattice=lbl.LBL_D3Q19, smol=lbl.LBL_SMOL_FV,
+                                            precision=lbl.LBL_FP32DEV, shape=(n, n, n)))
+    fields = 2 * 19 + 6 + 3 + 1 + 3  # populations x2, psi/phi x2, acc, mu, u, noise, u_end
+    assert fields * 4 * N <= got < fields * 4 * N + (64 << 20)
+    assert lbl.lbl_sim_bytes(lbl.make_params(lattice=lbl.LBL_D3Q19,
+                                             shape=(1291, 1291, 1291))) == 0
+
+
+def test_component_offsets_use_64_bit_arithmetic():
+    """No device source forms a component offset as the 32-bit product or sum
+    of N and a site index (k * g.N + s must be taken in size_t)."""
+    import glob
+    bad = re.compile(r"\[\s*(\d+\s*\*\s*)?g\.N\s*\+")
+    for path in glob.glob(os.path.join(ROOT, "paper_1104_0078_amd", "csrc", "*")):
+        for k, line in enumerate(open(path), 1):
+            assert not bad.search(line), "%s:%d: %s" % (path, k, line.strip())

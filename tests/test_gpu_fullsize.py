@@ -71,3 +71,44 @@ def test_full_size_sampled_parity(oracle_state, precision, schedule):
     ctol = 1e-13 if precision == H.FP64 else 1e-6
     assert abs(tot1[0] - tot0[0]) <= ctol * abs(tot0[0])
     assert abs(tot1[4] - tot0[4]) <= ctol * tot0[9] + 1e-300
+
+
+SHAPE_W = (128, 128, 128)
+WINDOW = 100
+
+
+@pytest.fixture(scope="module")
+def oracle_window():
+    """The same two-phase workload on a 128^3 lattice, 100 oracle steps (the
+    acceptance window)."""
+    c = H.config(lattice=H.D3Q19, smol=H.FV, shape=SHAPE_W, a=-0.04, b=0.04, kappa=0.05,
+                 M=0.1, kT=1e-5, eta=0.1, init=1, psi_std=1e-3)
+    print("window oracle: %s, %d steps" % (SHAPE_W, WINDOW), flush=True)
+    f, psi = H.oracle_run(c, WINDOW)
+    return c, f.reshape(19, -1), psi.reshape(-1)
+
+
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
+def test_window_128_sampled_parity(oracle_window, precision):
+    """100 steps of the 128^3 two-phase workload: 200 000 sampled sites and
+    the interface plane z = L/4 against the oracle, FP64 within 1e-12 and
+    FP32-deviation within 1e-5."""
+
+    from paper_1104_0078_amd import lbl
+    c0, f_ref, psi_ref = oracle_window
+    c = dict(c0, precision=precision)
+    print("window case: 128^3 precision %d, %d steps" % (precision, WINDOW), flush=True)
+    N = SHAPE_W[0] * SHAPE_W[1] * SHAPE_W[2]
+    rng = np.random.default_rng(11)
+    idx = rng.choice(N, size=200000, replace=False)
+    row = np.arange(SHAPE_W[0] * SHAPE_W[1]) + (SHAPE_W[2] // 4) * SHAPE_W[0] * SHAPE_W[1]
+    s = np.unique(np.concatenate([idx, row]))
+    with lbl.Sim(H.lbl_params(c), lbl.make_init(kind=1, psi_std=1e-3)) as sim:
+        sim.step(WINDOW)
+        f_gpu = sim.observe(lbl.LBL_OBS_POP).reshape(19, N)[:, s]
+        psi_gpu = sim.observe(lbl.LBL_OBS_PSI)[s]
+    ef = float(np.abs(f_gpu - f_ref[:, s]).max() / np.abs(f_ref).max())
+    ep = float(np.abs(psi_gpu - psi_ref[s]).max() / np.abs(psi_ref).max())
+    print("  rel err populations %.3e psi %.3e over %d sites" % (ef, ep, s.size), flush=True)
+    tol = H.TOL[precision]
+    assert ef <= tol and ep <= tol

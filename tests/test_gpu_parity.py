@@ -50,6 +50,49 @@ def test_coupled_two_phase_tanh(lattice, smol):
     _check(c, 20)
 
 
+@pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q15, H.D3Q19])
+@pytest.mark.parametrize("smol", [H.FD, H.FV])
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
+@pytest.mark.parametrize("rk", [1, 4])
+def test_coupled_euler_and_rk4(lattice, smol, precision, rk):
+    """Full coupling with Euler and RK4 stages, two-phase: the RK4 mid stages
+    advect with the mean of u^n and the velocity of the streamed populations,
+    and the RK4 accumulator carries the weighted stage sums."""
+    c = H.config(lattice=lattice, smol=smol, precision=precision, rk=rk, shape=SHAPES[lattice],
+                 a=-0.04, b=0.04, kappa=0.05, init=1, kT=1e-5)
+    _check(c, 20)
+
+
+@pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q19])
+@pytest.mark.parametrize("rk", [1, 4])
+def test_coupled_euler_and_rk4_one_phase(lattice, rk):
+    c = H.config(lattice=lattice, smol=H.FV, rk=rk, shape=SHAPES[lattice], kT=1e-4)
+    _check(c, 20)
+
+
+# The acceptance window: GPU and oracle fields over the first 100 steps on the
+# same Philox stream, FP64 within 1e-12 and FP32-deviation within 1e-5.
+WINDOW = 100
+
+
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
+def test_window_d2q9_fd_64(precision):
+    """D2Q9 + FD on the 64 x 64 periodic lattice at tau_s = 0.8 (eta = 0.1),
+    other rates 1, kT = 1e-5, M = 0.1, A = 0.04, B = 0.1, K = 0.05,
+    psi0 = N(0, 1e-3), seed 1234."""
+    c = H.config(lattice=H.D2Q9, smol=H.FD, precision=precision, shape=(64, 64, 1))
+    _check(c, WINDOW)
+
+
+@pytest.mark.parametrize("lattice", [H.D3Q15, H.D3Q19])
+@pytest.mark.parametrize("two_phase", [False, True])
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
+def test_window_3d_fv(lattice, two_phase, precision):
+    kw = dict(a=-0.04, b=0.04, kappa=0.05, init=1) if two_phase else {}
+    c = H.config(lattice=lattice, smol=H.FV, precision=precision, shape=SHAPES[lattice], **kw)
+    _check(c, WINDOW)
+
+
 @pytest.mark.parametrize("coupling", [H.SMOL_ONLY, H.LB_ONLY])
 @pytest.mark.parametrize("rk", [1, 2, 4])
 def test_partial_couplings_and_stages(coupling, rk):

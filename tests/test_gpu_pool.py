@@ -44,6 +44,14 @@ MIX = [
     # ragged SMOL tiles in x and y, LB rows longer than 64 sites
     (H.config(lattice=H.D3Q19, smol=H.FV, shape=(70, 21, 9), seed=18, a=-0.04, b=0.04,
               init=1), 13),
+    # Euler and RK4 stages under full coupling (batched stage kernels with
+    # rk = 1 and rk = 4, the RK4 accumulator)
+    (H.config(lattice=H.D2Q9, smol=H.FD, shape=(40, 36, 1), seed=19, rk=1, a=-0.04, b=0.04,
+              init=1), 15),
+    (H.config(lattice=H.D3Q19, smol=H.FV, shape=(18, 14, 12), seed=20, rk=4, a=-0.04, b=0.04,
+              init=1), 14),
+    (H.config(lattice=H.D2Q9, smol=H.FV, precision=H.FP32DEV, shape=(36, 40, 1), seed=22,
+              rk=4), 16),
 ]
 
 
