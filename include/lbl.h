@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define LBL_ABI_VERSION 3
+#define LBL_ABI_VERSION 4
 
 typedef struct lbl_sim lbl_sim;
 
@@ -399,11 +399,43 @@ const char *lbl_pool_last_error(const lbl_pool *pool);
 /* Release the pool, cancelling what is still queued or running. */
 int lbl_pool_destroy(lbl_pool *pool);
 
+/* ------------------------------------------------------------------------
+ * Stepping without allocation.  For callers that cannot allocate device
+ * memory: code under HIP graph capture, serving loops and harnesses that
+ * forbid hipMalloc.
+ *
+ * lbl_step_static advances a state held by the caller by nsteps coupled
+ * steps.  pop (Q*N FP64, the canonical order of the POP observable: fbar at
+ * step step0) and psi (N FP64) are device memory of the current device; they
+ * are read first and then overwritten with the state after nsteps steps.
+ * The result is bit for bit that of lbl_create with an LBL_INIT_USER state
+ * (pop, psi, step0) followed by lbl_step(nsteps) and the LBL_OBS_POP and
+ * LBL_OBS_PSI observables.  Every other field of the step (the second
+ * population buffer, stage inputs, velocities, chemical potential, noise)
+ * lives in a workspace of LBL_STATIC_SCRATCH_BYTES bytes that the library
+ * holds on each device until the process ends; the call allocates no device
+ * memory and creates no stream, event or FFT plan.  Work is enqueued on
+ * `stream` (a hipStream_t; NULL is the null stream) and the call returns
+ * without waiting.  All calls on one device share its workspace, which keeps
+ * the last call's contents: calls that overlap in time on one device race,
+ * so order them on one stream.  The first call on a device resolves the
+ * workspace's address (hipGetSymbolAddress); make it outside graph capture.
+ * Errors: LBL_E_INVAL (NULL pointers, nsteps < 0, invalid parameters as for
+ * lbl_create, fd_noise = LBL_FDNOISE_FOURIER, sample_every or sample_full_k
+ * not 0), LBL_E_NOMEM (the lattice's buffers, lbl_sim_bytes(params) plus
+ * 256-byte alignment of each, exceed the workspace), LBL_E_DEVICE.  The
+ * message of the last failure on this thread is lbl_last_error(NULL).
+ */
+#define LBL_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int lbl_step_static(const lbl_params *params, void *stream, int64_t step0, int64_t nsteps,
+                    double *pop, double *psi);
+
 /* Static text for a status code. */
 const char *lbl_strerror(int status);
 
 /* Text of the last error raised on this handle ("" if none).  With a NULL
- * handle: the last error of a failed lbl_create on this thread. */
+ * handle: the last error of a failed lbl_create or lbl_step_static on this
+ * thread. */
 const char *lbl_last_error(const lbl_sim *sim);
 
 /* LBL_ABI_VERSION of the loaded library. */

@@ -10,6 +10,8 @@
 #include <cmath>
 #include <deque>
 #include <map>
+#include <mutex>
+#include <array>
 #include <cstdio>
 #include <cstring>
 #include <exception>
@@ -1010,13 +1012,16 @@ Table select(const lbl_params& p) {
 }
 
 // Device allocations of one simulation, in creation order.
-std::vector<size_t> alloc_plan(const lbl_params& p) {
+constexpr int kPlanBuffers = 23;
+using Plan = std::array<size_t, kPlanBuffers>;
+
+Plan alloc_plan(const lbl_params& p) {
   const int q = p.lattice, d = p.lattice == LBL_D2Q9 ? 2 : 3;
   const size_t N = static_cast<size_t>(p.nx) * p.ny * p.nz;
   const size_t sz = p.precision == LBL_FP64 ? 8 : 4;
   const int Lmax = std::max(p.nx, std::max(p.ny, p.nz));
   const int nparts = std::min(1024, std::max(1, static_cast<int>((N + kBlock - 1) / kBlock)));
-  return {sz * N * q, sz * N * q, sz * N, sz * N, sz * N, sz * N, sz * N, sz * N,
+  return Plan{sz * N * q, sz * N * q, sz * N, sz * N, sz * N, sz * N, sz * N, sz * N,
           sz * N * d, sz * N, sizeof(double) * 10 * nparts, sizeof(double) * 16,
           sizeof(double) * kMaxFields * 3 * Lmax,
           sizeof(double) * kMaxFields * static_cast<size_t>(p.nz) * p.nx,
@@ -1065,13 +1070,10 @@ size_t obs_bytes(const lbl_sim* s, int what) {
   }
 }
 
-int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* env,
-                lbl_sim** out) {
-  if (!out) return fail(nullptr, LBL_E_INVAL, "out must not be NULL");
-  *out = nullptr;
-  if (int rc = validate(params, init)) return rc;
-  lbl_sim* s = new (std::nothrow) lbl_sim();
-  if (!s) return fail(nullptr, LBL_E_NOMEM, "host allocation failed");
+// Fields of a simulation that follow from its parameters alone: sizes, the
+// Philox key, the relaxation rates and noise amplitudes of the mode classes,
+// and the default launch schedule.
+void setup_fields(lbl_sim* s, const lbl_params* params) {
   s->p = *params;
   s->q = params->lattice;
   s->d = params->lattice == LBL_D2Q9 ? 2 : 3;
@@ -1080,6 +1082,58 @@ int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* e
   s->ssize = params->precision == LBL_FP64 ? 8 : 4;
   s->k0 = static_cast<uint32_t>(params->seed);
   s->k1 = static_cast<uint32_t>(params->seed >> 32);
+  const double ws = 1.0 / (0.5 + params->eta / (params->rho * kCs2));
+  s->gamma_s = 1.0 - ws;
+  s->gamma_b = 1.0 - params->omega_bulk;
+  s->gamma_g = 1.0 - params->omega_ghost;
+  auto sig = [&](double g) { return std::sqrt((1.0 - g * g) * params->rho * params->kT / kCs2); };
+  s->sigma_s = sig(s->gamma_s);
+  s->sigma_b = sig(s->gamma_b);
+  s->sigma_g = sig(s->gamma_g);
+  // z-chunks of the tiled SMOL kernels: set from their occupancy at init.
+  s->zc = s->zc_prep = params->nz;
+  // LB blocks: the widest power of two up to 256 that fits along x (whole
+  // rows where possible, so that pulls shifted along x stay inside a block).
+  s->lb_lw = 5;
+  while (s->lb_lw < 8 && (2 << s->lb_lw) <= params->nx) ++s->lb_lw;
+  s->nparts = std::min(1024, std::max(1, grid_for(s->N)));
+}
+
+// Buffers of the allocation plan, in plan order.
+void assign_buffers(lbl_sim* s, const std::array<void*, kPlanBuffers>& b) {
+  s->f[0] = b[0];
+  s->f[1] = b[1];
+  s->psi[0] = b[2];
+  s->psi[1] = b[3];
+  s->phi[0] = b[4];
+  s->phi[1] = b[5];
+  s->acc = b[6];
+  s->mu = b[7];
+  s->u = b[8];
+  s->noise = b[9];
+  s->part = static_cast<double*>(b[10]);
+  s->tot = static_cast<double*>(b[11]);
+  s->planes = static_cast<double*>(b[12]);
+  s->col = static_cast<double*>(b[13]);
+  s->sk = static_cast<double*>(b[14]);
+  s->uk = static_cast<double*>(b[15]);
+  s->u_end = b[16];
+  s->fspec = b[17];
+  s->famp = b[18];
+  s->sig = b[19];
+  s->fstress = b[20];
+  s->fk_spec = b[21];
+  s->fk_acc = static_cast<double*>(b[22]);
+}
+
+int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* env,
+                lbl_sim** out) {
+  if (!out) return fail(nullptr, LBL_E_INVAL, "out must not be NULL");
+  *out = nullptr;
+  if (int rc = validate(params, init)) return rc;
+  lbl_sim* s = new (std::nothrow) lbl_sim();
+  if (!s) return fail(nullptr, LBL_E_NOMEM, "host allocation failed");
+  setup_fields(s, params);
   if (env) {
     s->device = env->device;
     s->stream = static_cast<hipStream_t>(env->stream);
@@ -1097,58 +1151,16 @@ int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* e
     delete s;
     return rc;
   }
-  // Relaxation rates and noise amplitudes of the mode classes.
-  const double ws = 1.0 / (0.5 + params->eta / (params->rho * kCs2));
-  s->gamma_s = 1.0 - ws;
-  s->gamma_b = 1.0 - params->omega_bulk;
-  s->gamma_g = 1.0 - params->omega_ghost;
-  auto sig = [&](double g) { return std::sqrt((1.0 - g * g) * params->rho * params->kT / kCs2); };
-  s->sigma_s = sig(s->gamma_s);
-  s->sigma_b = sig(s->gamma_b);
-  s->sigma_g = sig(s->gamma_g);
-
   const size_t N = static_cast<size_t>(s->N);
   const size_t sz = s->ssize;
-  // z-chunks of the tiled SMOL kernels: set from their occupancy at init.
-  s->zc = s->zc_prep = params->nz;
-  // LB blocks: the widest power of two up to 256 that fits along x (whole
-  // rows where possible, so that pulls shifted along x stay inside a block).
-  s->lb_lw = 5;
-  while (s->lb_lw < 8 && (2 << s->lb_lw) <= params->nx) ++s->lb_lw;
-  s->nparts = std::min(1024, std::max(1, grid_for(s->N)));
-  const std::vector<size_t> plan = alloc_plan(*params);
-  std::vector<void*> bufs;
+  const Plan plan = alloc_plan(*params);
+  std::array<void*, kPlanBuffers> bufs{};
   bool ok = true;
-  for (size_t b : plan) {
-    void* ptr = dev_alloc(s, b);
-    ok = ok && ptr;
-    bufs.push_back(ptr);
+  for (int k = 0; k < kPlanBuffers; ++k) {
+    bufs[k] = dev_alloc(s, plan[k]);
+    ok = ok && bufs[k];
   }
-  if (ok) {
-    s->f[0] = bufs[0];
-    s->f[1] = bufs[1];
-    s->psi[0] = bufs[2];
-    s->psi[1] = bufs[3];
-    s->phi[0] = bufs[4];
-    s->phi[1] = bufs[5];
-    s->acc = bufs[6];
-    s->mu = bufs[7];
-    s->u = bufs[8];
-    s->noise = bufs[9];
-    s->part = static_cast<double*>(bufs[10]);
-    s->tot = static_cast<double*>(bufs[11]);
-    s->planes = static_cast<double*>(bufs[12]);
-    s->col = static_cast<double*>(bufs[13]);
-    s->sk = static_cast<double*>(bufs[14]);
-    s->uk = static_cast<double*>(bufs[15]);
-    s->u_end = bufs[16];
-    s->fspec = bufs[17];
-    s->famp = bufs[18];
-    s->sig = bufs[19];
-    s->fstress = bufs[20];
-    s->fk_spec = bufs[21];
-    s->fk_acc = static_cast<double*>(bufs[22]);
-  }
+  if (ok) assign_buffers(s, bufs);
   if (!ok) {
     std::string msg = "device allocation failed";
     release_all(s);
@@ -1545,9 +1557,116 @@ size_t result_bytes(const PoolReq& r, int what) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Workspace of lbl_step_static: a file-scope device array, one copy per GPU,
+// held from the library's load onto that GPU until the process ends.  In host
+// code its name is only a stand-in symbol; kernels and copies get the address
+// hipGetSymbolAddress returns on each device, resolved once per device.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) unsigned char scratch[LBL_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this device's workspace (the device must be current).
+int scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(nullptr, LBL_E_DEVICE, "device ordinal beyond the workspace table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(nullptr, LBL_E_DEVICE,
+                  std::string("hipGetSymbolAddress(workspace): ") + hipGetErrorString(e));
+    g_scratch_dev[device] = ptr;
+  }
+  *out = g_scratch_dev[device];
+  return LBL_OK;
+}
+
+int zero_async(lbl_sim* s, void* ptr, size_t bytes) {
+  const int64_t n = static_cast<int64_t>(bytes / 4);
+  if (n == 0) return LBL_OK;
+  k_zero_words<<<grid_for64(n), kBlock, 0, s->stream>>>(n, static_cast<uint32_t*>(ptr));
+  return hip_check(s, hipGetLastError(), "k_zero_words");
+}
+
+int step_static_impl(const lbl_params* params, void* stream, int64_t step0, int64_t nsteps,
+                     double* pop, double* psi) {
+  if (!params || !pop || !psi)
+    return fail(nullptr, LBL_E_INVAL, "params, pop and psi must not be NULL");
+  if (nsteps < 0) return fail(nullptr, LBL_E_INVAL, "nsteps must be >= 0");
+  lbl_init ini{};
+  ini.kind = LBL_INIT_USER;
+  ini.user_on_device = 1;
+  ini.psi0 = psi;
+  ini.f0 = pop;
+  ini.step0 = step0;
+  if (int rc = validate(params, &ini)) return rc;
+  if (params->fd_noise != LBL_FDNOISE_LINK)
+    return fail(nullptr, LBL_E_INVAL,
+                "the Fourier-space FD noise needs hipFFT plans, which allocate; "
+                "not available in lbl_step_static");
+  if (params->sample_every != 0 || params->sample_full_k != 0)
+    return fail(nullptr, LBL_E_INVAL, "lbl_step_static takes no samples "
+                                      "(sample_every and sample_full_k must be 0)");
+  // Lay the simulation's buffers out in the workspace, 256-byte aligned.
+  const Plan plan = alloc_plan(*params);
+  std::array<size_t, kPlanBuffers> off{};
+  size_t total = 0;
+  for (int k = 0; k < kPlanBuffers; ++k) {
+    off[k] = total;
+    total += (std::max<size_t>(plan[k], 8) + 255) / 256 * 256;
+  }
+  if (total > LBL_STATIC_SCRATCH_BYTES)
+    return fail(nullptr, LBL_E_NOMEM,
+                "the lattice needs " + std::to_string(total) +
+                    " bytes of workspace, more than the static workspace of " +
+                    std::to_string(static_cast<size_t>(LBL_STATIC_SCRATCH_BYTES)) + " bytes");
+  int dev = 0;
+  if (int rc = hip_check(nullptr, hipGetDevice(&dev), "hipGetDevice")) return rc;
+  void* base = nullptr;
+  if (int rc = scratch_address(dev, &base)) return rc;
+  std::array<void*, kPlanBuffers> bufs{};
+  for (int k = 0; k < kPlanBuffers; ++k) bufs[k] = static_cast<unsigned char*>(base) + off[k];
+  lbl_sim s;
+  setup_fields(&s, params);
+  s.device = dev;
+  s.stream = static_cast<hipStream_t>(stream);
+  assign_buffers(&s, bufs);
+  // The workspace keeps the previous call's contents: clear what the step
+  // reads before writing (the SMOL noise stays zero when kT = 0).
+  int rc = zero_async(&s, s.noise, s.ssize * static_cast<size_t>(s.N));
+  if (!rc) rc = zero_async(&s, s.u, s.ssize * static_cast<size_t>(s.N) * s.d);
+  const Table t = select(*params);
+  if (!rc) rc = t.init(&s, &ini);
+  s.step = step0;
+  if (!rc) rc = t.step(&s, nsteps);
+  if (!rc) rc = t.observe(&s, LBL_OBS_POP, pop);
+  if (!rc) rc = t.observe(&s, LBL_OBS_PSI, psi);
+  if (rc) return fail(nullptr, rc, s.err.empty() ? "lbl_step_static failed" : s.err);
+  return LBL_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int lbl_abi_version(void) { return LBL_ABI_VERSION; }
+
+int lbl_step_static(const lbl_params* params, void* stream, int64_t step0, int64_t nsteps,
+                    double* pop, double* psi) {
+  try {
+    g_create_error.clear();
+    return step_static_impl(params, stream, step0, nsteps, pop, psi);
+  } catch (...) {
+    return fail(nullptr, LBL_E_DEVICE, "unexpected exception in lbl_step_static");
+  }
+}
 
 const char* lbl_strerror(int status) {
   switch (status) {

@@ -1523,6 +1523,13 @@ __global__ __launch_bounds__(256) void k_from_f64(int64_t n, const double* __res
   if (s < n) out[s] = static_cast<S>(in[s]);
 }
 
+// Zero n 32-bit words: a kernel rather than a memset, so that a caller may
+// capture the clear into a graph.
+__global__ __launch_bounds__(256) void k_zero_words(int64_t n, uint32_t* __restrict__ p) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 // Totals in FP64: per-block partials of (rho, j, psi, |rho|, |j|, |psi|),
 // then one block sums the partials in a fixed order (deterministic).
 constexpr int kTotBlock = 256;

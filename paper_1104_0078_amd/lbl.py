@@ -157,6 +157,8 @@ def library():
                   "lbl_pool_result", "lbl_pool_release", "lbl_pool_stats",
                   "lbl_pool_set_schedule", "lbl_pool_get_schedule", "lbl_pool_destroy"):
             getattr(L, n).restype = ctypes.c_int
+        L.lbl_step_static.argtypes = [P(lbl_params), vp, i64, i64, vp, vp]
+        L.lbl_step_static.restype = ctypes.c_int
         L.lbl_abi_version.argtypes = []
         L.lbl_abi_version.restype = ctypes.c_int
         _lib = L
@@ -194,6 +196,18 @@ def lbl_step(sim, nsteps):
 
 def lbl_observe(sim, what, dst_ptr, nbytes, dst_is_device):
     return library().lbl_observe(sim, what, dst_ptr, nbytes, dst_is_device)
+
+
+def lbl_step_static(params, stream, step0, nsteps, pop_ptr, psi_ptr):
+    """Advance the device state (pop, psi) by nsteps steps without allocating
+    (workspace of LBL_STATIC_SCRATCH_BYTES per device).  pop_ptr and psi_ptr
+    are device addresses; stream a hipStream_t handle (0: null stream)."""
+    return library().lbl_step_static(ctypes.byref(params), ctypes.c_void_p(stream),
+                                     int(step0), int(nsteps), ctypes.c_void_p(pop_ptr),
+                                     ctypes.c_void_p(psi_ptr))
+
+
+LBL_STATIC_SCRATCH_BYTES = 64 << 20
 
 
 def lbl_observable_bytes(sim, what):

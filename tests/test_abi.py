@@ -57,7 +57,7 @@ int main(void) {
 
 
 def test_constants_and_strings():
-    assert lbl.lbl_abi_version() == 3
+    assert lbl.lbl_abi_version() == 4
     assert lbl.lbl_strerror(0) == "ok"
     assert "buffer" in lbl.lbl_strerror(lbl.LBL_E_BUFSIZE)
     assert lbl.lbl_strerror(12345) == "unknown status"
