@@ -89,6 +89,31 @@ def kernel_alg_bytes_per_site(name, w, rk=2):
     return None
 
 
+def state_bytes_per_site(name, w):
+    """The part of the step's algorithmic bytes (the state read once and
+    written once, 2 Q b + 2 b per site) that one launch of a kernel moves:
+    the populations (2 Q b) for the LB passes that collide and stream them;
+    None for the kernels whose HBM traffic is the method's intermediate
+    fields (chemical potential, noise, velocities, Runge-Kutta stages)."""
+    b = 8 if w["precision"] == 0 else 4
+    if name == "k_lb":
+        return 2 * w["lattice"] * b
+    return None
+
+
+def step_traffic_per_site(ktimes, workload, steps, N):
+    """Measured HBM bytes of one whole step per site: the committed counter
+    traffic of every kernel (if taken on the current sources) times its
+    launches per step; None when a kernel of the step has no current entry."""
+    total = 0.0
+    for kname, klaunch, _ in ktimes:
+        t = traffic_for(kname, workload)
+        if t is None:
+            return None
+        total += t * klaunch / steps
+    return total / N
+
+
 def source_hash():
     """Hash of the kernel sources with comments and white space removed: the
     committed counter summary stays valid across edits of comments alone and
@@ -144,7 +169,7 @@ def cpu_baseline(w, workload_name, min_seconds=10.0, max_steps=200, lbl=None):
         O.run(p, f, psi, nsteps, 1)
         nsteps += 1
         dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = O.max_threads()
     out = {"value": N * nsteps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
            "sample": "%d step(s) of %s (%d sites), FP64 oracle, %.1f s" % (
                nsteps, workload_name, N, dt)}
@@ -161,6 +186,80 @@ def cpu_baseline(w, workload_name, min_seconds=10.0, max_steps=200, lbl=None):
                 e_pop = rel(sim.observe(lbl.LBL_OBS_POP), f)
             err[name] = {"psi": e_psi, "pop": e_pop}
         out["gpu_error_vs_oracle"] = err
+    return out
+
+
+def cpu_model():
+    """The host CPU's model name (lscpu), for the baseline's context."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return None
+
+
+def _oracle_timed(O, p, w, max_steps, min_seconds):
+    """Oracle steps from the workload's initial state until min_seconds have
+    passed (at most max_steps); returns (f, psi, steps, seconds)."""
+    f, psi = O.init(p, w["init"], w["psi_std"])
+    nsteps, dt = 0, 0.0
+    t0 = time.perf_counter()
+    while nsteps < max_steps and dt < min_seconds:
+        O.run(p, f, psi, nsteps, 1)
+        nsteps += 1
+        dt = time.perf_counter() - t0
+    return f, psi, nsteps, dt
+
+
+def cpu_baseline_plan(lbl, torch):
+    """The oracle on the small specified workloads, each at one thread and at
+    all host threads: D2Q9 + FD 64^2 for its full 2000 steps, and D3Q19 + FV
+    128^3 for a bounded number of steps (its 100-step window would take
+    minutes on one core).  Beside each, the GPU's rate on the same steps and
+    its error against the oracle's fields (FP64 and FP32-deviation)."""
+    import numpy as np
+    import oracle as O
+    nmax = O.max_threads()
+    out = []
+    for name, steps1, stepsn, min1, minn in (("d2q9_fd_fp64_64", 2000, 2000, 1e9, 1e9),
+                                             ("d3q19_fv_fp64_128", 100, 100, 4.0, 8.0)):
+        w = WORKLOADS[name]
+        p = O.make_params(lattice=w["lattice"], smol=w["smol"], shape=w["shape"], a=w["a"],
+                          b=w["b"], kappa=w["kappa"], M=w["M"], kT=w["kT"], eta=w["eta"],
+                          seed=1234)
+        N = O.nsites(p)
+        row = {"workload": name, "sites": N}
+        ref = None
+        for threads, steps, mins in ((1, steps1, min1), (nmax, stepsn, minn)):
+            O.set_threads(threads)
+            f, psi, k, dt = _oracle_timed(O, p, w, steps, mins)
+            row["threads_%d" % threads] = {"steps": k, "seconds": round(dt, 2),
+                                           "mlups": round(N * k / dt / 1e6, 3)}
+            if ref is None or k > ref[2]:
+                ref = (f, psi, k)
+        O.set_threads(nmax)
+        f, psi, k = ref
+        gpu = {}
+        for pname, prec in (("fp64", 0), ("fp32dev", 1)):
+            init = lbl.make_init(kind=w["init"], psi_std=w["psi_std"])
+            with lbl.Sim(make_sim_params(lbl, w, prec), init, device=0) as sim:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sim.step(k)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                e_psi = float(np.abs(sim.observe(lbl.LBL_OBS_PSI) - psi).max() /
+                              np.abs(psi).max())
+                e_pop = float(np.abs(sim.observe(lbl.LBL_OBS_POP) - f).max() / np.abs(f).max())
+            gpu[pname] = {"mlups": round(N * k / dt / 1e6, 1), "err_psi": e_psi,
+                          "err_pop": e_pop}
+        row["gpu_same_steps"] = dict(gpu, steps=k,
+                                     measure="max |gpu - oracle| / max |oracle| over all sites")
+        out.append(row)
     return out
 
 
@@ -356,6 +455,45 @@ def run_served(lbl, torch, rate, seconds, budget_gb=200, tick=200, seed=1234):
                    "FP32/FP64 50/50; steps log-uniform [500, 20000]; S(k) and totals returned"}
 
 
+def pool_error_vs_oracle(lbl, kinds, nsteps=100):
+    """Error against the FP64 oracle of pooled requests: one request of each
+    kind (lattice, variant, phase, storage) at the kind's smallest side runs
+    `nsteps` steps in a pool and its psi is compared with the oracle's over the
+    same steps.  A pooled request's fields are bitwise the same alone and in a
+    mix (tested), so this is the error of every request of the kind."""
+    import numpy as np
+    import oracle as O
+    out = []
+    refs = {}
+    for k in kinds:
+        okey = (k["lattice"], k["smol"], k["shape"], k["two_phase"])
+        a, b = (-0.04, 0.04) if k["two_phase"] else (0.04, 0.1)
+        init = 1 if k["two_phase"] else 0
+        if okey not in refs:
+            p = O.make_params(lattice=k["lattice"], smol=k["smol"], shape=k["shape"], a=a, b=b,
+                              kappa=0.05, M=0.1, kT=1e-5, eta=0.1, seed=k["seed"])
+            f, psi = O.init(p, init, 1e-3)
+            O.run(p, f, psi, 0, nsteps)
+            refs[okey] = psi
+        psi_ref = refs[okey]
+        p = lbl.make_params(lattice=k["lattice"], smol=k["smol"], precision=k["precision"],
+                            shape=k["shape"], rho=1.0, eta=0.1, M=0.1, a=a, b=b, kappa=0.05,
+                            kT=1e-5, seed=k["seed"])
+        with lbl.Pool(8 << 30) as pool:
+            rid = pool.submit(p, lbl.make_init(kind=init, psi_std=1e-3), nsteps, keep_psi=True)
+            while pool.run(50) > 0:
+                pass
+            psi = pool.result(rid, lbl.LBL_RES_PSI)
+        err = float(np.abs(psi - psi_ref).max() / np.abs(psi_ref).max())
+        out.append({"lattice": "D2Q9" if k["lattice"] == 9 else "D3Q19",
+                    "smol": "FD" if k["smol"] == 0 else "FV", "shape": list(k["shape"]),
+                    "two_phase": k["two_phase"],
+                    "storage": "fp64" if k["precision"] == 0 else "fp32-deviation",
+                    "steps": nsteps, "psi_rel_err": err,
+                    "bound": 1e-12 if k["precision"] == 0 else 1e-5})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -363,6 +501,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-plan", action="store_true",
+                    help="skip the oracle timings of the 64^2 and 128^3 workloads")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-fp32", action="store_true",
@@ -384,6 +524,8 @@ def main():
     ap.add_argument("--sub-rate", type=float, default=2.0,
                     help="a second served run below saturation (0: skip)")
     ap.add_argument("--sub-seconds", type=float, default=10.0)
+    ap.add_argument("--bound-budget-gb", type=float, default=6.0,
+                    help="a served run of the same arrivals under this HBM budget (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 2 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -434,9 +576,37 @@ def main():
                                              if traffic is not None else None),
                              "avg_launch_ms": round(avg_s * 1e3, 4), "launches": klaunch,
                              "alg_bytes_per_site": kb}
-    dom = max(r["ktimes"], key=lambda t: t[2])[0]
-    roofline = per_kernel.get(dom)
+    # Headline roofline: the dominant kernel (largest share of device time),
+    # its algorithmic bytes being its share of the step's state bytes (the
+    # populations it reads and writes once), over its mean launch time from
+    # the HIP events of the timed region; beside it the whole step, 2 Q b +
+    # 2 b per site over the step time, and the step's measured HBM traffic.
+    dom_t = max(r["ktimes"], key=lambda t: t[2])
+    dom = dom_t[0]
+    sb = state_bytes_per_site(dom, w)
     step_frac = r["mlups"] * 1e6 * alg_bytes_per_site(w) / (HBM_PEAK_GBS * 1e9)
+    step_traffic = step_traffic_per_site(r["ktimes"], args.workload, args.steps, N)
+    roofline = None
+    if sb is not None:
+        avg_s = dom_t[2] / dom_t[1] / 1e3
+        achieved = sb * N / avg_s / 1e9
+        traffic = traffic_for(dom, args.workload)
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "traffic_gbs": (round(traffic / avg_s / 1e9, 1)
+                                    if traffic is not None else None),
+                    "avg_launch_ms": round(avg_s * 1e3, 4), "launches": dom_t[1],
+                    "alg_bytes_per_site": sb,
+                    "alg_bytes_meaning": "populations read and written once (2Qb), the "
+                                         "kernel's share of the 2Qb + 2b state bytes"}
+    step_roofline = {"alg_bytes_per_site": alg_bytes_per_site(w),
+                     "achieved": round(alg_bytes_per_site(w) * r["mlups"] * 1e6 / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(step_frac, 4),
+                     "traffic_bytes_per_site": (round(step_traffic, 1)
+                                                if step_traffic is not None else None)}
+    if roofline is not None:
+        roofline["step"] = step_roofline
     out = {
         "metric": METRIC,
         "value": round(r["mlups"], 2),
@@ -457,8 +627,11 @@ def main():
                    "parallelism": "single GPU", "schedule": r["schedule"]},
         "hbm_alg_frac_step": round(step_frac, 4),
         "alg_bytes_per_site_step": alg_bytes_per_site(w),
-        "roofline": roofline,
+        "traffic_bytes_per_site_step": step_roofline["traffic_bytes_per_site"],
+        "roofline": roofline if roofline is not None else step_roofline,
+        # kernel level: every field a kernel reads or writes counted once
         "kernel_rooflines": {k: {"frac": v["frac"], "achieved": v["achieved"],
+                                 "alg_bytes_per_site": v["alg_bytes_per_site"],
                                  "traffic_gbs": v["traffic_gbs"],
                                  "avg_launch_ms": v["avg_launch_ms"]}
                              for k, v in per_kernel.items()},
@@ -503,6 +676,10 @@ def main():
             out["batched"][name] = run_ensemble(lbl, torch, prec, args.ensemble_steps, tune)
             print("ensemble %s done: %.1f MLUPS" % (name, out["batched"][name]["mlups"]),
                   file=sys.stderr, flush=True)
+        # the ensemble's kind: D2Q9 + FD one-phase, replica 0's seed, smallest side
+        out["batched"]["error_vs_oracle"] = pool_error_vs_oracle(lbl, [
+            dict(lattice=9, smol=0, shape=(32, 32, 1), two_phase=False, precision=pr,
+                 seed=1234) for pr in (0, 1)])
     if not args.no_served:
         # At the mix's own arrival rate (overloaded: the offered load exceeds
         # the device, so latency includes the queue), then below saturation.
@@ -513,6 +690,24 @@ def main():
         print("served done: p50 %.2f s p99 %.2f s, %.0f MLUPS" % (
             out["served"]["p50_s"], out["served"]["p99_s"], out["served"]["aggregate_mlups"]),
               file=sys.stderr, flush=True)
+        # The same arrivals with an HBM budget that binds: requests wait in
+        # the queue until resident ones finish and release their memory.
+        if args.bound_budget_gb > 0:
+            bb = run_served(lbl, torch, args.serve_rate, args.serve_seconds,
+                            budget_gb=args.bound_budget_gb)
+            bb["sample"] = ("bounded sample of the mix (rate %.3g/s, window %.3g s) under an "
+                            "HBM budget of %g GB" % (args.serve_rate, args.serve_seconds,
+                                                     args.bound_budget_gb))
+            out["served_budget_bound"] = bb
+            print("served (budget %g GB) done: p50 %.2f s p99 %.2f s, max queued %d" % (
+                args.bound_budget_gb, bb["p50_s"], bb["p99_s"], bb["max_queued"]),
+                  file=sys.stderr, flush=True)
+        # one request of every kind of the mix against the oracle
+        kinds = [dict(lattice=lat, smol=sm, shape=shp, two_phase=tp, precision=pr, seed=1234)
+                 for lat, sm, shp in ((9, 0, (64, 64, 1)), (19, 1, (64, 64, 64)))
+                 for tp in (False, True) for pr in (0, 1)]
+        out["served"]["error_vs_oracle"] = pool_error_vs_oracle(lbl, kinds)
+        print("served error vs oracle done", file=sys.stderr, flush=True)
         if args.sub_rate > 0:
             sub = run_served(lbl, torch, args.sub_rate, args.sub_seconds)
             sub["sample"] = "below saturation (rate %.3g/s, window %.3g s)" % (
@@ -522,6 +717,11 @@ def main():
                 sub["p50_s"], sub["p99_s"]), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.workload, lbl=lbl)
+        out["cpu_baseline"]["cpu_model"] = cpu_model()
+        out["cpu_baseline"]["host_threads"] = os.cpu_count()
+        if not args.no_cpu_plan:
+            out["cpu_baseline"]["specified_workloads"] = cpu_baseline_plan(lbl, torch)
+            print("cpu baseline of the specified workloads done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

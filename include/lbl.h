@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define LBL_ABI_VERSION 4
+#define LBL_ABI_VERSION 5
 
 typedef struct lbl_sim lbl_sim;
 
@@ -108,7 +108,25 @@ typedef struct lbl_params {
   int32_t force_form; /* enum lbl_force_form */
   int32_t sample_full_k; /* 0 or 1: at every sample (sample_every > 0) also
                             accumulate the whole-zone spectrum LBL_OBS_SK_FULL */
+  int32_t walls;      /* enum lbl_walls */
+  int32_t reserved;   /* 0 */
+  double u_wall[2][3]; /* velocities of the lower and upper wall (LBL_WALLS_LAST):
+                          tangential, the component along the last axis is 0 */
 } lbl_params;
+
+/* Boundaries (the closing remark of Sec. V.B: the finite-volume SMOL admits
+ * walls and shear boundaries):
+ *  PERIODIC (default): every axis periodic;
+ *  LAST: solid planar walls across the last axis (z in 3-D, y in 2-D), half a
+ *    lattice spacing below layer 0 and above layer L-1, moving tangentially
+ *    at u_wall[0] (lower) and u_wall[1] (upper).  The LB populations that
+ *    would leave through a wall return to their site reversed (halfway
+ *    bounce-back, with the term 2 w_i rho c_i.U / c_s^2 of a moving wall);
+ *    the SMOL stencils drop every link that crosses a wall, so no order
+ *    parameter flows through it and the fluctuation-dissipation balance of the
+ *    noise is kept.  FV variant, force PSI_GRAD_MU, single simulations only
+ *    (a pool refuses such a request); the SMOL runs as per-site passes. */
+enum lbl_walls { LBL_WALLS_PERIODIC = 0, LBL_WALLS_LAST = 1 };
 
 /* Force density of the order parameter on the fluid (full coupling):
  *  PSI_GRAD_MU (default, the paper's discretisation, Sec. IV): F = -psi G mu
@@ -221,7 +239,7 @@ enum lbl_observable {
   LBL_OBS_SK2_AXES = 10, /* d*Lmax FP64: mean over samples of the square of each
                            SK_AXES sample (its variance is SK2 - SK^2) */
   LBL_OBS_UK2_AXES = 11, /* d*d*Lmax FP64: the same for UK_AXES */
-  LBL_OBS_SK_FULL = 12   /* nz*ny*(nx/2+1) FP64: mean over samples of
+  LBL_OBS_SK_FULL = 12,  /* nz*ny*(nx/2+1) FP64: mean over samples of
                             |sum_x psi e^{-i q.x}|^2 / N over the whole zone,
                             q = 2 pi (kx/nx, ky/ny, kz/nz), kx in [0, nx/2] (the
                             other half follows from S(-q) = S(q)), element
@@ -230,6 +248,15 @@ enum lbl_observable {
                             lbl_params.sample_full_k: otherwise its size is 0 and
                             lbl_observe gives LBL_E_INVAL (Figs. test1b, test2a,
                             test2: the spectrum over wave-vector planes) */
+  LBL_OBS_HEIGHTS = 13  /* 2*C FP64, C = nx*ny (3-D) or nx (2-D): heights of two
+                           interfaces along the last axis (length L) per column
+                           c = x + nx*y (3-D) or x (2-D): the zero crossing of
+                           psi by linear interpolation between the two sites
+                           that bracket it (Sec. VI.C), z + psi(z)/(psi(z) -
+                           psi(z+1)) at the first z with psi(z) psi(z+1) <= 0 in
+                           the window [L/8, 3L/8) (element [c], the interface
+                           near L/4) or [5L/8, 7L/8) (element [C + c]); NaN
+                           when the window holds none */
 };
 
 /* Copy an observable of the current state into dst (host memory, or device
@@ -273,13 +300,15 @@ int lbl_timing_read(lbl_sim *sim, lbl_kernel_time *out, int max_entries, int *n_
  * 1 runs the first Runge-Kutta stage on a second stream of the library's
  * own (default priority), concurrently with the velocity pass of the
  * streamed populations that only the later stages read (full coupling, 2 or
- * 4 stages); 0 runs everything on the simulation's stream.  Default: the
+ * 4 stages); 2 draws the SMOL noise on that second stream, concurrently with
+ * the LB passes (the noise depends on the counter alone), and joins it before
+ * the first stage; 0 runs everything on the simulation's stream.  Default: the
  * widest width up to 256 that fits nx, no swizzle, zc per kernel from its
  * occupancy (the stage's blocks fill the device's resident slots in one
  * round, the preparation kernel's in two; at least 8 planes), overlap 0.
  * The z-marching stress pass of force_form STRESS (FV, 3-D) keeps its own
  * default (two rounds) whatever zc is.  Errors: LBL_E_INVAL (NULL,
- * unsupported width, zc < 0, overlap not 0 or 1). */
+ * unsupported width, zc < 0, overlap not 0, 1 or 2). */
 typedef struct lbl_schedule {
   int32_t lb_width;
   int32_t xcd_swizzle;

@@ -36,7 +36,8 @@ class Params(ctypes.Structure):
         ("kT", ctypes.c_double), ("omega_bulk", ctypes.c_double),
         ("omega_ghost", ctypes.c_double), ("u_imposed", ctypes.c_double * 3),
         ("seed", ctypes.c_uint64),
-        ("force_form", ctypes.c_int32), ("pad1", ctypes.c_int32),
+        ("force_form", ctypes.c_int32), ("walls", ctypes.c_int32),
+        ("u_wall", ctypes.c_double * 6),
     ]
 
 
@@ -82,6 +83,9 @@ def lib():
             "orc_run": (ctypes.c_int, [P, dp, dp, ctypes.c_uint32, ctypes.c_int64]),
             "orc_totals": (None, [P, dp, dp, dp]),
             "orc_axis_spectrum": (None, [P, dp, ctypes.c_int32, dp]),
+            "orc_heights": (None, [P, dp, dp]),
+            "orc_set_threads": (None, [ctypes.c_int32]),
+            "orc_max_threads": (ctypes.c_int32, []),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(L, name)
@@ -99,12 +103,16 @@ def _dp(a):
 def make_params(lattice=D2Q9, smol=FD, coupling=FULL, rk_stages=2, shape=(16, 16, 1),
                 rho0=1.0, eta=0.1, M=0.1, a=0.04, b=0.1, kappa=0.05, kT=1e-5,
                 omega_bulk=1.0, omega_ghost=1.0, u_imposed=(0.0, 0.0, 0.0), seed=1234,
-                fd_noise=FDNOISE_LINK, force_form=FORCE_PSI_GRAD_MU):
+                fd_noise=FDNOISE_LINK, force_form=FORCE_PSI_GRAD_MU, walls=0,
+                u_wall=(0.0, 0.0, 0.0, 0.0, 0.0, 0.0)):
     nx, ny, nz = (tuple(shape) + (1, 1, 1))[:3]
     p = Params()
     p.lattice, p.smol, p.coupling, p.rk_stages = lattice, smol, coupling, rk_stages
     p.fd_noise = fd_noise
     p.force_form = force_form
+    p.walls = walls
+    for k in range(6):
+        p.u_wall[k] = float(u_wall[k])
     p.nx, p.ny, p.nz = nx, ny, nz
     p.rho0, p.eta, p.M, p.a, p.b, p.kappa, p.kT = rho0, eta, M, a, b, kappa, kT
     p.omega_bulk, p.omega_ghost = omega_bulk, omega_ghost
@@ -275,3 +283,22 @@ def axis_spectrum(p, field, lmax=None):
     lib().orc_axis_spectrum(ctypes.byref(p), _dp(np.ascontiguousarray(field, dtype=np.float64)),
                             lmax, _dp(out))
     return out[:d_of(p)]
+
+
+def heights(p, psi):
+    """Interface heights (2, C): the zero crossings of psi along the last axis
+    near L/4 and 3L/4 per column (C = nx*ny in 3-D, nx in 2-D)."""
+    C = p.nx * p.ny if d_of(p) == 3 else p.nx
+    out = np.zeros((2, C))
+    lib().orc_heights(ctypes.byref(p), _dp(np.ascontiguousarray(psi, dtype=np.float64)),
+                      _dp(out))
+    return out
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's site loops."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads():
+    return int(lib().orc_max_threads())

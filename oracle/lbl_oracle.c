@@ -16,6 +16,9 @@
 #include "lbl_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -260,6 +263,30 @@ static int64_t shift(const orc_params *p, int64_t s, int cx, int cy, int cz) {
   return x + (int64_t)p->nx * (y + (int64_t)p->ny * z);
 }
 
+/* Walls (the closing remark of Sec. V.B: the FV scheme admits walls and
+ * shear boundaries).  Reading: solid planar walls across the last axis (z in
+ * 3-D, y in 2-D), half a lattice spacing below layer 0 and above layer L-1.
+ * Every stencil link between a site and a point beyond a wall is removed:
+ * there is no flux through a wall.  In a stencil centred at x this means a
+ * scalar field takes, beyond the wall, its value at x (the difference along
+ * the removed link vanishes), and a flux field takes minus its value at x
+ * (the link average of the flux vanishes).  The operators stay adjoint:
+ * Div = -Grad^T, and the Laplacians are symmetric with zero row sums. */
+static int last_coord(const orc_params *p, int64_t s) {
+  if (orc_d(p->lattice) == 3) return (int)(s / ((int64_t)p->nx * p->ny));
+  return (int)((s / p->nx) % p->ny);
+}
+
+/* 1 when the offset (cx, cy, cz) from site s crosses a wall. */
+static int crosses_wall(const orc_params *p, int64_t s, int cx, int cy, int cz) {
+  if (!p->walls) return 0;
+  int three_d = orc_d(p->lattice) == 3;
+  int L = three_d ? p->nz : p->ny;
+  int h = last_coord(p, s) + (three_d ? cz : cy);
+  (void)cx;
+  return h < 0 || h >= L;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Discrete operators.                                                       */
 /* ------------------------------------------------------------------------ */
@@ -280,7 +307,7 @@ void orc_laplacian(const orc_params *p, const double *in, double *out) {
         for (int cx = -1; cx <= 1; cx++) {
           int r2 = cx * cx + cy * cy + cz * cz;
           if (r2 == 0) continue;
-          double v = in[shift(p, s, cx, cy, cz)];
+          double v = crosses_wall(p, s, cx, cy, cz) ? in[s] : in[shift(p, s, cx, cy, cz)];
           if (r2 == 1) s1 += v;
           else if (r2 == 2) s2 += v;
           else s3 += v;
@@ -309,10 +336,18 @@ void orc_gradient(const orc_params *p, const double *in, double *out) {
       if (p->smol == ORC_FD) {
         int e[3] = {0, 0, 0};
         e[a] = 1;
-        g = 0.5 * (in[shift(p, s, e[0], e[1], e[2])] - in[shift(p, s, -e[0], -e[1], -e[2])]);
+        double vp = crosses_wall(p, s, e[0], e[1], e[2]) ? in[s]
+                                                         : in[shift(p, s, e[0], e[1], e[2])];
+        double vm = crosses_wall(p, s, -e[0], -e[1], -e[2])
+                        ? in[s]
+                        : in[shift(p, s, -e[0], -e[1], -e[2])];
+        g = 0.5 * (vp - vm);
       } else {
-        for (int i = 0; i < q; i++)
-          g += w[i] * c[3 * i + a] * in[shift(p, s, c[3 * i], c[3 * i + 1], c[3 * i + 2])];
+        for (int i = 0; i < q; i++) {
+          int cx = c[3 * i], cy = c[3 * i + 1], cz = c[3 * i + 2];
+          double v = crosses_wall(p, s, cx, cy, cz) ? in[s] : in[shift(p, s, cx, cy, cz)];
+          g += w[i] * c[3 * i + a] * v;
+        }
         g = g / CS2;
       }
       out[a * N + s] = g;
@@ -339,15 +374,22 @@ void orc_divergence(const orc_params *p, const double *in, double *out) {
       for (int a = 0; a < d; a++) {
         int e[3] = {0, 0, 0};
         e[a] = 1;
-        div += 0.5 * (in[a * N + shift(p, s, e[0], e[1], e[2])] -
-                      in[a * N + shift(p, s, -e[0], -e[1], -e[2])]);
+        double vp = crosses_wall(p, s, e[0], e[1], e[2])
+                        ? -in[a * N + s]
+                        : in[a * N + shift(p, s, e[0], e[1], e[2])];
+        double vm = crosses_wall(p, s, -e[0], -e[1], -e[2])
+                        ? -in[a * N + s]
+                        : in[a * N + shift(p, s, -e[0], -e[1], -e[2])];
+        div += 0.5 * (vp - vm);
       }
     } else {
       for (int i = 0; i < q; i++) {
-        int64_t t = shift(p, s, c[3 * i], c[3 * i + 1], c[3 * i + 2]);
-        double cx = 0.0;
-        for (int a = 0; a < d; a++) cx += c[3 * i + a] * in[a * N + t];
-        div += w[i] * cx;
+        int cx = c[3 * i], cy = c[3 * i + 1], cz = c[3 * i + 2];
+        int out_ = crosses_wall(p, s, cx, cy, cz);
+        int64_t t = out_ ? s : shift(p, s, cx, cy, cz);
+        double cv = 0.0;
+        for (int a = 0; a < d; a++) cv += c[3 * i + a] * (out_ ? -in[a * N + t] : in[a * N + t]);
+        div += w[i] * cv;
       }
       div = div / CS2;
     }
@@ -647,6 +689,7 @@ typedef struct {
   int32_t c[19 * 3];
   double w[19];
   double E[19 * 19];
+  int opp[19];      /* index of the opposite velocity */
   double gamma[19]; /* per-mode gamma_k = 1 - omega_k */
   double sigma[19]; /* per-mode noise amplitude */
 } lb_tables;
@@ -662,6 +705,11 @@ static void lb_setup(const orc_params *p, lb_tables *t) {
   t->d = orc_d(p->lattice);
   orc_velocities(p->lattice, t->c, t->w);
   orc_basis(p->lattice, t->E);
+  for (int i = 0; i < t->q; i++)
+    for (int j = 0; j < t->q; j++)
+      if (t->c[3 * j] == -t->c[3 * i] && t->c[3 * j + 1] == -t->c[3 * i + 1] &&
+          t->c[3 * j + 2] == -t->c[3 * i + 2])
+        t->opp[i] = j;
   double ws = omega_shear(p);
   for (int k = 0; k < t->q; k++) {
     int cls = mode_class(p->lattice, k);
@@ -822,8 +870,19 @@ int orc_step(const orc_params *p, double *f, double *psi, uint32_t step) {
       for (int k = 0; k < nr; k++)
         r[k] = orc_normal(p->seed, (uint32_t)s, step, ORC_TAG_LB, (uint32_t)k);
       collide_site(&t, fb, Fs, r, fs);
-      for (int i = 0; i < q; i++)
-        fn[i * N + shift(p, s, t.c[3 * i], t.c[3 * i + 1], t.c[3 * i + 2])] = fs[i];
+      for (int i = 0; i < q; i++) {
+        int cx = t.c[3 * i], cy = t.c[3 * i + 1], cz = t.c[3 * i + 2];
+        if (crosses_wall(p, s, cx, cy, cz)) {
+          /* Halfway bounce-back at a wall moving with velocity U (Ladd):
+           * the population returns to s reversed, less 2 w_i rho0 c_i.U/c_s^2. */
+          const double *U = last_coord(p, s) == 0 ? p->u_wall : p->u_wall + 3;
+          double cU = 0.0;
+          for (int a = 0; a < d; a++) cU += t.c[3 * i + a] * U[a];
+          fn[t.opp[i] * N + s] = fs[i] - 2.0 * t.w[i] * p->rho0 * cU / CS2;
+        } else {
+          fn[i * N + shift(p, s, cx, cy, cz)] = fs[i];
+        }
+      }
     }
     memcpy(f, fn, sizeof(double) * N * q);
     free(fn);
@@ -952,4 +1011,44 @@ void orc_axis_spectrum(const orc_params *p, const double *field, int32_t lmax, d
     }
     free(plane);
   }
+}
+
+/* Interface heights (Sec. VI.C): zero crossing of psi along the last axis in
+ * the two windows around L/4 and 3L/4, by linear interpolation. */
+void orc_heights(const orc_params *p, const double *psi, double *out) {
+  int d = orc_d(p->lattice);
+  int64_t L = d == 3 ? p->nz : p->ny;
+  int64_t C = d == 3 ? (int64_t)p->nx * p->ny : p->nx;
+  int64_t lo[2] = {L / 8, 5 * L / 8}, hi[2] = {3 * L / 8, 7 * L / 8};
+  for (int k = 0; k < 2; k++) {
+    for (int64_t c = 0; c < C; c++) {
+      double h = NAN;
+      for (int64_t z = lo[k]; z < hi[k]; z++) {
+        double a = psi[c + C * z], b = psi[c + C * (z + 1)];
+        if (a * b <= 0.0) {
+          h = (double)z + a / (a - b);
+          break;
+        }
+      }
+      out[k * C + c] = h;
+    }
+  }
+}
+
+/* Thread count of the OpenMP site loops (test infrastructure: the CPU
+ * baseline times the oracle at one thread and at all host threads). */
+void orc_set_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int32_t orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

@@ -51,7 +51,9 @@ typedef struct orc_params {
   double u_imposed[3]; /* uniform advecting velocity used when coupling == ORC_SMOL_ONLY */
   uint64_t seed;
   int32_t force_form;  /* ORC_FORCE_PSI_GRAD_MU or ORC_FORCE_STRESS */
-  int32_t pad1;
+  int32_t walls;       /* 0: periodic; 1: solid walls across the last axis (below
+                          layer 0 and above layer L-1, half a spacing away) */
+  double u_wall[6];    /* velocities of the lower wall (0..2) and upper wall (3..5) */
 } orc_params;
 
 /* Lattice tables and mode basis. */
@@ -66,7 +68,8 @@ void orc_links(int lattice, int32_t *c /* nlinks*3 */, double *lambda /* nlinks 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_normal(uint64_t seed, uint32_t site, uint32_t step, uint32_t tag, uint32_t slot);
 
-/* Discrete operators (periodic). */
+/* Discrete operators (periodic, or with walls across the last axis: every
+ * stencil link that crosses a wall is removed; see orc_laplacian). */
 void orc_laplacian(const orc_params *p, const double *in, double *out);
 void orc_gradient(const orc_params *p, const double *in, double *out /* d*N */);
 void orc_divergence(const orc_params *p, const double *in /* d*N */, double *out);
@@ -105,6 +108,19 @@ void orc_totals(const orc_params *p, const double *f, const double *psi, double 
 /* Axis structure factors: out[alpha*L_max + k] = |sum_x psi e^{-i k_alpha x_alpha}|^2 / N
  * with k_alpha = 2 pi k / L_alpha, k = 0 .. L_alpha - 1. */
 void orc_axis_spectrum(const orc_params *p, const double *field, int32_t lmax, double *out);
+
+/* Interface heights along the last axis (z in 3-D, y in 2-D; length L), per
+ * column c (c = x + nx*y in 3-D, x in 2-D; C columns): the zero crossing of
+ * psi by linear interpolation between the two sites that bracket it (Sec.
+ * VI.C), z + psi(z) / (psi(z) - psi(z+1)) at the first z of the window with
+ * psi(z) psi(z+1) <= 0.  Windows: [L/8, 3L/8) for the interface near L/4
+ * (out[c]) and [5L/8, 7L/8) for the one near 3L/4 (out[C + c]); NaN if the
+ * window holds no crossing. */
+void orc_heights(const orc_params *p, const double *psi, double *out);
+
+/* OpenMP threads of the site loops (n > 0), and the current maximum. */
+void orc_set_threads(int32_t n);
+int32_t orc_max_threads(void);
 
 #ifdef __cplusplus
 }

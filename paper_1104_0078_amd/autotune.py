@@ -12,7 +12,9 @@ Schedule knobs (see lbl_set_schedule / lbl_pool_set_schedule in lbl.h):
   lb_width     sites along x per 256-thread block of the per-site LB kernels;
   xcd_swizzle  block order that hands each XCD a contiguous part of the work
                (single simulations: bit 0 the LB kernels, bit 1 the SMOL tiles);
-  zc           planes per block of the z-marching SMOL kernels (3-D).
+  zc           planes per block of the z-marching SMOL kernels (3-D);
+  overlap      1: the first stage, 2: the SMOL noise on a second stream
+               (single simulations).
 """
 import json
 import os
@@ -92,12 +94,19 @@ def tune_sim(sim, params, steps=6, use_cache=True, candidates=None):
     for cand in candidates or sim_candidates(params):
         table.append({"schedule": cand, "ms_per_step": round(_time_sim(sim, cand, steps), 4)})
     best = min(table, key=lambda r: r["ms_per_step"])
+    # Last dimension, on top of the best schedule so far: the first stage on
+    # a second stream, concurrent with the velocity pass (full coupling,
+    # several stages), or the SMOL noise on it, concurrent with the LB passes.
+    overlaps = []
     if params.coupling == 0 and params.rk_stages > 1:
-        # Last dimension: the first stage on a second stream, concurrent with
-        # the velocity pass, on top of the best schedule so far.
-        cand = dict(best["schedule"], overlap=1)
+        overlaps.append(1)
+    if params.coupling != 2 and params.kT > 0:
+        overlaps.append(2)
+    base = best["schedule"]
+    for ov in overlaps:
+        cand = dict(base, overlap=ov)
         table.append({"schedule": cand, "ms_per_step": round(_time_sim(sim, cand, steps), 4)})
-        best = min(table, key=lambda r: r["ms_per_step"])
+    best = min(table, key=lambda r: r["ms_per_step"])
     sim.set_schedule(**best["schedule"])
     entry = {"schedule": best["schedule"], "ms_per_step": best["ms_per_step"], "table": table}
     _store(path, key, entry)

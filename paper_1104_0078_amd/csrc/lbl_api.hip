@@ -62,6 +62,7 @@ struct lbl_sim {
   double* fk_acc = nullptr;        // sum over samples of |psi_q|^2 / N
   void* sig = nullptr;      // force_form STRESS: order-parameter stress, d(d+1)/2 components
   void* fstress = nullptr;  // and its divergence, the force density (d*N)
+  void* wflux = nullptr;    // walls: node noise, then the stages' node flux (d*N)
   double* part = nullptr;
   int nparts = 0;
   double* tot = nullptr;
@@ -78,7 +79,8 @@ struct lbl_sim {
   int zc_stress = 1;  // planes per block of the z-marching FV stress kernels (3-D)
   int lb_lw = 6;       // log2 of the LB block width along x
   int lb_swizzle = 0;  // XCD-contiguous block order: bit 0 LB kernels, bit 1 tile kernels
-  int overlap = 0;     // first RK stage on `aux`, concurrent with the velocity pass
+  int overlap = 0;     // 1: first RK stage on `aux`, concurrent with the velocity pass;
+                       // 2: SMOL noise on `aux`, concurrent with the LB passes
   hipStream_t aux = nullptr;  // created on first use (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double gamma_s = 0, gamma_b = 0, gamma_g = 0, sigma_s = 0, sigma_b = 0, sigma_g = 0;
@@ -299,6 +301,26 @@ int validate(const lbl_params* p, const lbl_init* in) {
                 "force_form must be LBL_FORCE_PSI_GRAD_MU or LBL_FORCE_STRESS");
   if (p->sample_full_k != 0 && p->sample_full_k != 1)
     return fail(nullptr, LBL_E_INVAL, "sample_full_k must be 0 or 1");
+  if (p->walls != LBL_WALLS_PERIODIC && p->walls != LBL_WALLS_LAST)
+    return fail(nullptr, LBL_E_INVAL, "walls must be LBL_WALLS_PERIODIC or LBL_WALLS_LAST");
+  if (p->reserved != 0) return fail(nullptr, LBL_E_INVAL, "reserved must be 0");
+  for (int w = 0; w < 2; ++w)
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(p->u_wall[w][k]))
+        return fail(nullptr, LBL_E_INVAL, "wall velocities must be finite");
+  if (p->walls == LBL_WALLS_LAST) {
+    if (p->smol != LBL_SMOL_FV)
+      return fail(nullptr, LBL_E_INVAL, "walls are an option of the FV variant");
+    if (p->force_form != LBL_FORCE_PSI_GRAD_MU)
+      return fail(nullptr, LBL_E_INVAL, "walls need force_form LBL_FORCE_PSI_GRAD_MU");
+    const int last = p->lattice == LBL_D2Q9 ? 1 : 2;
+    if (p->u_wall[0][last] != 0.0 || p->u_wall[1][last] != 0.0)
+      return fail(nullptr, LBL_E_INVAL, "walls move tangentially (no component along the "
+                                        "last axis)");
+  } else if (p->u_wall[0][0] != 0.0 || p->u_wall[0][1] != 0.0 || p->u_wall[0][2] != 0.0 ||
+             p->u_wall[1][0] != 0.0 || p->u_wall[1][1] != 0.0 || p->u_wall[1][2] != 0.0) {
+    return fail(nullptr, LBL_E_INVAL, "wall velocities need walls");
+  }
   if (in->kind < LBL_INIT_REST || in->kind > LBL_INIT_USER)
     return fail(nullptr, LBL_E_INVAL, "unknown init kind");
   if (in->kind == LBL_INIT_TANH_2IF && !(p->a < 0 && p->b > 0 && p->kappa > 0))
@@ -516,7 +538,7 @@ struct Impl {
         f0 = tmp;
         p0 = tmp + static_cast<size_t>(s->q) * s->N;
       }
-      k_scatter_user<S, DEV, Q><<<grid, kBlock, 0, s->stream>>>(g, s->p.rho, f0, f);
+      k_scatter_user<S, DEV, Q><<<grid, kBlock, 0, s->stream>>>(g, wall_spec(s), f0, f);
       if (int rc = launched(s, "k_scatter_user")) return rc;
       k_from_f64<S><<<grid, kBlock, 0, s->stream>>>(s->N, p0, psi);
       if (int rc = launched(s, "k_from_f64")) return rc;
@@ -528,7 +550,7 @@ struct Impl {
       return LBL_OK;
     }
     k_init_uniform<S, DEV, Q><<<grid, kBlock, 0, s->stream>>>(
-        g, s->p.rho, in->boost_u[0], in->boost_u[1], Lat<Q>::D == 3 ? in->boost_u[2] : 0.0, f);
+        g, wall_spec(s), in->boost_u[0], in->boost_u[1], Lat<Q>::D == 3 ? in->boost_u[2] : 0.0, f);
     if (int rc = launched(s, "k_init_uniform")) return rc;
     double psi_eq = 0, l = 1;
     const int tanh_on = in->kind == LBL_INIT_TANH_2IF;
@@ -565,7 +587,18 @@ struct Impl {
                                                           : nullptr;
     a.noise = s->p.kT > 0;
     a.nt = 2.0 * sizeof(S) * s->q * static_cast<double>(s->N) > kStreamBytes;
+    for (int w = 0; w < 2; ++w)
+      for (int k = 0; k < 3; ++k) a.uw[w][k] = S(s->p.u_wall[w][k]);
     return a;
+  }
+
+  static WallSpec wall_spec(const lbl_sim* s) {
+    WallSpec w;
+    w.on = s->p.walls == LBL_WALLS_LAST;
+    w.rho0 = s->p.rho;
+    for (int k = 0; k < 2; ++k)
+      for (int c = 0; c < 3; ++c) w.u[k][c] = s->p.u_wall[k][c];
+    return w;
   }
 
   static dim3 site_grid(const lbl_sim* s) {
@@ -577,6 +610,17 @@ struct Impl {
     const dim3 grid(site_map_blocks(m)), block(kSiteBlock);
     const bool ghost = s->gamma_g != 0.0;
     const hipStream_t st = s->stream;
+    if (s->p.walls == LBL_WALLS_LAST) {
+      // walls: the non-temporal choice is left to the default policy
+      return launch(s, name, [&] {
+        if (!collide)
+          k_lb<S, DEV, Q, SMOL, false, false, false, true><<<grid, block, 0, st>>>(a, m);
+        else if (ghost)
+          k_lb<S, DEV, Q, SMOL, true, true, false, true><<<grid, block, 0, st>>>(a, m);
+        else
+          k_lb<S, DEV, Q, SMOL, false, true, false, true><<<grid, block, 0, st>>>(a, m);
+      });
+    }
     return launch(s, name, [&] {
       if (!collide) {
         if (a.nt)
@@ -629,7 +673,41 @@ struct Impl {
     const dim3 grid = site_grid(s), block(kBX, kBY);
     const Geom g = geom(s);
     const Coef<S> c = coef(s);
+    if (s->p.walls == LBL_WALLS_LAST)
+      return launch(s, "k_mu_w",
+                    [&] { k_mu_w<S, Q><<<grid, block, 0, s->stream>>>(g, c, phi, mu); });
     return launch(s, "k_mu", [&] { k_mu<S, Q><<<grid, block, 0, s->stream>>>(g, c, phi, mu); });
+  }
+
+  // SMOL noise between walls: node noise into s->wflux, N = Div xi.
+  static int wall_noise(lbl_sim* s, uint32_t step) {
+    const Geom g = geom(s);
+    S* xi = static_cast<S*>(s->wflux);
+    const S amp = S(std::sqrt(2.0 * s->p.kT * s->p.M));
+    if (int rc = launch(s, "k_xi", [&] {
+          k_xi<S, Lat<Q>::D><<<grid_for(s->N), kBlock, 0, s->stream>>>(g, step, s->k0, s->k1,
+                                                                      amp, xi);
+        }))
+      return rc;
+    const dim3 grid = site_grid(s), block(kBX, kBY);
+    S* noise = static_cast<S*>(s->noise);
+    return launch(s, "k_div_noise_w", [&] {
+      k_div_noise_w<S, Q><<<grid, block, 0, s->stream>>>(g, xi, noise);
+    });
+  }
+
+  // One Runge-Kutta stage between walls: mu(phi), the node flux, then the
+  // divergence with the stage's combination.
+  static int wall_stage(lbl_sim* s, const StageArgs<S>& a) {
+    const dim3 grid = site_grid(s), block(kBX, kBY);
+    S* mu = static_cast<S*>(s->mu);
+    S* J = static_cast<S*>(s->wflux);
+    if (int rc = launch_mu(s, a.phi, mu)) return rc;
+    if (int rc = launch(s, "k_flux_w",
+                        [&] { k_flux_w<S, Q><<<grid, block, 0, s->stream>>>(a, mu, J); }))
+      return rc;
+    return launch(s, "k_stage_w",
+                  [&] { k_stage_w<S, Q><<<grid, block, 0, s->stream>>>(a, J); });
   }
 
   static int one_step(lbl_sim* s) {
@@ -658,7 +736,31 @@ struct Impl {
       if (int rc = stress_force(s, psin)) return rc;
     if (want_noise && !prep_noise)
       if (int rc = fourier_noise(s, n)) return rc;
-    if (prep_noise || want_mu) {
+    // With overlap 2 the SMOL noise (arithmetic-bound: the Box-Muller
+    // normals) is drawn on the second stream while the memory-bound LB
+    // passes run here; it depends on the counter only, and the previous
+    // step's stages, its last readers, precede the fork.  Joined before the
+    // first stage.
+    const bool walls = s->p.walls == LBL_WALLS_LAST;
+    if (walls) {
+      // per-site passes; the node-noise buffer is consumed before the stages
+      if (want_mu)
+        if (int rc = launch_mu(s, psin, static_cast<S*>(s->mu))) return rc;
+      if (prep_noise)
+        if (int rc = wall_noise(s, n)) return rc;
+    }
+    const bool split = !walls && prep_noise && s->overlap == 2;
+    if (split) {
+      if (int rc = ensure_aux(s)) return rc;
+      if (int rc = hip_check(s, hipEventRecord(s->ev_fork, s->stream), "fork")) return rc;
+      if (int rc = hip_check(s, hipStreamWaitEvent(s->aux, s->ev_fork, 0), "fork")) return rc;
+    }
+    for (int part = split ? 0 : 1; part < 2 && !walls; ++part) {
+      // part 0: the noise alone on `aux`; part 1: what remains on the stream
+      const bool do_noise = prep_noise && (part == 0 || !split);
+      const bool do_mu = want_mu && part == 1;
+      if (!do_noise && !do_mu) continue;
+      const hipStream_t ps = part == 0 ? s->aux : s->stream;
       PrepArgs<S> pa;
       pa.g = g;
       pa.c = coef(s);
@@ -668,14 +770,17 @@ struct Impl {
       pa.step = n;
       pa.zc = s->zc_prep;
       pa.psi = psin;
-      pa.noise = prep_noise ? noise : nullptr;
-      pa.mu = want_mu ? static_cast<S*>(s->mu) : nullptr;
+      pa.noise = do_noise ? noise : nullptr;
+      pa.mu = do_mu ? static_cast<S*>(s->mu) : nullptr;
+      const char* name = part == 0 ? "k_prep_noise" : "k_prep";
       int rc;
       if (SMOL == kFV)
-        rc = launch(s, "k_prep", [&] { k_prep_fv<S, Q><<<tgp, tb, 0, s->stream>>>(pa, tmp); });
+        rc = launch_on(s, ps, name, [&] { k_prep_fv<S, Q><<<tgp, tb, 0, ps>>>(pa, tmp); });
       else
-        rc = launch(s, "k_prep", [&] { k_prep_fd<S, Q><<<tgp, tb, 0, s->stream>>>(pa, tmp); });
+        rc = launch_on(s, ps, name, [&] { k_prep_fd<S, Q><<<tgp, tb, 0, ps>>>(pa, tmp); });
       if (rc) return rc;
+      if (part == 0)
+        if (int rc2 = hip_check(s, hipEventRecord(s->ev_join, s->aux), "join")) return rc2;
     }
     if (cpl != LBL_SMOL_ONLY) {
       const LBArgs<S> a = lb_args(s, fin, fout, psin, u, cpl == LBL_FULL, n);
@@ -685,7 +790,7 @@ struct Impl {
     // and the first stage (at t_n) are independent: with `overlap` the first
     // stage runs on the second stream while the velocity pass runs here.
     const bool uend = cpl == LBL_FULL && s->p.rk_stages > 1;
-    const bool fork = uend && s->overlap;
+    const bool fork = uend && s->overlap == 1 && !walls;
     if (fork) {
       if (int rc = ensure_aux(s)) return rc;
       if (int rc = hip_check(s, hipEventRecord(s->ev_fork, s->stream), "fork")) return rc;
@@ -695,6 +800,8 @@ struct Impl {
       const LBArgs<S> a = lb_args(s, fout, nullptr, psin, static_cast<S*>(s->u_end), 1, n);
       if (int rc = launch_lb(s, a, false, "k_uend")) return rc;
     }
+    if (split)
+      if (int rc = hip_check(s, hipStreamWaitEvent(s->stream, s->ev_join, 0), "join")) return rc;
     if (cpl != LBL_LB_ONLY) {
       const int ns = s->p.rk_stages;
       static const double cn4[4] = {0.5, 0.5, 1.0, 0.0};
@@ -729,7 +836,9 @@ struct Impl {
         a.out = a.last ? psout : static_cast<S*>(s->phi[st & 1]);
         const hipStream_t ss = (fork && st == 0) ? s->aux : s->stream;
         int rc;
-        if (SMOL == kFV)
+        if (walls)
+          rc = wall_stage(s, a);
+        else if (SMOL == kFV)
           rc = launch_on(s, ss, "k_stage", [&] { k_stage_fv<S, Q><<<tg, tb, 0, ss>>>(a, tm); });
         else
           rc = launch_on(s, ss, "k_stage", [&] { k_stage_fd<S, Q><<<tg, tb, 0, ss>>>(a, tm); });
@@ -806,7 +915,7 @@ struct Impl {
     const Geom g = geom(s);
     const S* f = static_cast<const S*>(s->f[s->cur]);
     const S* psi = static_cast<const S*>(s->psi[s->pcur]);
-    k_totals_partial<S, DEV, Q><<<s->nparts, kTotBlock, 0, s->stream>>>(g, s->p.rho, f, psi,
+    k_totals_partial<S, DEV, Q><<<s->nparts, kTotBlock, 0, s->stream>>>(g, wall_spec(s), f, psi,
                                                                        s->part);
     if (int rc = launched(s, "k_totals_partial")) return rc;
     k_totals_final<<<1, 64, 0, s->stream>>>(s->nparts, s->part, dst);
@@ -919,10 +1028,10 @@ struct Impl {
         k_to_f64<S><<<grid, kBlock, 0, s->stream>>>(s->N, psi, dst);
         return launched(s, "k_to_f64");
       case LBL_OBS_POP:
-        k_gather<S, DEV, Q><<<grid, kBlock, 0, s->stream>>>(g, s->p.rho, f, dst, nullptr);
+        k_gather<S, DEV, Q><<<grid, kBlock, 0, s->stream>>>(g, wall_spec(s), f, dst, nullptr);
         return launched(s, "k_gather");
       case LBL_OBS_RHO:
-        k_gather<S, DEV, Q><<<grid, kBlock, 0, s->stream>>>(g, s->p.rho, f, nullptr, dst);
+        k_gather<S, DEV, Q><<<grid, kBlock, 0, s->stream>>>(g, wall_spec(s), f, nullptr, dst);
         return launched(s, "k_gather");
       case LBL_OBS_U: {
         if (s->p.coupling == LBL_SMOL_ONLY) return LBL_E_UNSUPPORTED;
@@ -950,6 +1059,12 @@ struct Impl {
       }
       case LBL_OBS_PSIK_AXES:
         return sample(s, false, dst);
+      case LBL_OBS_HEIGHTS: {
+        const int C = Lat<Q>::D == 3 ? s->p.nx * s->p.ny : s->p.nx;
+        const int L = Lat<Q>::D == 3 ? s->p.nz : s->p.ny;
+        k_heights<S><<<dim3((C + 255) / 256, 2), 256, 0, s->stream>>>(C, L, psi, dst);
+        return launched(s, "k_heights");
+      }
       case LBL_OBS_SK_AXES:
       case LBL_OBS_UK_AXES:
       case LBL_OBS_SK2_AXES:
@@ -1012,7 +1127,7 @@ Table select(const lbl_params& p) {
 }
 
 // Device allocations of one simulation, in creation order.
-constexpr int kPlanBuffers = 23;
+constexpr int kPlanBuffers = 24;
 using Plan = std::array<size_t, kPlanBuffers>;
 
 Plan alloc_plan(const lbl_params& p) {
@@ -1037,7 +1152,9 @@ Plan alloc_plan(const lbl_params& p) {
           p.force_form == LBL_FORCE_STRESS ? sz * N * d : 0,
           // sample_full_k: the half spectrum of psi and its FP64 accumulator
           p.sample_full_k ? 2 * sz * half_spectrum(p) : 0,
-          p.sample_full_k ? sizeof(double) * half_spectrum(p) : 0};
+          p.sample_full_k ? sizeof(double) * half_spectrum(p) : 0,
+          // walls: the node noise, then each stage's node flux (d*N)
+          p.walls == LBL_WALLS_LAST ? sz * N * d : 0};
 }
 
 size_t obs_bytes(const lbl_sim* s, int what) {
@@ -1065,6 +1182,8 @@ size_t obs_bytes(const lbl_sim* s, int what) {
       return 8;
     case LBL_OBS_SK_FULL:
       return s->p.sample_full_k ? 8 * half_spectrum(s->p) : 0;
+    case LBL_OBS_HEIGHTS:
+      return 8 * 2 * static_cast<size_t>(s->p.nx) * (s->d == 3 ? s->p.ny : 1);
     default:
       return 0;
   }
@@ -1124,6 +1243,7 @@ void assign_buffers(lbl_sim* s, const std::array<void*, kPlanBuffers>& b) {
   s->fstress = b[20];
   s->fk_spec = b[21];
   s->fk_acc = static_cast<double*>(b[22]);
+  s->wflux = b[23];
 }
 
 int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* env,
@@ -1800,8 +1920,8 @@ int lbl_set_schedule(lbl_sim* sim, const lbl_schedule* sch) {
   for (int k = 5; k <= 8; ++k)
     if (w == (1 << k)) lw = k;
   if (lw < 0) return fail(sim, LBL_E_INVAL, "lb_width must be 32, 64, 128 or 256");
-  if (sch->zc < 0 || sch->overlap < 0 || sch->overlap > 1)
-    return fail(sim, LBL_E_INVAL, "zc < 0 or overlap not 0/1");
+  if (sch->zc < 0 || sch->overlap < 0 || sch->overlap > 2)
+    return fail(sim, LBL_E_INVAL, "zc < 0 or overlap not 0, 1 or 2");
   sim->lb_lw = lw;
   sim->lb_swizzle = sch->xcd_swizzle & 3;
   sim->overlap = sch->overlap;
@@ -1912,6 +2032,8 @@ int lbl_pool_submit(lbl_pool* pl, const lbl_params* params, const lbl_init* init
     return pool_fail(pl, LBL_E_INVAL, "the stress-divergence force runs in single simulations only");
   if (params->sample_full_k != 0)
     return pool_fail(pl, LBL_E_INVAL, "pool requests report the final state (sample_full_k 0)");
+  if (params->walls != LBL_WALLS_PERIODIC)
+    return pool_fail(pl, LBL_E_INVAL, "pool requests are periodic (walls 0)");
   PoolReq r;
   r.id = pl->next_id++;
   r.p = *params;

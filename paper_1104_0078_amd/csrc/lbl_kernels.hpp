@@ -372,7 +372,53 @@ struct LBArgs {
   const S* Fext;  // force density given per site (d*N), else computed from mu
   int noise;  // 0: kT == 0
   int nt;     // host's choice of the NT kernel variant (see kStreamBytes)
+  S uw[2][3];  // walls (WALLS kernels): velocities of the lower and upper wall
 };
+
+// Walls across the last axis (z in 3-D, y in 2-D), half a spacing below the
+// first and above the last layer (the closing remark of Sec. V.B).  A pull
+// from beyond a wall is a halfway bounce-back: the site's own reversed
+// post-collision population plus Ladd's term 2 w_i rho0 c_i.U / c_s^2 of a
+// wall moving at U.  In the stencils every link that crosses a wall is
+// removed: a scalar field takes the centre's value beyond the wall, a flux
+// field minus the centre's value.
+template <int Q>
+struct Opposite {
+  int i[Q];
+};
+
+template <int Q>
+constexpr Opposite<Q> make_opposite() {
+  Opposite<Q> o{};
+  for (int i = 0; i < Q; ++i)
+    for (int j = 0; j < Q; ++j)
+      if (Lat<Q>::cx[j] == -Lat<Q>::cx[i] && Lat<Q>::cy[j] == -Lat<Q>::cy[i] &&
+          Lat<Q>::cz[j] == -Lat<Q>::cz[i])
+        o.i[i] = j;
+  return o;
+}
+
+template <int Q>
+inline constexpr Opposite<Q> kOpp = make_opposite<Q>();
+
+// Component of velocity i along the last axis.
+template <int Q>
+__host__ __device__ constexpr int c_last(int i) {
+  return Lat<Q>::D == 3 ? Lat<Q>::cz[i] : Lat<Q>::cy[i];
+}
+
+// True when the offset (dy, dz) from a site at (y, z) leaves the lattice
+// across a wall (D-dimensional lattice).
+template <int D>
+__device__ __forceinline__ bool beyond_wall(const Geom& g, int y, int z, int dy, int dz) {
+  if constexpr (D == 3) {
+    const int h = z + dz;
+    return h < 0 || h >= g.nz;
+  } else {
+    const int h = y + dy;
+    return h < 0 || h >= g.ny;
+  }
+}
 
 // Launches whose populations outgrow the memory-side cache (256 MB on
 // MI355X) stream them non-temporally; smaller working sets keep them cached.
@@ -380,8 +426,11 @@ constexpr double kStreamBytes = 256.0 * 1024 * 1024;
 
 // GHOST: the ghost modes keep gamma_g m_g (omega_ghost != 1).
 // COLLIDE: false computes only u (observable).
+// WALLS: walls across the last axis (bounce-back pulls, one-sided force
+// gradient next to a wall).
 // The caller passes a site on the lattice.
-template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool COLLIDE, bool NT>
+template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool COLLIDE, bool NT,
+          bool WALLS = false>
 __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z) {
   using L = Lat<Q>;
   constexpr int D = L::D;
@@ -393,9 +442,28 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
 
   // The Q pulls go out first, the gathers of mu for the force behind them.
   S fv[Q];
+  bool wlo = false, whi = false;
+  if constexpr (WALLS) {
+    const int h = D == 3 ? z : y, Lh = D == 3 ? g.nz : g.ny;
+    wlo = h == 0;
+    whi = h == Lh - 1;
+  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const S* src = &a.f_in[static_cast<size_t>(i) * g.N + nb.at(-L::cx[i], -L::cy[i], -L::cz[i])];
+    if constexpr (WALLS) {
+      // the source lies beyond the lower (c_last > 0) or upper wall
+      if ((c_last<Q>(i) > 0 && wlo) || (c_last<Q>(i) < 0 && whi)) {
+        const S* U = c_last<Q>(i) > 0 ? a.uw[0] : a.uw[1];
+        S cU = 0;
+        if (L::cx[i]) cU += L::cx[i] * U[0];
+        if (L::cy[i]) cU += L::cy[i] * U[1];
+        if (L::cz[i]) cU += L::cz[i] * U[2];
+        fv[i] = a.f_in[static_cast<size_t>(kOpp<Q>.i[i]) * g.N + s] +
+                S(6.0 * L::w[i]) * a.rho0 * cU;
+        continue;
+      }
+    }
     if constexpr (NT)
       fv[i] = __builtin_nontemporal_load(src);
     else
@@ -418,7 +486,10 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
     } else {
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
-        const S t = S(L::w[i]) * mu[nb.at(L::cx[i], L::cy[i], L::cz[i])];
+        int site = nb.at(L::cx[i], L::cy[i], L::cz[i]);
+        if constexpr (WALLS)
+          if (beyond_wall<D>(g, y, z, L::cy[i], L::cz[i])) site = s;
+        const S t = S(L::w[i]) * mu[site];
         if (L::cx[i]) gx += L::cx[i] * t;
         if (L::cy[i]) gy += L::cy[i] * t;
         if (L::cz[i]) gz += L::cz[i] * t;
@@ -572,10 +643,11 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
   });
 }
 
-template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool COLLIDE, bool NT>
+template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool COLLIDE, bool NT,
+          bool WALLS = false>
 __global__ __launch_bounds__(kSiteBlock) void k_lb(LBArgs<S> a, SiteMap m) {
   int x, y, z;
-  if (site_of(m, a.g, x, y, z)) lb_body<S, DEV, Q, SMOL, GHOST, COLLIDE, NT>(a, x, y, z);
+  if (site_of(m, a.g, x, y, z)) lb_body<S, DEV, Q, SMOL, GHOST, COLLIDE, NT, WALLS>(a, x, y, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -1416,6 +1488,119 @@ __global__ __launch_bounds__(kTX* kTY) void k_stage_fd(StageArgs<S> a, TileMap m
 }
 
 // ---------------------------------------------------------------------------
+// FV SMOL between walls across the last axis: per-site passes (one thread per
+// site, the k_mu grid) with the links that cross a wall removed.  Per step:
+// mu(psi^n) for the force, the node noise xi into a buffer and N^n = Div xi;
+// per stage: mu(phi), the node flux J = -u phi + M Grad mu, and
+// G = Div J + N with the stage's combination.  Grad takes the centre's value
+// of a scalar beyond a wall and Div minus the centre's flux, so that
+// Div = -Grad^T (conservative, and the noise keeps the fluctuation-
+// dissipation balance).
+// ---------------------------------------------------------------------------
+template <typename S, int Q>
+__global__ __launch_bounds__(kBX* kBY) void k_mu_w(Geom g, Coef<S> c, const S* __restrict__ phi,
+                                                   S* __restrict__ mu) {
+  constexpr int D = Lat<Q>::D;
+  const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const Nbr nb(g, x, y, z);
+  const int s = nb.at(0, 0, 0);
+  mu[s] = chem_pot<S, D>(c, [&](int dx, int dy, int dz) {
+    return beyond_wall<D>(g, y, z, dy, dz) ? phi[s] : phi[nb.at(dx, dy, dz)];
+  });
+}
+
+// Node noise xi_a = amp z_a (z: normals of slots 0 .. d-1, SMOL stream).
+template <typename S, int D>
+__global__ __launch_bounds__(256) void k_xi(Geom g, uint32_t step, uint32_t k0, uint32_t k1, S amp,
+                                            S* __restrict__ xi) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= g.N) return;
+  S zz[4];
+  if constexpr (D == 3)
+    Normal4<S>::gen(static_cast<uint32_t>(s), step, 0, kTagSMOL, k0, k1, zz);
+  else
+    Normal4<S>::gen2(static_cast<uint32_t>(s), step, 0, kTagSMOL, k0, k1, zz);
+#pragma unroll
+  for (int c = 0; c < D; ++c) xi[static_cast<size_t>(c) * g.N + s] = amp * zz[c];
+}
+
+// (1/c_s^2) sum_i w_i c_i . X(x + c_i), X beyond a wall taken as -X(x).
+template <typename S, int Q>
+__device__ __forceinline__ S div_w(const Geom& g, const Nbr& nb, int y, int z,
+                                   const S* __restrict__ X) {
+  using L = Lat<Q>;
+  constexpr int D = L::D;
+  const int s = nb.at(0, 0, 0);
+  S acc = 0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const bool out = beyond_wall<D>(g, y, z, L::cy[i], L::cz[i]);
+    const int t = out ? s : nb.at(L::cx[i], L::cy[i], L::cz[i]);
+    S v = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int ca = a == 0 ? L::cx[i] : (a == 1 ? L::cy[i] : L::cz[i]);
+      if (ca) v += ca * X[static_cast<size_t>(a) * g.N + t];
+    }
+    acc += S(L::w[i]) * (out ? -v : v);
+  }
+  return S(3) * acc;
+}
+
+template <typename S, int Q>
+__global__ __launch_bounds__(kBX* kBY) void k_div_noise_w(Geom g, const S* __restrict__ xi,
+                                                          S* __restrict__ noise) {
+  const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const Nbr nb(g, x, y, z);
+  noise[nb.at(0, 0, 0)] = div_w<S, Q>(g, nb, y, z, xi);
+}
+
+// J = -u phi + M (1/c_s^2) sum_i w_i c_i mu(x + c_i), mu beyond a wall taken
+// as mu(x).
+template <typename S, int Q>
+__global__ __launch_bounds__(kBX* kBY) void k_flux_w(StageArgs<S> a, const S* __restrict__ mu,
+                                                     S* __restrict__ J) {
+  using L = Lat<Q>;
+  constexpr int D = L::D;
+  const Geom& g = a.g;
+  const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const Nbr nb(g, x, y, z);
+  const int s = nb.at(0, 0, 0);
+  S gm[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int t = beyond_wall<D>(g, y, z, L::cy[i], L::cz[i]) ? s : nb.at(L::cx[i], L::cy[i],
+                                                                        L::cz[i]);
+    const S v = S(L::w[i]) * mu[t];
+    if (L::cx[i]) gm[0] += L::cx[i] * v;
+    if (L::cy[i]) gm[1] += L::cy[i] * v;
+    if (L::cz[i]) gm[2] += L::cz[i] * v;
+  }
+  const S ph = a.phi[s];
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+    J[static_cast<size_t>(c) * g.N + s] = -uval(a, c, s) * ph + a.c.M * (S(3) * gm[c]);
+}
+
+// G = Div J + N^n, combined as the stage's mode says.
+template <typename S, int Q>
+__global__ __launch_bounds__(kBX* kBY) void k_stage_w(StageArgs<S> a, const S* __restrict__ J) {
+  const Geom& g = a.g;
+  const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const Nbr nb(g, x, y, z);
+  const int s = nb.at(0, 0, 0);
+  combine(a, s, div_w<S, Q>(g, nb, y, z, J) + a.noise[s]);
+}
+
+// ---------------------------------------------------------------------------
 // Initial state and observables (one thread per site, 1-D grid).
 // ---------------------------------------------------------------------------
 // Diagnostics: normals of Philox blocks 0 .. nblk-1 at sites site0 + i,
@@ -1431,21 +1616,6 @@ __global__ __launch_bounds__(256) void k_diag_normals(uint32_t site0, int n, int
     Normal4<S>::gen(site0 + static_cast<uint32_t>(i), step, static_cast<uint32_t>(b), tag, k0, k1, z);
     for (int l = 0; l < 4 && 4 * b + l < nslots; ++l)
       out[static_cast<size_t>(i) * nslots + 4 * b + l] = static_cast<double>(z[l]);
-  }
-}
-
-template <typename S, bool DEV, int Q>
-__global__ __launch_bounds__(256) void k_init_uniform(Geom g, double rho0, double ux, double uy,
-                                                      double uz, S* __restrict__ f) {
-  using L = Lat<Q>;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.N) return;
-  const double usq = ux * ux + uy * uy + uz * uz;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const double cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
-    const double fe = L::w[i] * rho0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
-    f[static_cast<size_t>(i) * g.N + s] = static_cast<S>(DEV ? fe - L::w[i] * rho0 : fe);
   }
 }
 
@@ -1468,9 +1638,42 @@ __global__ __launch_bounds__(256) void k_init_psi(Geom g, double std_, int tanh_
   psi[s] = static_cast<S>(v);
 }
 
-// Stored f*(x) = fbar(x + c_i) for a user fbar given in FP64.
+// Walls across the last axis for the kernels that convert between the
+// stored post-collision populations and the streamed ones (on = 0: periodic).
+struct WallSpec {
+  int on;
+  double rho0;
+  double u[2][3];  // velocities of the lower and upper wall
+};
+
+// fbar_i at site s = (x, y, z): f*_i(x - c_i) as the next step's streaming
+// pulls it, or, where x - c_i lies beyond a wall, the site's own reversed
+// f*_opp(i) plus the moving-wall term 6 w_i rho0 c_i.U (the same rule as the
+// bounce-back pull of the LB kernel).  FP64, stored units (deviations when
+// the populations are stored as deviations).
+template <typename S, int Q>
+__device__ __forceinline__ double streamed_pop(const Geom& g, const WallSpec& w,
+                                               const S* __restrict__ f, const Nbr& nb, int s,
+                                               int y, int z, int i) {
+  using L = Lat<Q>;
+  if (w.on && beyond_wall<L::D>(g, y, z, -L::cy[i], -L::cz[i])) {
+    const double* U = c_last<Q>(i) > 0 ? w.u[0] : w.u[1];
+    double cU = 0;
+    if (L::cx[i]) cU += L::cx[i] * U[0];
+    if (L::cy[i]) cU += L::cy[i] * U[1];
+    if (L::cz[i]) cU += L::cz[i] * U[2];
+    return static_cast<double>(f[static_cast<size_t>(kOpp<Q>.i[i]) * g.N + s]) +
+           6.0 * L::w[i] * w.rho0 * cU;
+  }
+  return static_cast<double>(
+      f[static_cast<size_t>(i) * g.N + nb.at(-L::cx[i], -L::cy[i], -L::cz[i])]);
+}
+
+// Stored f*(x) = fbar(x + c_i) for a user fbar given in FP64; the inverse of
+// streamed_pop: where x + c_i lies beyond a wall, f*_i(x) = fbar_opp(i)(x) +
+// 6 w_i rho0 c_i.U of the wall that c_i points into.
 template <typename S, bool DEV, int Q>
-__global__ __launch_bounds__(256) void k_scatter_user(Geom g, double rho0,
+__global__ __launch_bounds__(256) void k_scatter_user(Geom g, WallSpec w,
                                                       const double* __restrict__ fin,
                                                       S* __restrict__ f) {
   using L = Lat<Q>;
@@ -1480,14 +1683,55 @@ __global__ __launch_bounds__(256) void k_scatter_user(Geom g, double rho0,
   const Nbr nb(g, x, y, z);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double v = fin[static_cast<size_t>(i) * g.N + nb.at(L::cx[i], L::cy[i], L::cz[i])];
-    f[static_cast<size_t>(i) * g.N + s] = static_cast<S>(DEV ? v - L::w[i] * rho0 : v);
+    double v;
+    if (w.on && beyond_wall<L::D>(g, y, z, L::cy[i], L::cz[i])) {
+      const double* U = c_last<Q>(i) < 0 ? w.u[0] : w.u[1];
+      double cU = 0;
+      if (L::cx[i]) cU += L::cx[i] * U[0];
+      if (L::cy[i]) cU += L::cy[i] * U[1];
+      if (L::cz[i]) cU += L::cz[i] * U[2];
+      v = fin[static_cast<size_t>(kOpp<Q>.i[i]) * g.N + s] + 6.0 * L::w[i] * w.rho0 * cU;
+    } else {
+      v = fin[static_cast<size_t>(i) * g.N + nb.at(L::cx[i], L::cy[i], L::cz[i])];
+    }
+    f[static_cast<size_t>(i) * g.N + s] = static_cast<S>(DEV ? v - L::w[i] * w.rho0 : v);
   }
 }
 
-// fbar(x) = f*(x - c_i), in FP64 (+ w_i rho0 for deviations); rho optional.
+// Uniform start: the streamed populations are the equilibrium of (rho0, u)
+// at every site.  Stored f*_i(x) = f^eq_i, except where x + c_i lies beyond a
+// wall: there the next pull bounces f*_i back into fbar_opp(i)(x), so f*_i =
+// f^eq_opp(i) + 6 w_i rho0 c_i.U (as k_scatter_user).
 template <typename S, bool DEV, int Q>
-__global__ __launch_bounds__(256) void k_gather(Geom g, double rho0, const S* __restrict__ f,
+__global__ __launch_bounds__(256) void k_init_uniform(Geom g, WallSpec w, double ux, double uy,
+                                                      double uz, S* __restrict__ f) {
+  using L = Lat<Q>;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.N) return;
+  const int y = (s / g.nx) % g.ny, z = s / (g.nx * g.ny);
+  const double rho0 = w.rho0;
+  const double usq = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const bool out = w.on && beyond_wall<L::D>(g, y, z, L::cy[i], L::cz[i]);
+    const int j = out ? kOpp<Q>.i[i] : i;
+    const double cu = L::cx[j] * ux + L::cy[j] * uy + L::cz[j] * uz;
+    double fe = L::w[j] * rho0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+    if (out) {
+      const double* U = c_last<Q>(i) < 0 ? w.u[0] : w.u[1];
+      double cU = 0;
+      if (L::cx[i]) cU += L::cx[i] * U[0];
+      if (L::cy[i]) cU += L::cy[i] * U[1];
+      if (L::cz[i]) cU += L::cz[i] * U[2];
+      fe += 6.0 * L::w[i] * rho0 * cU;
+    }
+    f[static_cast<size_t>(i) * g.N + s] = static_cast<S>(DEV ? fe - L::w[i] * rho0 : fe);
+  }
+}
+
+// fbar(x) (streamed_pop), in FP64 (+ w_i rho0 for deviations); rho optional.
+template <typename S, bool DEV, int Q>
+__global__ __launch_bounds__(256) void k_gather(Geom g, WallSpec w, const S* __restrict__ f,
                                                 double* __restrict__ pop,
                                                 double* __restrict__ rho) {
   using L = Lat<Q>;
@@ -1498,9 +1742,8 @@ __global__ __launch_bounds__(256) void k_gather(Geom g, double rho0, const S* __
   double r = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    double v = static_cast<double>(
-        f[static_cast<size_t>(i) * g.N + nb.at(-L::cx[i], -L::cy[i], -L::cz[i])]);
-    if (DEV) v += L::w[i] * rho0;
+    double v = streamed_pop<S, Q>(g, w, f, nb, s, y, z, i);
+    if (DEV) v += L::w[i] * w.rho0;
     if (pop) pop[static_cast<size_t>(i) * g.N + s] = v;
     r += v;
   }
@@ -1535,7 +1778,7 @@ __global__ __launch_bounds__(256) void k_zero_words(int64_t n, uint32_t* __restr
 constexpr int kTotBlock = 256;
 
 template <typename S, bool DEV, int Q>
-__global__ __launch_bounds__(kTotBlock) void k_totals_partial(Geom g, double rho0,
+__global__ __launch_bounds__(kTotBlock) void k_totals_partial(Geom g, WallSpec w,
                                                               const S* __restrict__ f,
                                                               const S* __restrict__ psi,
                                                               double* __restrict__ part) {
@@ -1548,9 +1791,8 @@ __global__ __launch_bounds__(kTotBlock) void k_totals_partial(Geom g, double rho
     double r = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      double v = static_cast<double>(
-          f[static_cast<size_t>(i) * g.N + nb.at(-L::cx[i], -L::cy[i], -L::cz[i])]);
-      if (DEV) v += L::w[i] * rho0;
+      double v = streamed_pop<S, Q>(g, w, f, nb, s, y, z, i);
+      if (DEV) v += L::w[i] * w.rho0;
       r += v;
       if (L::cx[i]) jx += L::cx[i] * v;
       if (L::cy[i]) jy += L::cy[i] * v;

@@ -148,4 +148,31 @@ __global__ __launch_bounds__(256) void k_scale(int n, double c, const double* __
   if (i < n) out[i] = c * in[i];
 }
 
+// Interface heights along the last axis (Sec. VI.C), one thread per column
+// c of C: the zero crossing of psi by linear interpolation between the two
+// sites that bracket it, z + psi(z) / (psi(z) - psi(z+1)) at the first z with
+// psi(z) psi(z+1) <= 0, in FP64 from the stored values; the window is
+// [L/8, 3L/8) for the interface near L/4 (blockIdx.y = 0) and [5L/8, 7L/8)
+// for the one near 3L/4; NaN when the window holds no crossing.
+// out[k*C + c].
+template <typename S>
+__global__ __launch_bounds__(256) void k_heights(int C, int L, const S* __restrict__ psi,
+                                                 double* __restrict__ out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  const int k = blockIdx.y;
+  if (c >= C) return;
+  const int lo = k == 0 ? L / 8 : 5 * L / 8, hi = k == 0 ? 3 * L / 8 : 7 * L / 8;
+  double h = __builtin_nan("");
+  double a = static_cast<double>(psi[c + static_cast<size_t>(C) * lo]);
+  for (int z = lo; z < hi; ++z) {
+    const double b = static_cast<double>(psi[c + static_cast<size_t>(C) * (z + 1)]);
+    if (a * b <= 0.0) {
+      h = static_cast<double>(z) + a / (a - b);
+      break;
+    }
+    a = b;
+  }
+  out[static_cast<size_t>(k) * C + c] = h;
+}
+
 }  // namespace lbl

@@ -28,9 +28,10 @@ LBL_FULL, LBL_SMOL_ONLY, LBL_LB_ONLY = 0, 1, 2
 LBL_INIT_REST, LBL_INIT_TANH_2IF, LBL_INIT_USER = 0, 1, 2
 LBL_FDNOISE_LINK, LBL_FDNOISE_FOURIER = 0, 1
 LBL_FORCE_PSI_GRAD_MU, LBL_FORCE_STRESS = 0, 1
+LBL_WALLS_PERIODIC, LBL_WALLS_LAST = 0, 1
 (LBL_OBS_PSI, LBL_OBS_RHO, LBL_OBS_U, LBL_OBS_POP, LBL_OBS_TOTALS, LBL_OBS_SK_AXES,
  LBL_OBS_UK_AXES, LBL_OBS_STEP, LBL_OBS_NSAMPLES, LBL_OBS_PSIK_AXES, LBL_OBS_SK2_AXES,
- LBL_OBS_UK2_AXES, LBL_OBS_SK_FULL) = range(13)
+ LBL_OBS_UK2_AXES, LBL_OBS_SK_FULL, LBL_OBS_HEIGHTS) = range(14)
 
 
 class lbl_params(ctypes.Structure):
@@ -44,7 +45,8 @@ class lbl_params(ctypes.Structure):
         ("omega_ghost", ctypes.c_double), ("u_imposed", ctypes.c_double * 3),
         ("seed", ctypes.c_uint64), ("sample_every", ctypes.c_int32),
         ("fd_noise", ctypes.c_int32), ("force_form", ctypes.c_int32),
-        ("sample_full_k", ctypes.c_int32),
+        ("sample_full_k", ctypes.c_int32), ("walls", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("u_wall", (ctypes.c_double * 3) * 2),
     ]
 
 
@@ -234,7 +236,8 @@ def make_params(lattice=LBL_D2Q9, smol=LBL_SMOL_FD, precision=LBL_FP64, coupling
                 rk_stages=2, shape=(64, 64, 1), rho=1.0, eta=0.1, M=0.1, a=0.04, b=0.1,
                 kappa=0.05, kT=1e-5, omega_bulk=1.0, omega_ghost=1.0, u_imposed=(0, 0, 0),
                 seed=1234, sample_every=0, fd_noise=LBL_FDNOISE_LINK,
-                force_form=LBL_FORCE_PSI_GRAD_MU, sample_full_k=0):
+                force_form=LBL_FORCE_PSI_GRAD_MU, sample_full_k=0, walls=LBL_WALLS_PERIODIC,
+                u_wall=((0, 0, 0), (0, 0, 0))):
     nx, ny, nz = (tuple(shape) + (1, 1, 1))[:3]
     p = lbl_params()
     p.lattice, p.smol, p.precision, p.coupling, p.rk_stages = (lattice, smol, precision,
@@ -249,6 +252,10 @@ def make_params(lattice=LBL_D2Q9, smol=LBL_SMOL_FD, precision=LBL_FP64, coupling
     p.fd_noise = fd_noise
     p.force_form = force_form
     p.sample_full_k = sample_full_k
+    p.walls = walls
+    for w in range(2):
+        for k in range(3):
+            p.u_wall[w][k] = float(u_wall[w][k])
     return p
 
 
@@ -364,6 +371,9 @@ class Sim:
         if what == LBL_OBS_SK_FULL:
             p = self.params
             return out.reshape(p.nz, p.ny, p.nx // 2 + 1)
+        if what == LBL_OBS_HEIGHTS:
+            p = self.params
+            return out.reshape(2, p.ny, p.nx) if self.d == 3 else out.reshape(2, p.nx)
         return out
 
     def observe_into(self, what, tensor):

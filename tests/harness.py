@@ -17,9 +17,11 @@ TOL = {FP64: 1e-12, FP32DEV: 1e-5}
 def config(lattice=D2Q9, smol=FD, precision=FP64, coupling=FULL, rk=2, shape=(70, 45, 1),
            rho=1.0, eta=0.1, M=0.1, a=0.04, b=0.1, kappa=0.05, kT=1e-5, omega_bulk=1.0,
            omega_ghost=1.0, u_imposed=(0.0, 0.0, 0.0), seed=1234, init=0, psi_std=1e-3,
-           boost=(0.0, 0.0, 0.0), fd_noise=0, force_form=0):
+           boost=(0.0, 0.0, 0.0), fd_noise=0, force_form=0, walls=0,
+           u_wall=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))):
     return dict(lattice=lattice, smol=smol, precision=precision, coupling=coupling, rk=rk,
-                fd_noise=fd_noise, force_form=force_form,
+                fd_noise=fd_noise, force_form=force_form, walls=walls,
+                u_wall=tuple(tuple(w) for w in u_wall),
                 shape=tuple(shape), rho=rho, eta=eta, M=M, a=a, b=b, kappa=kappa, kT=kT,
                 omega_bulk=omega_bulk, omega_ghost=omega_ghost, u_imposed=tuple(u_imposed),
                 seed=seed, init=init, psi_std=psi_std, boost=tuple(boost))
@@ -31,7 +33,9 @@ def oracle_params(c):
                          M=c["M"], a=c["a"], b=c["b"], kappa=c["kappa"], kT=c["kT"],
                          omega_bulk=c["omega_bulk"], omega_ghost=c["omega_ghost"],
                          u_imposed=c["u_imposed"], seed=c["seed"], fd_noise=c["fd_noise"],
-                         force_form=c["force_form"])
+                         force_form=c["force_form"], walls=c.get("walls", 0),
+                         u_wall=tuple(c.get("u_wall", ((0,) * 3, (0,) * 3))[0]) +
+                         tuple(c.get("u_wall", ((0,) * 3, (0,) * 3))[1]))
 
 
 def lbl_params(c, sample_every=0):
@@ -42,7 +46,8 @@ def lbl_params(c, sample_every=0):
                            kappa=c["kappa"], kT=c["kT"], omega_bulk=c["omega_bulk"],
                            omega_ghost=c["omega_ghost"], u_imposed=c["u_imposed"],
                            seed=c["seed"], sample_every=sample_every, fd_noise=c["fd_noise"],
-                           force_form=c["force_form"])
+                           force_form=c["force_form"], walls=c.get("walls", 0),
+                           u_wall=c.get("u_wall", ((0, 0, 0), (0, 0, 0))))
 
 
 def oracle_run(c, nsteps, f=None, psi=None):

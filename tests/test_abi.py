@@ -57,7 +57,7 @@ int main(void) {
 
 
 def test_constants_and_strings():
-    assert lbl.lbl_abi_version() == 4
+    assert lbl.lbl_abi_version() == 5
     assert lbl.lbl_strerror(0) == "ok"
     assert "buffer" in lbl.lbl_strerror(lbl.LBL_E_BUFSIZE)
     assert lbl.lbl_strerror(12345) == "unknown status"
@@ -148,3 +148,25 @@ def test_component_offsets_use_64_bit_arithmetic():
     for path in glob.glob(os.path.join(ROOT, "paper_1104_0078_amd", "csrc", "*")):
         for k, line in enumerate(open(path), 1):
             assert not bad.search(line), "%s:%d: %s" % (path, k, line.strip())
+
+
+@pytest.mark.parametrize("change", [
+    dict(walls=2), dict(walls=1, smol=lbl.LBL_SMOL_FD), dict(walls=1, force_form=1),
+    dict(walls=1, u_wall=((0, 0, 0.01), (0, 0, 0))), dict(walls=0, u_wall=((0.01, 0, 0), (0, 0, 0))),
+    dict(walls=1, u_wall=((float("nan"), 0, 0), (0, 0, 0))),
+])
+def test_invalid_walls_rejected(change):
+    kw = dict(lattice=lbl.LBL_D3Q19, smol=lbl.LBL_SMOL_FV, shape=(8, 8, 8))
+    kw.update(change)
+    p = lbl.make_params(**kw)
+    rc, h = lbl.lbl_create(p, lbl.make_init(), lbl.lbl_env())
+    assert rc == lbl.LBL_E_INVAL and not h.value
+    assert lbl.lbl_last_error(None)
+
+
+def test_walls_memory():
+    """Walls add one d*N buffer (the node noise, then the stage flux)."""
+    kw = dict(lattice=lbl.LBL_D3Q19, smol=lbl.LBL_SMOL_FV, shape=(24, 20, 16))
+    base = lbl.lbl_sim_bytes(lbl.make_params(**kw))
+    walls = lbl.lbl_sim_bytes(lbl.make_params(walls=1, **kw))
+    assert walls - base == 8 * 3 * 24 * 20 * 16

@@ -31,6 +31,22 @@ def test_algorithmic_bytes_of_the_headline_workload():
     w32 = dict(w, precision=1)
     assert bench.alg_bytes_per_site(w32) == 160
     assert bench.kernel_alg_bytes_per_site("k_white", w) is None
+    # headline roofline: the LB pass's share of the state bytes, the populations
+    assert bench.state_bytes_per_site("k_lb", w) == 2 * 19 * 8 == 304
+    assert bench.state_bytes_per_site("k_lb", w32) == 2 * 19 * 4
+    assert bench.state_bytes_per_site("k_stage", w) is None
+
+
+def test_step_traffic_sums_the_kernels_of_a_step(monkeypatch):
+    """The step's measured traffic per site is the sum over its kernels of
+    the counter bytes per launch times launches per step, over N."""
+    per_launch = {"k_lb": 4.0e9, "k_prep": 5.0e8, "k_stage": 1.5e9}
+    monkeypatch.setattr(bench, "traffic_for", lambda k, wl: per_launch.get(k))
+    kt = [("k_prep", 10, 3.3), ("k_lb", 10, 12.0), ("k_stage", 20, 5.6)]
+    N = 256 ** 3
+    got = bench.step_traffic_per_site(kt, "any", 10, N)
+    assert abs(got - (4.0e9 + 5.0e8 + 2 * 1.5e9) / N) < 1e-9
+    assert bench.step_traffic_per_site(kt + [("k_other", 10, 1.0)], "any", 10, N) is None
 
 
 def test_committed_traffic_entries_are_self_consistent():

@@ -65,3 +65,31 @@ def test_axis_spectrum_and_totals():
     np.testing.assert_allclose(t[5], np.abs(f.sum(0)).sum(), rtol=1e-12)
     np.testing.assert_allclose(t[6:9], np.abs(j).sum(1), rtol=1e-12)
     np.testing.assert_allclose(t[9], np.abs(field).sum(), rtol=1e-12)
+
+
+@pytest.mark.parametrize("lattice,shape", [(O.D2Q9, (12, 40, 1)), (O.D3Q19, (6, 5, 48))])
+def test_interface_heights_closed_form(lattice, shape):
+    """Heights of the two interfaces (Sec. VI.C, zero crossing by linear
+    interpolation): on columns whose profile is linear through a chosen
+    crossing z* (clipped to +-1 away from it), the height is z* to rounding;
+    a column without a sign change in a window gives NaN; the flat two-phase
+    initial state has its interfaces at L/4 and 3L/4 exactly."""
+    p = O.make_params(lattice=lattice, shape=shape, a=-0.04, b=0.04, kappa=0.05)
+    d = O.d_of(p)
+    L = shape[2] if d == 3 else shape[1]
+    C = shape[0] * shape[1] if d == 3 else shape[0]
+    rng = np.random.default_rng(3)
+    zlo = rng.uniform(L / 8 + 1, 3 * L / 8 - 1, C)
+    zhi = rng.uniform(5 * L / 8 + 1, 7 * L / 8 - 1, C)
+    z = np.arange(L)[:, None]
+    col = np.where(z < L // 2, np.clip(z - zlo, -1, 1), np.clip(zhi - z, -1, 1))
+    col[:, 0] = 0.5  # no crossing anywhere in this column
+    psi = np.ascontiguousarray(col.reshape(-1))  # site = c + C * z
+    h = O.heights(p, psi)
+    np.testing.assert_allclose(h[0, 1:], zlo[1:], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(h[1, 1:], zhi[1:], rtol=0, atol=1e-13)
+    assert np.isnan(h[:, 0]).all()
+    _, psi0 = O.init(p, 1, 0.0)
+    h0 = O.heights(p, psi0)
+    np.testing.assert_allclose(h0[0], L / 4, atol=1e-12)
+    np.testing.assert_allclose(h0[1], 3 * L / 4, atol=1e-12)

@@ -84,3 +84,30 @@ def axis_q(L, axis, d):
     q = np.zeros((3, L))
     q[axis] = 2 * np.pi * np.arange(L) / L
     return q
+
+
+def n_eff(decay, nsamp, every):
+    """Effectively independent samples of |X_q|^2 for a mode whose amplitude
+    decays by the factor `decay` per step (|R| for psi, exp(-rate) for the
+    fluid), sampled `nsamp` times every `every` steps: the correlation of
+    |X_q|^2 between samples is decay^(2 every), and the variance of the mean
+    of an AR(1) series with that coefficient is that of
+    nsamp (1 - rho)/(1 + rho) independent samples."""
+    with np.errstate(invalid="ignore", over="ignore"):
+        rho = np.clip(decay, 0, 1) ** (2 * every)
+        return np.maximum(nsamp * (1 - rho) / (1 + rho), 1.0)
+
+
+def mean_and_se(ratios, neff):
+    """Mean of per-mode ratios <|X_q|^2>/theory over independent modes, and
+    its standard error: |X_q|^2 of a Gaussian mode has relative variance 1 per
+    independent sample, so each ratio carries variance 1/n_eff."""
+    ratios = np.asarray(ratios, dtype=float)
+    neff = np.asarray(neff, dtype=float)
+    return ratios.mean(), np.sqrt((1.0 / neff).sum()) / ratios.size
+
+
+def axis_modes(L):
+    """Independent axis wave numbers of a real field: m = 1 .. L/2 (m and L-m
+    are one mode)."""
+    return np.arange(1, L // 2 + 1)
