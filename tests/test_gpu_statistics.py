@@ -278,24 +278,45 @@ def _interface_heights(psi, nx, ny, lo, hi):
     return lo + idx + z0 / (z0 - z1)
 
 
-@pytest.mark.parametrize("smol,kT,force_form,nsamp,bar", [
-    (H.FD, 1.0 / 3000, 0, 2000, 0.1), (H.FV, 1.0 / 3000, 0, 2000, 0.1),
+CAP_BATCHES = 30
+
+
+@pytest.mark.parametrize("smol,kT,force_form,nsamp", [
+    (H.FD, 1.0 / 3000, 0, 2000), (H.FV, 1.0 / 3000, 0, 2000),
     # the paper's second temperature
-    (H.FD, 1e-7, 0, 4000, 0.15), (H.FV, 1e-7, 0, 4000, 0.15),
-    # the force as the divergence of the stress of Eq. (muf): measured 1.09-1.20
-    # (FD) and 1.03-1.10 (FV) over runs; the discrete stress divergence is not
-    # the exact adjoint of the advection, so the reversible coupling is no
-    # longer energy-neutral on the lattice and the interface spectrum is
-    # slightly enhanced (the default -psi grad mu form is)
-    (H.FD, 1.0 / 3000, 1, 4000, 0.3), (H.FV, 1.0 / 3000, 1, 4000, 0.3)])
-def test_capillary_spectrum(smol, kT, force_form, nsamp, bar):
+    (H.FD, 1e-7, 0, 4000), (H.FV, 1e-7, 0, 4000),
+    # the force as the divergence of the stress of Eq. (muf)
+    (H.FD, 1.0 / 3000, 1, 4000), (H.FV, 1.0 / 3000, 1, 4000)])
+def test_capillary_spectrum(smol, kT, force_form, nsamp):
     """The paper's capillary set-up (Sec. VI.C): a 1024 x 128 D2Q9 lattice with
     two flat interfaces 64 sites apart, -A = B = 0.05, K = 0.2, M = 0.1,
     kT = 1/3000 or 1e-7 (Fig. flucinterf), nu = c_s^2 tau with tau = 0.45.
     The height spectrum of the longest modes follows <|h_q|^2>/L =
-    kT/(gamma q^2) (Eq. flucinterf) with gamma from Eq. (st).  The bar is about
-    3 standard errors of the mean over the 16 longest modes (run-to-run spread
-    ~0.04 at 4000 samples)."""
+    kT/(gamma q^2) (Eq. flucinterf) with gamma from Eq. (st).
+
+    The heights come from linear interpolation between the two sites that
+    bracket the zero of psi, whose response to a displacement depends on
+    where the interface sits between sites: on the tanh profile its gain g
+    runs from 1/(l tanh(1/l)) = 1.041 (interface on a site) to 0.979 (half-way)
+    and averages to 1 over the offsets.  A rough interface (kT = 1/3000,
+    rms height ~0.5 sites) samples every offset; at kT = 1e-7 (rms ~0.01
+    sites) every column sits at the same offset, and |h_q|^2 carries g^2 of
+    that offset (up to 8%).  Each snapshot's |h_q|^2 is therefore divided by
+    the square of the mean gain over its columns (tests/theory.height_gain).
+
+    Per sample, r = |h_q|^2 gamma q^2/(L kT) averaged over both interfaces
+    and the 16 longest modes; its standard error comes from 30 batch means
+    (each batch spans several relaxation times of the longest mode).  Bar:
+    |<r> - 1| <= 3 SE + 0.03, the 0.03 allowing the finite-thickness
+    correction, of order (q l)^2 = 0.028 averaged over these modes (l = 2.83).
+
+    With the stress-divergence force the spectrum is a known excess (measured
+    1.09-1.20 with FD, 1.03-1.10 with FV): the discrete stress divergence is
+    not the exact adjoint of the advection, so the reversible coupling is not
+    energy-neutral on the lattice and heats the interface modes slightly (the
+    default -psi grad mu form pairs with Div = -Grad^T and is).  There the
+    test asserts the documented band: no deficit beyond the bar and an excess
+    below 0.3."""
     from paper_1104_0078_amd import lbl
     nx, ny = 1024, 128
     a, b, kappa = -0.05, 0.05, 0.2
@@ -304,19 +325,38 @@ def test_capillary_spectrum(smol, kT, force_form, nsamp, bar):
                  force_form=force_form)
     print("capillary case", c, flush=True)
     gamma = 2 * np.sqrt(2) / 3 * np.sqrt(kappa * abs(a) ** 3) / b
-    acc = np.zeros(nx)
-    with _sim(c) as sim:
-        sim.step(20000)
-        for _ in range(nsamp):
-            sim.step(100)
-            psi = sim.observe(lbl.LBL_OBS_PSI)
-            for lo, hi in ((8, 56), (72, 120)):  # interfaces at y = 32 and 96
-                h = _interface_heights(psi, nx, ny, lo, hi)
-                acc += np.abs(np.fft.fft(h - h.mean())) ** 2 / nx / 2
-    S = acc / nsamp
     m = np.arange(1, 17)
     q = 2 * np.pi * m / nx
-    ratio = S[m] * gamma * q ** 2 / kT
-    print("  capillary <|h_q|^2> gamma q^2/(L kT), m = 1..16: mean %.3f" % ratio.mean(),
+    l = np.sqrt(-2 * kappa / a)
+    series = np.empty(nsamp)
+    raw = np.empty(nsamp)
+    gains = np.empty((nsamp, 2))
+    per_mode = np.zeros(m.size)
+    with _sim(c) as sim:
+        sim.step(20000)
+        for k in range(nsamp):
+            sim.step(100)
+            psi = sim.observe(lbl.LBL_OBS_PSI)
+            sq = np.zeros(m.size)
+            sq_raw = np.zeros(m.size)
+            for j, (lo, hi) in enumerate(((8, 56), (72, 120))):  # interfaces at y = 32, 96
+                h = _interface_heights(psi, nx, ny, lo, hi)
+                gains[k, j] = T.height_gain(h, l)
+                s2 = np.abs(np.fft.fft(h - h.mean())[m]) ** 2 / nx / 2
+                sq_raw += s2
+                sq += s2 / gains[k, j] ** 2
+            r = sq * gamma * q ** 2 / kT
+            per_mode += r
+            series[k] = r.mean()
+            raw[k] = (sq_raw * gamma * q ** 2 / kT).mean()
+    nb = nsamp // CAP_BATCHES
+    bm = series[:nb * CAP_BATCHES].reshape(CAP_BATCHES, nb).mean(axis=1)
+    mean, se = bm.mean(), bm.std(ddof=1) / np.sqrt(CAP_BATCHES)
+    print("  capillary <|h_q|^2> gamma q^2/(L kT), m = 1..16: %.4f +- %.4f (estimator gain "
+          "%.4f, uncorrected %.4f); per mode %s"
+          % (mean, se, gains.mean(), raw.mean(), np.round(per_mode / nsamp, 3).tolist()),
           flush=True)
-    assert abs(ratio.mean() - 1) < bar
+    if force_form == 0:
+        assert abs(mean - 1) <= 3 * se + 0.03
+    else:
+        assert -(3 * se + 0.03) <= mean - 1 <= 0.3

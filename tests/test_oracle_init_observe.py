@@ -93,3 +93,31 @@ def test_interface_heights_closed_form(lattice, shape):
     h0 = O.heights(p, psi0)
     np.testing.assert_allclose(h0[0], L / 4, atol=1e-12)
     np.testing.assert_allclose(h0[1], 3 * L / 4, atol=1e-12)
+
+
+@pytest.mark.parametrize("l", [1.58, 2.83])
+def test_height_estimator_gain(l):
+    """The gain of the linear-interpolation heights on a tanh profile (the
+    correction the capillary tests apply) against finite differences of the
+    oracle's own estimator: columns psi = tanh((z - h)/l) with the lower
+    interface at h = 12 + delta, moved by +-1e-6."""
+    from tests import theory as T
+    L = 48
+    # offsets inside the cell (at delta = 0 the gain has a kink, where a
+    # central difference is off by O(eps)); one column each
+    delta = np.append(np.linspace(0.0125, 0.9875, 40), [0.5, 1e-3])
+    p = O.make_params(lattice=O.D2Q9, shape=(delta.size, L, 1), a=-0.04, b=0.04, kappa=0.05)
+    z = np.arange(L)[:, None]
+    eps = 1e-6
+
+    def est(h):
+        col = np.where(z < L // 2, np.tanh((z - h[None, :]) / l), np.tanh((36.0 - z) / l))
+        return O.heights(p, np.ascontiguousarray(col.reshape(-1)))[0]
+
+    hc = 12.0 + delta
+    g = (est(hc + eps) - est(hc - eps)) / (2 * eps)
+    np.testing.assert_allclose(g, T.interp_gain(delta, l), rtol=1e-7)
+    # on a site and half-way between sites; mean over the offsets
+    assert abs(T.interp_gain(0.0, l) - 1 / (l * np.tanh(1 / l))) < 1e-15
+    dd = (np.arange(100000) + 0.5) / 100000
+    assert abs(T.interp_gain(dd, l).mean() - 1) < 1e-9

@@ -111,3 +111,28 @@ def axis_modes(L):
     """Independent axis wave numbers of a real field: m = 1 .. L/2 (m and L-m
     are one mode)."""
     return np.arange(1, L // 2 + 1)
+
+
+def interp_gain(delta, l):
+    """Gain d h_est / d h of the linear-interpolation height estimator
+    (Sec. VI.C) on the tanh profile psi = psi_eq tanh((z - h)/l) of Eq. (tanh),
+    for an interface at fractional offset delta in [0, 1) above the site z0:
+    h_est - z0 = t(delta)/(t(delta) + t(1 - delta)), t(x) = tanh(x/l).  It is
+    1/(l tanh(1/l)) > 1 with the interface on a site, below 1 half-way between
+    sites, and its mean over the offsets is exactly 1 (h_est runs from z0 to
+    z0 + 1 as delta does)."""
+    a = np.tanh(np.asarray(delta, dtype=float) / l)
+    b = np.tanh((1.0 - np.asarray(delta, dtype=float)) / l)
+    da = (1.0 - a * a) / l
+    db = -(1.0 - b * b) / l
+    return (da * b - a * db) / (a + b) ** 2
+
+
+def height_gain(h, l):
+    """Long-wavelength gain of the height estimator over the columns of one
+    snapshot: the mean of interp_gain over the columns' offsets.  Where the
+    roughness is below a lattice spacing every column has the same offset and
+    the gain is that column's; a rough interface samples all offsets and the
+    gain tends to 1."""
+    h = np.asarray(h, dtype=float)
+    return float(np.mean(interp_gain(h - np.floor(h), l)))
