@@ -268,7 +268,9 @@ def make_sim_params(lbl, w, precision=None, seed=1234):
                            precision=w["precision"] if precision is None else precision,
                            shape=w["shape"], rho=1.0, eta=w["eta"], M=w["M"], a=w["a"],
                            b=w["b"], kappa=w["kappa"], kT=w["kT"], seed=seed,
-                           fd_noise=w.get("fd_noise", 0), force_form=w.get("force_form", 0))
+                           fd_noise=w.get("fd_noise", 0), force_form=w.get("force_form", 0),
+                           walls=w.get("walls", 0),
+                           u_wall=w.get("u_wall", ((0, 0, 0), (0, 0, 0))))
 
 
 def run_single(lbl, torch, w, wname, steps, warmup, tune, precision=None, schedule=None):
@@ -511,6 +513,8 @@ def main():
                     help="skip the FD variant of the same lattice (link vs Fourier noise)")
     ap.add_argument("--no-stress", action="store_true",
                     help="skip the run of the same workload with the stress-divergence force")
+    ap.add_argument("--no-walls", action="store_true",
+                    help="skip the leg with sliding walls across the last axis")
     ap.add_argument("--no-tune", action="store_true", help="no autotuning of the pool legs")
     ap.add_argument("--tune-single", action="store_true",
                     help="autotune the single-run schedule too (default: the library's own)")
@@ -670,6 +674,18 @@ def main():
             "ms_per_step": round(rs_["ms_per_step"], 4),
             "kernels_ms_per_step": {t[0]: round(t[2] / nst, 4) for t in rs_["ktimes"]}}
         print("stress force leg done: %.1f MLUPS" % rs_["mlups"], file=sys.stderr, flush=True)
+    if not args.no_walls and w["smol"] == 1:
+        # The same workload between walls across the last axis sliding at
+        # (0.02, -0.01, 0) and (-0.015, 0.01, 0): bounce-back LB passes and
+        # the wall stencils (per-site kernels).
+        nw = min(args.steps, 30)
+        ww = dict(w, walls=1, u_wall=((0.02, -0.01, 0.0), (-0.015, 0.01, 0.0)))
+        rw = run_single(lbl, torch, ww, args.workload, nw, args.warmup, False)
+        out["walls_same_workload"] = {
+            "value": round(rw["mlups"], 2), "unit": "MLUPS",
+            "ms_per_step": round(rw["ms_per_step"], 4),
+            "kernels_ms_per_step": {t[0]: round(t[2] / nw, 4) for t in rw["ktimes"]}}
+        print("walls leg done: %.1f MLUPS" % rw["mlups"], file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = {}
         for prec, name in ((1, "fp32"), (0, "fp64")):
