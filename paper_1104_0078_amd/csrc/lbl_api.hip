@@ -611,14 +611,19 @@ struct Impl {
     const bool ghost = s->gamma_g != 0.0;
     const hipStream_t st = s->stream;
     if (s->p.walls == LBL_WALLS_LAST) {
-      // walls: the non-temporal choice is left to the default policy
       return launch(s, name, [&] {
-        if (!collide)
-          k_lb<S, DEV, Q, SMOL, false, false, false, true><<<grid, block, 0, st>>>(a, m);
-        else if (ghost)
+        if (!collide) {
+          if (a.nt)
+            k_lb<S, DEV, Q, SMOL, false, false, true, true><<<grid, block, 0, st>>>(a, m);
+          else
+            k_lb<S, DEV, Q, SMOL, false, false, false, true><<<grid, block, 0, st>>>(a, m);
+        } else if (ghost) {
           k_lb<S, DEV, Q, SMOL, true, true, false, true><<<grid, block, 0, st>>>(a, m);
-        else
+        } else if (a.nt) {
+          k_lb<S, DEV, Q, SMOL, false, true, true, true><<<grid, block, 0, st>>>(a, m);
+        } else {
           k_lb<S, DEV, Q, SMOL, false, true, false, true><<<grid, block, 0, st>>>(a, m);
+        }
       });
     }
     return launch(s, name, [&] {
@@ -742,7 +747,12 @@ struct Impl {
     // step's stages, its last readers, precede the fork.  Joined before the
     // first stage.
     const bool walls = s->p.walls == LBL_WALLS_LAST;
-    if (walls) {
+    // 3-D lattices run the z-marching SMOL kernels with the wall rules on
+    // the end planes; 2-D lattices (walls across y) the per-site passes.
+    constexpr bool kTiledWalls = Lat<Q>::D == 3 && SMOL == kFV;
+    const bool walls_tiled = walls && kTiledWalls;
+    const bool walls_site = walls && !walls_tiled;
+    if (walls_site) {
       // per-site passes; the node-noise buffer is consumed before the stages
       if (want_mu)
         if (int rc = launch_mu(s, psin, static_cast<S*>(s->mu))) return rc;
@@ -755,7 +765,7 @@ struct Impl {
       if (int rc = hip_check(s, hipEventRecord(s->ev_fork, s->stream), "fork")) return rc;
       if (int rc = hip_check(s, hipStreamWaitEvent(s->aux, s->ev_fork, 0), "fork")) return rc;
     }
-    for (int part = split ? 0 : 1; part < 2 && !walls; ++part) {
+    for (int part = split ? 0 : 1; part < 2 && !walls_site; ++part) {
       // part 0: the noise alone on `aux`; part 1: what remains on the stream
       const bool do_noise = prep_noise && (part == 0 || !split);
       const bool do_mu = want_mu && part == 1;
@@ -774,7 +784,13 @@ struct Impl {
       pa.mu = do_mu ? static_cast<S*>(s->mu) : nullptr;
       const char* name = part == 0 ? "k_prep_noise" : "k_prep";
       int rc;
-      if (SMOL == kFV)
+      if constexpr (kTiledWalls) {
+        if (walls_tiled)
+          rc = launch_on(s, ps, name,
+                         [&] { k_prep_fv<S, Q, true><<<tgp, tb, 0, ps>>>(pa, tmp); });
+        else
+          rc = launch_on(s, ps, name, [&] { k_prep_fv<S, Q><<<tgp, tb, 0, ps>>>(pa, tmp); });
+      } else if (SMOL == kFV)
         rc = launch_on(s, ps, name, [&] { k_prep_fv<S, Q><<<tgp, tb, 0, ps>>>(pa, tmp); });
       else
         rc = launch_on(s, ps, name, [&] { k_prep_fd<S, Q><<<tgp, tb, 0, ps>>>(pa, tmp); });
@@ -836,9 +852,15 @@ struct Impl {
         a.out = a.last ? psout : static_cast<S*>(s->phi[st & 1]);
         const hipStream_t ss = (fork && st == 0) ? s->aux : s->stream;
         int rc;
-        if (walls)
+        if (walls_site) {
           rc = wall_stage(s, a);
-        else if (SMOL == kFV)
+        } else if constexpr (kTiledWalls) {
+          if (walls_tiled)
+            rc = launch_on(s, ss, "k_stage",
+                           [&] { k_stage_fv<S, Q, true><<<tg, tb, 0, ss>>>(a, tm); });
+          else
+            rc = launch_on(s, ss, "k_stage", [&] { k_stage_fv<S, Q><<<tg, tb, 0, ss>>>(a, tm); });
+        } else if (SMOL == kFV)
           rc = launch_on(s, ss, "k_stage", [&] { k_stage_fv<S, Q><<<tg, tb, 0, ss>>>(a, tm); });
         else
           rc = launch_on(s, ss, "k_stage", [&] { k_stage_fd<S, Q><<<tg, tb, 0, ss>>>(a, tm); });

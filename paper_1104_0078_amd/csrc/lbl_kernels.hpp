@@ -238,6 +238,23 @@ struct SoPlanes {
     k[0] = k[1];
     k[1] = k[2];
   }
+  // mu at the middle plane with the plane below (lo) or above (hi) beyond a
+  // wall: every link into it takes the centre value, i.e. that plane reads
+  // as uniform at c[1] (centre, 4 faces, 4 corners).
+  __device__ __forceinline__ S mu_walled(const Coef<S>& co, bool lo, bool hi) const {
+    SoPlanes<S> w = *this;
+    if (lo) {
+      w.c[0] = c[1];
+      w.f[0] = S(4) * c[1];
+      w.k[0] = S(4) * c[1];
+    }
+    if (hi) {
+      w.c[2] = c[1];
+      w.f[2] = S(4) * c[1];
+      w.k[2] = S(4) * c[1];
+    }
+    return w.mu(co);
+  }
 };
 
 template <typename S, int Q>
@@ -405,6 +422,18 @@ inline constexpr Opposite<Q> kOpp = make_opposite<Q>();
 template <int Q>
 __host__ __device__ constexpr int c_last(int i) {
   return Lat<Q>::D == 3 ? Lat<Q>::cz[i] : Lat<Q>::cy[i];
+}
+
+// Weight sum of the velocities that cross one wall (c_last = +1; the same
+// for -1 by symmetry): 1/6 on D3Q19 and D3Q15.  The flux rule of a wall
+// (minus the centre's value beyond it) turns the links across it into
+// -(sum of w_i c_i over them) . X(x) = +-W X_last(x).
+template <int Q>
+constexpr double wall_weight() {
+  double s = 0;
+  for (int i = 0; i < Q; ++i)
+    if (c_last<Q>(i) > 0) s += Lat<Q>::w[i];
+  return s;
 }
 
 // True when the offset (dy, dz) from a site at (y, z) leaves the lattice
@@ -729,7 +758,10 @@ __device__ __forceinline__ S prep_mu2(const PsiPlane<S>& r, const Coef<S>& c, in
 // (halo 1) lives in LDS at a time; each plane is folded into register partial
 // sums of N for the planes below, at and above it.  mu(psi) comes from one
 // psi plane and the plane sums of SoPlanes.
-template <typename S, int Q>
+// WALLS (3-D): walls across z.  A plane beyond a wall is neither drawn nor
+// folded; the links across it take minus the centre's xi (a term +-W xi_z
+// on the end planes) and the Laplacian the centre's psi (SoPlanes::mu_walled).
+template <typename S, int Q, bool WALLS = false>
 __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int by, int bz) {
   using L = Lat<Q>;
   constexpr int D = L::D;
@@ -789,12 +821,19 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
     const int plane = g.nx * g.ny;
     int pz = wrap_any(z0 - 1, g.nz);
     for (int p = z0 - 1; p <= z1; ++p, pz = next_plane(pz, g.nz)) {
-      if (a.noise) gen(plane * pz);
+      const bool ghost = WALLS && (p < 0 || p >= g.nz);  // a plane beyond a wall
+      if (a.noise && !ghost) gen(plane * pz);
       if (a.mu) prep_load_psi(spsi, a.psi, rxy, plane * pz, tid);
       __syncthreads();
       const bool emit = p - 1 >= z0 && p - 1 < z1;
       if (a.noise) {
-        fold();
+        if (!ghost) fold();
+        if constexpr (WALLS) {
+          constexpr S kWall = S(wall_weight<Q>());
+          const S xz = xi[D - 1][(tx + 1) + W * (ty + 1)];
+          if (p == 0) npart[1] += kWall * xz;
+          if (p == g.nz - 1) npart[1] -= kWall * xz;
+        }
         if (emit && live) a.noise[x + g.nx * (y + g.ny * (p - 1))] = S(3) * a.amp * npart[0];
         npart[0] = npart[1];
         npart[1] = npart[2];
@@ -802,7 +841,9 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
       }
       if (a.mu && live) {
         so.template push<W>(spsi.v + (tx + 1) + W * (ty + 1));
-        if (emit) a.mu[x + g.nx * (y + g.ny * (p - 1))] = so.mu(a.c);
+        if (emit)
+          a.mu[x + g.nx * (y + g.ny * (p - 1))] =
+              WALLS ? so.mu_walled(a.c, p - 1 == 0, p - 1 == g.nz - 1) : so.mu(a.c);
         so.roll();
       }
       __syncthreads();
@@ -810,10 +851,10 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
   }
 }
 
-template <typename S, int Q>
+template <typename S, int Q, bool WALLS = false>
 __global__ __launch_bounds__(kTX* kTY) void k_prep_fv(PrepArgs<S> a, TileMap m) {
   int bx, by, bz;
-  if (tile_of(m, bx, by, bz)) prep_fv_body<S, Q>(a, bx, by, bz);
+  if (tile_of(m, bx, by, bz)) prep_fv_body<S, Q, WALLS>(a, bx, by, bz);
 }
 
 // Stress-divergence force of the FV variant in 3-D (sigma and F = -G.sigma of
@@ -1257,7 +1298,10 @@ __device__ __forceinline__ void stage_fv2_body(const StageArgs<S>& a, int bx, in
 // the plane z - cz).  A thread owns fixed points of the mu region (index
 // e = tid + k NT in a (kTX+4) x (kTY+4) layout; J lives on its inner ring) and
 // one G point; iteration p loads phi(p) and emits mu(p-1), J(p-2), G(p-3).
-template <typename S, int Q>
+// WALLS: walls across z.  The Laplacian and Gamma mu take the centre's value
+// beyond a wall; a J plane beyond a wall is not folded, and the links across
+// it take minus the centre's J (a term +-W J_z on the end planes).
+template <typename S, int Q, bool WALLS = false>
 __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, int by, int bz) {
   using L = Lat<Q>;
   constexpr int D = 3;
@@ -1344,11 +1388,14 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
       if (!pon[k]) continue;
       const int e = tid + k * NT;
       so[k].template push<WP>(sphi + (e % WM + 1) + WP * (e / WM + 1));
-      if (do_mu) smu[mslot][e] = so[k].mu(a.c);
+      if (do_mu)
+        smu[mslot][e] = WALLS ? so[k].mu_walled(a.c, p - 1 == 0, p - 1 == g.nz - 1)
+                              : so[k].mu(a.c);
     }
     __syncthreads();
     // J(p-2) from mu(p-3), mu(p-2), mu(p-1).
     if (do_J) {
+      const bool jlo = WALLS && p - 2 == 0, jhi = WALLS && p - 2 == g.nz - 1;
 #pragma unroll
       for (int k = 0; k < NE; ++k) {
         if (!jon[k]) continue;
@@ -1356,7 +1403,9 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
         S gm[3] = {0, 0, 0};
 #pragma unroll
         for (int q = 1; q < Q; ++q) {
-          const S t = S(L::w[q]) * smu[ring(p - 2 + L::cz[q], 3)][e + L::cx[q] + WM * L::cy[q]];
+          const bool cut = (jlo && L::cz[q] < 0) || (jhi && L::cz[q] > 0);
+          const S t = S(L::w[q]) * (cut ? smu[ring(p - 2, 3)][e]
+                                        : smu[ring(p - 2 + L::cz[q], 3)][e + L::cx[q] + WM * L::cy[q]]);
           if (L::cx[q]) gm[0] += L::cx[q] * t;
           if (L::cy[q]) gm[1] += L::cy[q] * t;
           if (L::cz[q]) gm[2] += L::cz[q] * t;
@@ -1371,14 +1420,22 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
     __syncthreads();
     // Gamma . J(p-2) into the G partials; G(p-3) complete.
     if (do_J) {
+      if (!(WALLS && (p - 2 < 0 || p - 2 >= g.nz))) {
 #pragma unroll
-      for (int q = 1; q < Q; ++q) {
-        const int e = (tx + 2 + L::cx[q]) + WM * (ty + 2 + L::cy[q]);
-        S v = 0;
-        if (L::cx[q]) v += L::cx[q] * sJ[0][e];
-        if (L::cy[q]) v += L::cy[q] * sJ[1][e];
-        if (L::cz[q]) v += L::cz[q] * sJ[2][e];
-        gpart[1 - L::cz[q]] += S(L::w[q]) * v;
+        for (int q = 1; q < Q; ++q) {
+          const int e = (tx + 2 + L::cx[q]) + WM * (ty + 2 + L::cy[q]);
+          S v = 0;
+          if (L::cx[q]) v += L::cx[q] * sJ[0][e];
+          if (L::cy[q]) v += L::cy[q] * sJ[1][e];
+          if (L::cz[q]) v += L::cz[q] * sJ[2][e];
+          gpart[1 - L::cz[q]] += S(L::w[q]) * v;
+        }
+      }
+      if constexpr (WALLS) {
+        constexpr S kWall = S(wall_weight<Q>());
+        const S jz = sJ[2][(tx + 2) + WM * (ty + 2)];
+        if (p - 2 == 0) gpart[1] += kWall * jz;
+        if (p - 2 == g.nz - 1) gpart[1] -= kWall * jz;
       }
       if (do_G) combine_in(a, s, S(3) * gpart[0] + sv.noise, sv);
       gpart[0] = gpart[1];
@@ -1388,18 +1445,18 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
   }
 }
 
-template <typename S, int Q>
+template <typename S, int Q, bool WALLS = false>
 __device__ __forceinline__ void stage_fv_body(const StageArgs<S>& a, int bx, int by, int bz) {
   if constexpr (Lat<Q>::D == 3)
-    stage_fv3_body<S, Q>(a, bx, by, bz);
+    stage_fv3_body<S, Q, WALLS>(a, bx, by, bz);
   else
     stage_fv2_body<S, Q>(a, bx, by);
 }
 
-template <typename S, int Q>
+template <typename S, int Q, bool WALLS = false>
 __global__ __launch_bounds__(kTX* kTY) void k_stage_fv(StageArgs<S> a, TileMap m) {
   int bx, by, bz;
-  if (tile_of(m, bx, by, bz)) stage_fv_body<S, Q>(a, bx, by, bz);
+  if (tile_of(m, bx, by, bz)) stage_fv_body<S, Q, WALLS>(a, bx, by, bz);
 }
 
 // FD stage (Sec. V.A): G = -D.(u phi) + M L_SO mu(phi) + N with the central

@@ -113,9 +113,10 @@ def test_walls_schedules_do_not_change_results():
     c = H.config(lattice=H.D3Q19, smol=H.FV, shape=(70, 21, 13), init=1, a=-0.04, b=0.04,
                  kappa=0.05, walls=1, u_wall=SLIDE)
     out = []
-    for w, swz, ov in ((64, 0, 0), (32, 1, 1), (256, 3, 2)):
+    # z-chunks of 4 and 5 planes put chunk edges next to both walls (nz = 13)
+    for w, swz, zc, ov in ((64, 0, 0, 0), (32, 1, 4, 1), (256, 3, 5, 2), (128, 2, 13, 0)):
         with lbl.Sim(H.lbl_params(c), lbl.make_init(kind=1, psi_std=1e-3)) as sim:
-            sim.set_schedule(lb_width=w, xcd_swizzle=swz, zc=0, overlap=ov)
+            sim.set_schedule(lb_width=w, xcd_swizzle=swz, zc=zc, overlap=ov)
             sim.step(6)
             out.append((sim.observe(lbl.LBL_OBS_POP), sim.observe(lbl.LBL_OBS_PSI)))
     for f, p in out[1:]:
