@@ -1546,7 +1546,9 @@ __global__ __launch_bounds__(kTX* kTY) void k_stage_fd(StageArgs<S> a, TileMap m
 
 // ---------------------------------------------------------------------------
 // FV SMOL between walls across the last axis: per-site passes (one thread per
-// site, the k_mu grid) with the links that cross a wall removed.  Per step:
+// site, the k_mu grid) with the links that cross a wall removed, used on 2-D
+// lattices (3-D lattices take the WALLS variants of the z-marching kernels;
+// these passes also give the velocity observable its mu).  Per step:
 // mu(psi^n) for the force, the node noise xi into a buffer and N^n = Div xi;
 // per stage: mu(phi), the node flux J = -u phi + M Grad mu, and
 // G = Div J + N with the stage's combination.  Grad takes the centre's value
