@@ -62,7 +62,7 @@ struct lbl_sim {
   double* fk_acc = nullptr;        // sum over samples of |psi_q|^2 / N
   void* sig = nullptr;      // force_form STRESS: order-parameter stress, d(d+1)/2 components
   void* fstress = nullptr;  // and its divergence, the force density (d*N)
-  void* wflux = nullptr;    // walls: node noise, then the stages' node flux (d*N)
+  void* wflux = nullptr;    // 2-D walls: node noise, then the stages' node flux (d*N)
   double* part = nullptr;
   int nparts = 0;
   double* tot = nullptr;
@@ -1175,8 +1175,9 @@ Plan alloc_plan(const lbl_params& p) {
           // sample_full_k: the half spectrum of psi and its FP64 accumulator
           p.sample_full_k ? 2 * sz * half_spectrum(p) : 0,
           p.sample_full_k ? sizeof(double) * half_spectrum(p) : 0,
-          // walls: the node noise, then each stage's node flux (d*N)
-          p.walls == LBL_WALLS_LAST ? sz * N * d : 0};
+          // walls on a 2-D lattice (per-site passes): the node noise, then
+          // each stage's node flux (d*N); 3-D lattices keep them on chip
+          p.walls == LBL_WALLS_LAST && p.lattice == LBL_D2Q9 ? sz * N * d : 0};
 }
 
 size_t obs_bytes(const lbl_sim* s, int what) {

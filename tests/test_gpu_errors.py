@@ -178,3 +178,20 @@ def test_sim_bytes_match_the_allocations(case, options):
         n = len(mem.live)
     want = lbl.lbl_sim_bytes(params)
     assert want <= taken <= want + 8 * n
+
+
+@pytest.mark.parametrize("lattice,shape", [(H.D2Q9, (37, 21, 1)), (H.D3Q19, (13, 11, 9))])
+def test_sim_bytes_match_the_allocations_with_walls(lattice, shape):
+    """The same with walls: a 2-D lattice takes the per-site passes' flux
+    buffer, a 3-D lattice nothing more."""
+    from paper_1104_0078_amd import lbl
+    c = H.config(lattice=lattice, smol=H.FV, shape=shape, walls=1,
+                 u_wall=((0.01, 0, 0), (-0.01, 0, 0)))
+    params = H.lbl_params(c)
+    mem = CountingMemory()
+    with lbl.Sim(params, lbl.make_init(psi_std=1e-3), memory=mem) as sim:
+        taken = sum(mem.live.values())
+        n = len(mem.live)
+        sim.step(2)
+    want = lbl.lbl_sim_bytes(params)
+    assert want <= taken <= want + 8 * n
