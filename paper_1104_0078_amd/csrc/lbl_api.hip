@@ -62,7 +62,6 @@ struct lbl_sim {
   double* fk_acc = nullptr;        // sum over samples of |psi_q|^2 / N
   void* sig = nullptr;      // force_form STRESS: order-parameter stress, d(d+1)/2 components
   void* fstress = nullptr;  // and its divergence, the force density (d*N)
-  void* wflux = nullptr;    // 2-D walls: node noise, then the stages' node flux (d*N)
   double* part = nullptr;
   int nparts = 0;
   double* tot = nullptr;
@@ -684,37 +683,6 @@ struct Impl {
     return launch(s, "k_mu", [&] { k_mu<S, Q><<<grid, block, 0, s->stream>>>(g, c, phi, mu); });
   }
 
-  // SMOL noise between walls: node noise into s->wflux, N = Div xi.
-  static int wall_noise(lbl_sim* s, uint32_t step) {
-    const Geom g = geom(s);
-    S* xi = static_cast<S*>(s->wflux);
-    const S amp = S(std::sqrt(2.0 * s->p.kT * s->p.M));
-    if (int rc = launch(s, "k_xi", [&] {
-          k_xi<S, Lat<Q>::D><<<grid_for(s->N), kBlock, 0, s->stream>>>(g, step, s->k0, s->k1,
-                                                                      amp, xi);
-        }))
-      return rc;
-    const dim3 grid = site_grid(s), block(kBX, kBY);
-    S* noise = static_cast<S*>(s->noise);
-    return launch(s, "k_div_noise_w", [&] {
-      k_div_noise_w<S, Q><<<grid, block, 0, s->stream>>>(g, xi, noise);
-    });
-  }
-
-  // One Runge-Kutta stage between walls: mu(phi), the node flux, then the
-  // divergence with the stage's combination.
-  static int wall_stage(lbl_sim* s, const StageArgs<S>& a) {
-    const dim3 grid = site_grid(s), block(kBX, kBY);
-    S* mu = static_cast<S*>(s->mu);
-    S* J = static_cast<S*>(s->wflux);
-    if (int rc = launch_mu(s, a.phi, mu)) return rc;
-    if (int rc = launch(s, "k_flux_w",
-                        [&] { k_flux_w<S, Q><<<grid, block, 0, s->stream>>>(a, mu, J); }))
-      return rc;
-    return launch(s, "k_stage_w",
-                  [&] { k_stage_w<S, Q><<<grid, block, 0, s->stream>>>(a, J); });
-  }
-
   static int one_step(lbl_sim* s) {
     const Geom g = geom(s);
     const uint32_t n = static_cast<uint32_t>(s->step);
@@ -747,25 +715,16 @@ struct Impl {
     // step's stages, its last readers, precede the fork.  Joined before the
     // first stage.
     const bool walls = s->p.walls == LBL_WALLS_LAST;
-    // 3-D lattices run the z-marching SMOL kernels with the wall rules on
-    // the end planes; 2-D lattices (walls across y) the per-site passes.
-    constexpr bool kTiledWalls = Lat<Q>::D == 3 && SMOL == kFV;
+    // Walls (an FV option) run the tiled SMOL kernels with the wall rules.
+    constexpr bool kTiledWalls = SMOL == kFV;
     const bool walls_tiled = walls && kTiledWalls;
-    const bool walls_site = walls && !walls_tiled;
-    if (walls_site) {
-      // per-site passes; the node-noise buffer is consumed before the stages
-      if (want_mu)
-        if (int rc = launch_mu(s, psin, static_cast<S*>(s->mu))) return rc;
-      if (prep_noise)
-        if (int rc = wall_noise(s, n)) return rc;
-    }
     const bool split = !walls && prep_noise && s->overlap == 2;
     if (split) {
       if (int rc = ensure_aux(s)) return rc;
       if (int rc = hip_check(s, hipEventRecord(s->ev_fork, s->stream), "fork")) return rc;
       if (int rc = hip_check(s, hipStreamWaitEvent(s->aux, s->ev_fork, 0), "fork")) return rc;
     }
-    for (int part = split ? 0 : 1; part < 2 && !walls_site; ++part) {
+    for (int part = split ? 0 : 1; part < 2; ++part) {
       // part 0: the noise alone on `aux`; part 1: what remains on the stream
       const bool do_noise = prep_noise && (part == 0 || !split);
       const bool do_mu = want_mu && part == 1;
@@ -852,9 +811,7 @@ struct Impl {
         a.out = a.last ? psout : static_cast<S*>(s->phi[st & 1]);
         const hipStream_t ss = (fork && st == 0) ? s->aux : s->stream;
         int rc;
-        if (walls_site) {
-          rc = wall_stage(s, a);
-        } else if constexpr (kTiledWalls) {
+        if constexpr (kTiledWalls) {
           if (walls_tiled)
             rc = launch_on(s, ss, "k_stage",
                            [&] { k_stage_fv<S, Q, true><<<tg, tb, 0, ss>>>(a, tm); });
@@ -1149,7 +1106,7 @@ Table select(const lbl_params& p) {
 }
 
 // Device allocations of one simulation, in creation order.
-constexpr int kPlanBuffers = 24;
+constexpr int kPlanBuffers = 23;
 using Plan = std::array<size_t, kPlanBuffers>;
 
 Plan alloc_plan(const lbl_params& p) {
@@ -1174,10 +1131,7 @@ Plan alloc_plan(const lbl_params& p) {
           p.force_form == LBL_FORCE_STRESS ? sz * N * d : 0,
           // sample_full_k: the half spectrum of psi and its FP64 accumulator
           p.sample_full_k ? 2 * sz * half_spectrum(p) : 0,
-          p.sample_full_k ? sizeof(double) * half_spectrum(p) : 0,
-          // walls on a 2-D lattice (per-site passes): the node noise, then
-          // each stage's node flux (d*N); 3-D lattices keep them on chip
-          p.walls == LBL_WALLS_LAST && p.lattice == LBL_D2Q9 ? sz * N * d : 0};
+          p.sample_full_k ? sizeof(double) * half_spectrum(p) : 0};
 }
 
 size_t obs_bytes(const lbl_sim* s, int what) {
@@ -1266,7 +1220,6 @@ void assign_buffers(lbl_sim* s, const std::array<void*, kPlanBuffers>& b) {
   s->fstress = b[20];
   s->fk_spec = b[21];
   s->fk_acc = static_cast<double*>(b[22]);
-  s->wflux = b[23];
 }
 
 int create_impl(const lbl_params* params, const lbl_init* init, const lbl_env* env,

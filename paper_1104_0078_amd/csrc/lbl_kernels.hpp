@@ -744,11 +744,14 @@ __device__ __forceinline__ void prep_load_psi(PsiPlane<S>& r, const S* __restric
   }
 }
 
-// 2-D mu at the tile point (tx, ty).
-template <typename S>
-__device__ __forceinline__ S prep_mu2(const PsiPlane<S>& r, const Coef<S>& c, int tx, int ty) {
+// 2-D mu at the tile point (tx, ty).  WALLS: walls across y; a neighbour
+// row beyond a wall (global row y + dy outside [0, ny)) reads the centre.
+template <typename S, bool WALLS = false>
+__device__ __forceinline__ S prep_mu2(const PsiPlane<S>& r, const Coef<S>& c, int tx, int ty,
+                                      int y = 0, int ny = 0) {
   using R = PsiPlane<S>;
   return chem_pot<S, 2>(c, [&](int dx, int dy, int) {
+    if (WALLS && (y + dy < 0 || y + dy >= ny)) return r.v[(tx + 1) + R::W * (ty + 1)];
     return r.v[(tx + 1 + dx) + R::W * (ty + 1 + dy)];
   });
 }
@@ -758,9 +761,11 @@ __device__ __forceinline__ S prep_mu2(const PsiPlane<S>& r, const Coef<S>& c, in
 // (halo 1) lives in LDS at a time; each plane is folded into register partial
 // sums of N for the planes below, at and above it.  mu(psi) comes from one
 // psi plane and the plane sums of SoPlanes.
-// WALLS (3-D): walls across z.  A plane beyond a wall is neither drawn nor
-// folded; the links across it take minus the centre's xi (a term +-W xi_z
-// on the end planes) and the Laplacian the centre's psi (SoPlanes::mu_walled).
+// WALLS: walls across the last axis.  3-D: a plane beyond a wall is neither
+// drawn nor folded; the links across it take minus the centre's xi (a term
+// +-W xi_z on the end planes) and the Laplacian the centre's psi
+// (SoPlanes::mu_walled).  2-D: a link to a row beyond a wall takes minus the
+// centre's xi, and the Laplacian the centre's psi.
 template <typename S, int Q, bool WALLS = false>
 __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int by, int bz) {
   using L = Lat<Q>;
@@ -799,11 +804,17 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
   auto fold = [&]() {
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
-      const int e = (tx + 1 + L::cx[q]) + W * (ty + 1 + L::cy[q]);
+      int e = (tx + 1 + L::cx[q]) + W * (ty + 1 + L::cy[q]);
+      bool cut = false;  // 2-D walls: the link leaves across a wall
+      if constexpr (WALLS && D == 2) {
+        cut = y + L::cy[q] < 0 || y + L::cy[q] >= g.ny;
+        if (cut) e = (tx + 1) + W * (ty + 1);
+      }
       S v = 0;
       if (L::cx[q]) v += L::cx[q] * xi[0][e];
       if (L::cy[q]) v += L::cy[q] * xi[1][e];
       if (D == 3 && L::cz[q]) v += L::cz[q] * xi[D - 1][e];
+      if (cut) v = -v;
       npart[1 - L::cz[q]] += S(L::w[q]) * v;
     }
   };
@@ -815,7 +826,7 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
       fold();
       if (live) a.noise[x + g.nx * y] = S(3) * a.amp * npart[1];
     }
-    if (a.mu && live) a.mu[x + g.nx * y] = prep_mu2(spsi, a.c, tx, ty);
+    if (a.mu && live) a.mu[x + g.nx * y] = prep_mu2<S, WALLS>(spsi, a.c, tx, ty, y, g.ny);
   } else {
     // Iteration p: xi(p) and psi(p) staged; N(p-1) and mu(p-1) emitted.
     const int plane = g.nx * g.ny;
@@ -1231,7 +1242,9 @@ __device__ __forceinline__ void combine_in(const StageArgs<S>& a, int s, S G, co
 // FV stage (Sec. V.B, Eq. fvft): G = Gamma . J + N with the node flux
 // J = -u phi + M Gamma mu(phi).  2-D: one plane, phi (halo 3), mu (halo 2)
 // and J (halo 1) in LDS, one phase each.
-template <typename S, int Q>
+// WALLS: walls across y; mu and Gamma mu read the centre's value across a
+// wall, Gamma . J minus the centre's J.
+template <typename S, int Q, bool WALLS = false>
 __device__ __forceinline__ void stage_fv2_body(const StageArgs<S>& a, int bx, int by) {
   using L = Lat<Q>;
   constexpr int D = L::D;
@@ -1257,7 +1270,9 @@ __device__ __forceinline__ void stage_fv2_body(const StageArgs<S>& a, int bx, in
   __syncthreads();
   for (int e = tid; e < WM * HM; e += NT) {
     const int i = e % WM, j = e / WM;
+    const int yr = y0 - 2 + j;  // global row of this mu point
     smu[e] = chem_pot<S, D>(a.c, [&](int dx, int dy, int) {
+      if (WALLS && (yr + dy < 0 || yr + dy >= g.ny)) return sphi[(i + 1) + WP * (j + 1)];
       return sphi[(i + 1 + dx) + WP * (j + 1 + dy)];
     });
   }
@@ -1265,10 +1280,13 @@ __device__ __forceinline__ void stage_fv2_body(const StageArgs<S>& a, int bx, in
   for (int e = tid; e < WJ * HJ; e += NT) {
     const int i = e % WJ, j = e / WJ;
     const int site = wrap_r(x0 - 1 + i, g.nx, near) + g.nx * wrap_r(y0 - 1 + j, g.ny, near);
+    const int yr = y0 - 1 + j;  // global row of this J point
     S gm[2] = {0, 0};
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
-      const S t = S(L::w[q]) * smu[(i + 1 + L::cx[q]) + WM * (j + 1 + L::cy[q])];
+      const bool cut = WALLS && (yr + L::cy[q] < 0 || yr + L::cy[q] >= g.ny);
+      const S t = S(L::w[q]) * (cut ? smu[(i + 1) + WM * (j + 1)]
+                                    : smu[(i + 1 + L::cx[q]) + WM * (j + 1 + L::cy[q])]);
       if (L::cx[q]) gm[0] += L::cx[q] * t;
       if (L::cy[q]) gm[1] += L::cy[q] * t;
     }
@@ -1280,11 +1298,12 @@ __device__ __forceinline__ void stage_fv2_body(const StageArgs<S>& a, int bx, in
   S G = 0;
 #pragma unroll
   for (int q = 1; q < Q; ++q) {
-    const int e = (tx + 1 + L::cx[q]) + WJ * (ty + 1 + L::cy[q]);
+    const bool cut = WALLS && (y + L::cy[q] < 0 || y + L::cy[q] >= g.ny);
+    const int e = cut ? (tx + 1) + WJ * (ty + 1) : (tx + 1 + L::cx[q]) + WJ * (ty + 1 + L::cy[q]);
     S v = 0;
     if (L::cx[q]) v += L::cx[q] * sJ[0][e];
     if (L::cy[q]) v += L::cy[q] * sJ[1][e];
-    G += S(L::w[q]) * v;
+    G += S(L::w[q]) * (cut ? -v : v);
   }
   if (live) combine_in(a, x + g.nx * y, S(3) * G + sv.noise, sv);
 }
@@ -1450,7 +1469,7 @@ __device__ __forceinline__ void stage_fv_body(const StageArgs<S>& a, int bx, int
   if constexpr (Lat<Q>::D == 3)
     stage_fv3_body<S, Q, WALLS>(a, bx, by, bz);
   else
-    stage_fv2_body<S, Q>(a, bx, by);
+    stage_fv2_body<S, Q, WALLS>(a, bx, by);
 }
 
 template <typename S, int Q, bool WALLS = false>
@@ -1544,18 +1563,10 @@ __global__ __launch_bounds__(kTX* kTY) void k_stage_fd(StageArgs<S> a, TileMap m
   if (tile_of(m, bx, by, bz)) stage_fd_body<S, Q>(a, bx, by, bz);
 }
 
-// ---------------------------------------------------------------------------
-// FV SMOL between walls across the last axis: per-site passes (one thread per
-// site, the k_mu grid) with the links that cross a wall removed, used on 2-D
-// lattices (3-D lattices take the WALLS variants of the z-marching kernels;
-// these passes also give the velocity observable its mu).  Per step:
-// mu(psi^n) for the force, the node noise xi into a buffer and N^n = Div xi;
-// per stage: mu(phi), the node flux J = -u phi + M Grad mu, and
-// G = Div J + N with the stage's combination.  Grad takes the centre's value
-// of a scalar beyond a wall and Div minus the centre's flux, so that
-// Div = -Grad^T (conservative, and the noise keeps the fluctuation-
-// dissipation balance).
-// ---------------------------------------------------------------------------
+// mu(phi) between walls across the last axis, one thread per site (the k_mu
+// grid): a neighbour beyond a wall reads the centre's value.  The velocity
+// observable takes its force from it; the step computes mu in the tiled
+// kernels.
 template <typename S, int Q>
 __global__ __launch_bounds__(kBX* kBY) void k_mu_w(Geom g, Coef<S> c, const S* __restrict__ phi,
                                                    S* __restrict__ mu) {
@@ -1570,94 +1581,6 @@ __global__ __launch_bounds__(kBX* kBY) void k_mu_w(Geom g, Coef<S> c, const S* _
   });
 }
 
-// Node noise xi_a = amp z_a (z: normals of slots 0 .. d-1, SMOL stream).
-template <typename S, int D>
-__global__ __launch_bounds__(256) void k_xi(Geom g, uint32_t step, uint32_t k0, uint32_t k1, S amp,
-                                            S* __restrict__ xi) {
-  const int s = blockIdx.x * 256 + threadIdx.x;
-  if (s >= g.N) return;
-  S zz[4];
-  if constexpr (D == 3)
-    Normal4<S>::gen(static_cast<uint32_t>(s), step, 0, kTagSMOL, k0, k1, zz);
-  else
-    Normal4<S>::gen2(static_cast<uint32_t>(s), step, 0, kTagSMOL, k0, k1, zz);
-#pragma unroll
-  for (int c = 0; c < D; ++c) xi[static_cast<size_t>(c) * g.N + s] = amp * zz[c];
-}
-
-// (1/c_s^2) sum_i w_i c_i . X(x + c_i), X beyond a wall taken as -X(x).
-template <typename S, int Q>
-__device__ __forceinline__ S div_w(const Geom& g, const Nbr& nb, int y, int z,
-                                   const S* __restrict__ X) {
-  using L = Lat<Q>;
-  constexpr int D = L::D;
-  const int s = nb.at(0, 0, 0);
-  S acc = 0;
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const bool out = beyond_wall<D>(g, y, z, L::cy[i], L::cz[i]);
-    const int t = out ? s : nb.at(L::cx[i], L::cy[i], L::cz[i]);
-    S v = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const int ca = a == 0 ? L::cx[i] : (a == 1 ? L::cy[i] : L::cz[i]);
-      if (ca) v += ca * X[static_cast<size_t>(a) * g.N + t];
-    }
-    acc += S(L::w[i]) * (out ? -v : v);
-  }
-  return S(3) * acc;
-}
-
-template <typename S, int Q>
-__global__ __launch_bounds__(kBX* kBY) void k_div_noise_w(Geom g, const S* __restrict__ xi,
-                                                          S* __restrict__ noise) {
-  const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= g.nx || y >= g.ny) return;
-  const Nbr nb(g, x, y, z);
-  noise[nb.at(0, 0, 0)] = div_w<S, Q>(g, nb, y, z, xi);
-}
-
-// J = -u phi + M (1/c_s^2) sum_i w_i c_i mu(x + c_i), mu beyond a wall taken
-// as mu(x).
-template <typename S, int Q>
-__global__ __launch_bounds__(kBX* kBY) void k_flux_w(StageArgs<S> a, const S* __restrict__ mu,
-                                                     S* __restrict__ J) {
-  using L = Lat<Q>;
-  constexpr int D = L::D;
-  const Geom& g = a.g;
-  const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= g.nx || y >= g.ny) return;
-  const Nbr nb(g, x, y, z);
-  const int s = nb.at(0, 0, 0);
-  S gm[3] = {0, 0, 0};
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const int t = beyond_wall<D>(g, y, z, L::cy[i], L::cz[i]) ? s : nb.at(L::cx[i], L::cy[i],
-                                                                        L::cz[i]);
-    const S v = S(L::w[i]) * mu[t];
-    if (L::cx[i]) gm[0] += L::cx[i] * v;
-    if (L::cy[i]) gm[1] += L::cy[i] * v;
-    if (L::cz[i]) gm[2] += L::cz[i] * v;
-  }
-  const S ph = a.phi[s];
-#pragma unroll
-  for (int c = 0; c < D; ++c)
-    J[static_cast<size_t>(c) * g.N + s] = -uval(a, c, s) * ph + a.c.M * (S(3) * gm[c]);
-}
-
-// G = Div J + N^n, combined as the stage's mode says.
-template <typename S, int Q>
-__global__ __launch_bounds__(kBX* kBY) void k_stage_w(StageArgs<S> a, const S* __restrict__ J) {
-  const Geom& g = a.g;
-  const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= g.nx || y >= g.ny) return;
-  const Nbr nb(g, x, y, z);
-  const int s = nb.at(0, 0, 0);
-  combine(a, s, div_w<S, Q>(g, nb, y, z, J) + a.noise[s]);
-}
 
 // ---------------------------------------------------------------------------
 // Initial state and observables (one thread per site, 1-D grid).

@@ -182,8 +182,8 @@ def test_sim_bytes_match_the_allocations(case, options):
 
 @pytest.mark.parametrize("lattice,shape", [(H.D2Q9, (37, 21, 1)), (H.D3Q19, (13, 11, 9))])
 def test_sim_bytes_match_the_allocations_with_walls(lattice, shape):
-    """The same with walls: a 2-D lattice takes the per-site passes' flux
-    buffer, a 3-D lattice nothing more."""
+    """The same with walls (the wall rules live in the kernels; no buffer is
+    added)."""
     from paper_1104_0078_amd import lbl
     c = H.config(lattice=lattice, smol=H.FV, shape=shape, walls=1,
                  u_wall=((0.01, 0, 0), (-0.01, 0, 0)))
