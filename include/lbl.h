@@ -124,8 +124,9 @@ typedef struct lbl_params {
  *    bounce-back, with the term 2 w_i rho c_i.U / c_s^2 of a moving wall);
  *    the SMOL stencils drop every link that crosses a wall, so no order
  *    parameter flows through it and the fluctuation-dissipation balance of the
- *    noise is kept.  FV variant, force PSI_GRAD_MU, single simulations only
- *    (a pool refuses such a request); the SMOL runs as per-site passes. */
+ *    noise is kept.  FV variant, force PSI_GRAD_MU; single simulations and
+ *    pool requests (a pool batches requests with walls in groups of their
+ *    own). */
 enum lbl_walls { LBL_WALLS_PERIODIC = 0, LBL_WALLS_LAST = 1 };
 
 /* Force density of the order parameter on the fluid (full coupling):

@@ -936,6 +936,8 @@ struct Impl {
     r.u0 = S(s->p.u_imposed[0]);
     r.u1 = S(s->p.u_imposed[1]);
     r.u2 = S(Lat<Q>::D == 3 ? s->p.u_imposed[2] : 0.0);
+    for (int k = 0; k < 2; ++k)
+      for (int c = 0; c < 3; ++c) r.uw[k][c] = S(s->p.u_wall[k][c]);
     r.k0 = s->k0;
     r.k1 = s->k1;
     return r;
@@ -970,7 +972,12 @@ struct Impl {
   // caller into a graph).
   static int enqueue_group(hipStream_t stream, const void* reps_dev, RepState* states, int nrep,
                            const Work* wlb, int nlb, int lb_lw, const Work* wtile, int ntile,
-                           int rk, bool ghost, int nt, int64_t nsteps) {
+                           int rk, bool ghost, int nt, bool walls, int64_t nsteps) {
+    if constexpr (SMOL == kFV)
+      if (walls)
+        return enqueue_walls(stream, reps_dev, states, nrep, wlb, nlb, lb_lw, wtile, ntile, rk,
+                             ghost, nt, nsteps);
+    if (walls) return LBL_E_INVAL;
     const Replica<S>* reps = static_cast<const Replica<S>*>(reps_dev);
     const dim3 bsite(kSiteBlock), btile(kTX, kTY);
     for (int64_t k = 0; k < nsteps; ++k) {
@@ -989,6 +996,38 @@ struct Impl {
         kb_uend<S, DEV, Q, SMOL, false><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw, rk);
       for (int st = 0; st < rk; ++st)
         kb_stage<S, Q, SMOL><<<ntile, btile, 0, stream>>>(reps, states, wtile, st, rk);
+      kb_advance<S><<<(nrep + 255) / 256, 256, 0, stream>>>(reps, states, nrep);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return LBL_E_DEVICE;
+    }
+    return LBL_OK;
+  }
+
+  // The same for a group whose replicas have walls (FV only).
+  static int enqueue_walls(hipStream_t stream, const void* reps_dev, RepState* states, int nrep,
+                           const Work* wlb, int nlb, int lb_lw, const Work* wtile, int ntile,
+                           int rk, bool ghost, int nt, int64_t nsteps) {
+    const Replica<S>* reps = static_cast<const Replica<S>*>(reps_dev);
+    const dim3 bsite(kSiteBlock), btile(kTX, kTY);
+    for (int64_t k = 0; k < nsteps; ++k) {
+      kb_prep<S, Q, SMOL, true><<<ntile, btile, 0, stream>>>(reps, states, wtile);
+      if (ghost)
+        kb_lb<S, DEV, Q, SMOL, true, false, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
+                                                                               lb_lw);
+      else if (nt)
+        kb_lb<S, DEV, Q, SMOL, false, true, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
+                                                                               lb_lw);
+      else
+        kb_lb<S, DEV, Q, SMOL, false, false, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
+                                                                                lb_lw);
+      if (rk > 1 && nt)
+        kb_uend<S, DEV, Q, SMOL, true, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw,
+                                                                          rk);
+      else if (rk > 1)
+        kb_uend<S, DEV, Q, SMOL, false, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
+                                                                           lb_lw, rk);
+      for (int st = 0; st < rk; ++st)
+        kb_stage<S, Q, SMOL, true><<<ntile, btile, 0, stream>>>(reps, states, wtile, st, rk);
       kb_advance<S><<<(nrep + 255) / 256, 256, 0, stream>>>(reps, states, nrep);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return LBL_E_DEVICE;
@@ -1070,7 +1109,7 @@ using ObsFn = int (*)(lbl_sim*, int, double*);
 using TablesFn = void (*)(const std::vector<lbl_sim*>&, int, int, void*, std::vector<Work>&,
                           std::vector<Work>&);
 using EnqueueFn = int (*)(hipStream_t, const void*, RepState*, int, const Work*, int, int,
-                          const Work*, int, int, bool, int, int64_t);
+                          const Work*, int, int, bool, int, bool, int64_t);
 
 using ChunkFn = int (*)(lbl_sim*);
 
@@ -1308,13 +1347,14 @@ struct PoolReq {
 };
 
 struct GroupKey {
-  int precision, lattice, smol, rk, ghost;
+  int precision, lattice, smol, rk, ghost, walls;
   bool operator<(const GroupKey& o) const {
     if (precision != o.precision) return precision < o.precision;
     if (lattice != o.lattice) return lattice < o.lattice;
     if (smol != o.smol) return smol < o.smol;
     if (rk != o.rk) return rk < o.rk;
-    return ghost < o.ghost;
+    if (ghost != o.ghost) return ghost < o.ghost;
+    return walls < o.walls;
   }
 };
 
@@ -1337,7 +1377,8 @@ struct Group {
 };
 
 GroupKey key_of(const lbl_params& p) {
-  return GroupKey{p.precision, p.lattice, p.smol, p.rk_stages, p.omega_ghost != 1.0 ? 1 : 0};
+  return GroupKey{p.precision, p.lattice, p.smol, p.rk_stages, p.omega_ghost != 1.0 ? 1 : 0,
+                  p.walls == LBL_WALLS_LAST ? 1 : 0};
 }
 
 }  // namespace
@@ -1559,7 +1600,7 @@ int run_group(lbl_pool* pl, Group& g, int64_t max_steps) {
     const int rc = t.enqueue(ls, g.reps.ptr, static_cast<RepState*>(g.states.ptr), n,
                              static_cast<const Work*>(g.wlb.ptr), g.nlb, g.lb_lw,
                              static_cast<const Work*>(g.wtile.ptr), g.ntile, g.key.rk,
-                             g.key.ghost != 0, g.nt, steps);
+                             g.key.ghost != 0, g.nt, g.key.walls != 0, steps);
     e = hipStreamEndCapture(ls, &graph);
     if (rc || e != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -2008,8 +2049,6 @@ int lbl_pool_submit(lbl_pool* pl, const lbl_params* params, const lbl_init* init
     return pool_fail(pl, LBL_E_INVAL, "the stress-divergence force runs in single simulations only");
   if (params->sample_full_k != 0)
     return pool_fail(pl, LBL_E_INVAL, "pool requests report the final state (sample_full_k 0)");
-  if (params->walls != LBL_WALLS_PERIODIC)
-    return pool_fail(pl, LBL_E_INVAL, "pool requests are periodic (walls 0)");
   PoolReq r;
   r.id = pl->next_id++;
   r.p = *params;

@@ -30,6 +30,7 @@ struct Replica {
   S* noise;
   S rho0, gamma_s, gamma_b, gamma_g, sigma_s, sigma_b, sigma_g, amp;
   S u0, u1, u2;
+  S uw[2][3];  // walls: velocities of the lower and upper wall
   uint32_t k0, k1;
 };
 
@@ -46,7 +47,8 @@ struct Work {
   int bx, by, bz;
 };
 
-template <typename S, int Q, int SMOL>
+// WALLS: every replica of the launch has walls across the last axis (FV).
+template <typename S, int Q, int SMOL, bool WALLS = false>
 __global__ __launch_bounds__(kTX* kTY) void kb_prep(const Replica<S>* __restrict__ reps,
                                                    const RepState* __restrict__ st,
                                                    const Work* __restrict__ work) {
@@ -67,7 +69,7 @@ __global__ __launch_bounds__(kTX* kTY) void kb_prep(const Replica<S>* __restrict
   a.mu = r.coupling == kCplFull ? r.mu : nullptr;
   if (!a.noise && !a.mu) return;
   if constexpr (SMOL == kFV)
-    prep_fv_body<S, Q>(a, w.bx, w.by, w.bz);
+    prep_fv_body<S, Q, WALLS>(a, w.bx, w.by, w.bz);
   else
     prep_fd_body<S, Q>(a, w.bx, w.by, w.bz);
 }
@@ -79,7 +81,7 @@ __device__ __forceinline__ void lb_tile_site(const Work& w, int lw, int& x, int&
   y = w.by * (kSiteBlock >> lw) + (threadIdx.x >> lw);
 }
 
-template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool NT>
+template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool NT, bool WALLS = false>
 __global__ __launch_bounds__(kSiteBlock) void kb_lb(const Replica<S>* __restrict__ reps,
                                                       const RepState* __restrict__ st,
                                                       const Work* __restrict__ work, int lw) {
@@ -108,15 +110,17 @@ __global__ __launch_bounds__(kSiteBlock) void kb_lb(const Replica<S>* __restrict
   a.Fext = nullptr;
   a.noise = r.noise_on;
   a.nt = NT;
+  for (int k = 0; k < 2; ++k)
+    for (int c = 0; c < 3; ++c) a.uw[k][c] = r.uw[k][c];
   int x, y;
   lb_tile_site(w, lw, x, y);
-  if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, GHOST, true, NT>(a, x, y, w.bz);
+  if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, GHOST, true, NT, WALLS>(a, x, y, w.bz);
 }
 
 // Velocity of the streamed populations, (jbar^{n+1} + F^n/2)/rho^{n+1}, for
 // the Runge-Kutta stages at t_{n+1}: the LB body without collision, pulling
 // the populations the step just wrote.
-template <typename S, bool DEV, int Q, int SMOL, bool NT>
+template <typename S, bool DEV, int Q, int SMOL, bool NT, bool WALLS = false>
 __global__ __launch_bounds__(kSiteBlock) void kb_uend(const Replica<S>* __restrict__ reps,
                                                      const RepState* __restrict__ st,
                                                      const Work* __restrict__ work, int lw, int rk) {
@@ -136,14 +140,16 @@ __global__ __launch_bounds__(kSiteBlock) void kb_uend(const Replica<S>* __restri
   a.Fext = nullptr;
   a.noise = 0;
   a.nt = NT;
+  for (int k = 0; k < 2; ++k)
+    for (int c = 0; c < 3; ++c) a.uw[k][c] = r.uw[k][c];
   int x, y;
   lb_tile_site(w, lw, x, y);
-  if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, false, false, NT>(a, x, y, w.bz);
+  if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, false, false, NT, WALLS>(a, x, y, w.bz);
 }
 
 // Stage `st` of `ns` (ns = 1, 2 or 4), with the same combinations as the
 // single-simulation path.
-template <typename S, int Q, int SMOL>
+template <typename S, int Q, int SMOL, bool WALLS = false>
 __global__ __launch_bounds__(kTX* kTY) void kb_stage(const Replica<S>* __restrict__ reps,
                                                     const RepState* __restrict__ state,
                                                     const Work* __restrict__ work, int st,
@@ -179,7 +185,7 @@ __global__ __launch_bounds__(kTX* kTY) void kb_stage(const Replica<S>* __restric
   }
   a.out = a.last ? r.psi[1 - rs.pcur] : r.phi[st & 1];
   if constexpr (SMOL == kFV)
-    stage_fv_body<S, Q>(a, w.bx, w.by, w.bz);
+    stage_fv_body<S, Q, WALLS>(a, w.bx, w.by, w.bz);
   else
     stage_fd_body<S, Q>(a, w.bx, w.by, w.bz);
 }

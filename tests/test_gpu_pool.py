@@ -52,6 +52,13 @@ MIX = [
               init=1), 14),
     (H.config(lattice=H.D2Q9, smol=H.FV, precision=H.FP32DEV, shape=(36, 40, 1), seed=22,
               rk=4), 16),
+    # walls across the last axis, sliding; batched in groups of their own
+    (H.config(lattice=H.D3Q19, smol=H.FV, shape=(20, 14, 12), seed=23, a=-0.04, b=0.04,
+              init=1, walls=1, u_wall=((0.02, -0.01, 0), (-0.015, 0.01, 0))), 18),
+    (H.config(lattice=H.D2Q9, smol=H.FV, shape=(36, 28, 1), seed=24, walls=1,
+              u_wall=((0.02, 0, 0), (-0.01, 0, 0))), 21),
+    (H.config(lattice=H.D3Q15, smol=H.FV, precision=H.FP32DEV, shape=(14, 12, 10), seed=25,
+              rk=4, walls=1, u_wall=((0.01, 0.01, 0), (0, 0, 0))), 12),
 ]
 
 
