@@ -180,3 +180,45 @@ def test_walls_static_entry_point_matches_allocating_path():
     # the re-entry passes the state through the observed (streamed) form,
     # which rounds (f + t) - t once at the wall layers
     assert H.rel_err(f_s, f8) <= 1e-14 and H.rel_err(p_s, p8) <= 1e-14
+
+
+@pytest.mark.parametrize("lattice,shape", [(H.D2Q9, (13, 17, 1)), (H.D3Q19, (7, 7, 11))])
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
+def test_walls_fluctuation_profile(lattice, shape, precision):
+    """Thermal fluctuations between walls: the SMOL alone (B = 0, no flow,
+    A = 0.04, K = 0.05, M = 0.1, kT = 1e-5) from psi = 0.  Per layer parallel
+    to the walls, the variance of psi - mean(psi) over 6000 samples (every
+    25 steps after 20 000) against the exact stationary covariance of the
+    discrete frozen-noise Heun scheme built from the oracle's operators with
+    walls (tests/theory.stationary_covariance, pinned to the closed form on
+    periodic lattices and to the Boltzmann limit with walls).  The layers
+    next to the walls fluctuate ~30% more than the bulk; each layer within
+    max(2%, 3 SE), SE from 30 batch means."""
+    from paper_1104_0078_amd import lbl
+    from tests import theory as T
+    c = H.config(lattice=lattice, smol=H.FV, coupling=H.SMOL_ONLY, precision=precision,
+                 shape=shape, a=0.04, b=0.0, kappa=0.05, M=0.1, kT=1e-5, walls=1, psi_std=0.0)
+    p = H.oracle_params(c)
+    L, Hm, Dv = T.smol_linear_operators(p)
+    C = T.stationary_covariance(L, Hm, Dv, 1e-5, 0.1)
+    d = 2 if lattice == H.D2Q9 else 3
+    nl = shape[d - 1]
+    want = np.diag(C).reshape(nl, -1).mean(axis=1)
+    print("walls fluctuation case:", lattice, shape, "precision", precision, flush=True)
+    nsamp, every = 6000, 25
+    series = np.empty((nsamp, nl))
+    with lbl.Sim(H.lbl_params(c), lbl.make_init(psi_std=0.0)) as sim:
+        sim.step(20000)
+        for k in range(nsamp):
+            sim.step(every)
+            psi = sim.observe(lbl.LBL_OBS_PSI)
+            series[k] = ((psi - psi.mean()) ** 2).reshape(nl, -1).mean(axis=1)
+    nb = 30
+    bm = series[:nsamp // nb * nb].reshape(nb, -1, nl).mean(axis=1)
+    got, se = bm.mean(axis=0), bm.std(axis=0, ddof=1) / np.sqrt(nb)
+    ratio, rse = got / want, se / want
+    print("  layer variance / prediction:", np.round(ratio, 4).tolist(), flush=True)
+    print("  prediction wall / middle layer: %.4f, measured %.4f" % (
+        want[0] / want[nl // 2], got[0] / got[nl // 2]), flush=True)
+    assert np.all(np.abs(ratio - 1) <= np.maximum(0.02, 3 * rse))
+    assert want[0] > 1.2 * want[nl // 2]

@@ -148,3 +148,55 @@ def test_wall_energy_dissipation(lattice, shape):
     E = np.array(E)
     assert np.all(np.diff(E) < 0)
     assert E[-1] < 0.7 * E[0]
+
+
+@pytest.mark.parametrize("lattice,shape", [(O.D2Q9, (9, 11, 1)), (O.D3Q19, (5, 5, 7)),
+                                           (O.D3Q15, (5, 5, 7))])
+def test_wall_noise_keeps_the_boltzmann_distribution(lattice, shape):
+    """Fluctuation-dissipation balance with walls: the stationary covariance
+    of the oracle's SMOL between walls (B = 0, no flow, Heun with frozen
+    noise) tends to the Boltzmann covariance kT H^-1 of the discrete free
+    energy, H = A - K L_SO (on the fluctuations of zero total), as the time
+    step shrinks (M -> 0 at fixed A, K), with the O(M^2) error of the
+    discrete-time scheme.  A wall rule that broke Div = -Grad^T or the
+    symmetry of L_SO would leave an O(1) deviation."""
+    from tests import theory as T
+    devs = []
+    for M in (0.1, 0.01):
+        p = O.make_params(lattice=lattice, smol=O.FV, coupling=O.SMOL_ONLY, shape=shape, a=0.04,
+                          b=0.0, kappa=0.05, M=M, kT=1e-5, walls=1)
+        L, H, Dv = T.smol_linear_operators(p)
+        C = T.stationary_covariance(L, H, Dv, 1e-5, M)
+        N = O.nsites(p)
+        P = np.eye(N) - np.ones((N, N)) / N
+        Cb = 1e-5 * P @ np.linalg.pinv(P @ H @ P, rcond=1e-10, hermitian=True) @ P
+        devs.append(np.abs(C - Cb).max() / np.abs(Cb).max())
+    assert devs[0] < 1e-3 and devs[1] < 1e-5
+    assert 50 < devs[0] / devs[1] < 200  # second order in the step
+    # the walls shape the profile: the end layers fluctuate more than the bulk
+    d = O.d_of(p)
+    per = np.diag(C).reshape(shape[d - 1], -1).mean(axis=1)
+    assert per[0] > 1.2 * per[len(per) // 2] and abs(per[0] - per[-1]) < 1e-12 * per[0]
+
+
+@pytest.mark.parametrize("lattice,shape", [(O.D2Q9, (9, 11, 1)), (O.D3Q19, (5, 5, 7))])
+def test_stationary_covariance_matches_the_discrete_closed_form(lattice, shape):
+    """The covariance machinery on a periodic lattice at a finite step
+    (M = 0.1) against the exact discrete-time static structure factor
+    2 kT M (-L_out) |Phi(z)|^2 / (1 - |R(z)|^2) of each Fourier mode (odd
+    sides: only q = 0 is conserved)."""
+    from tests import theory as T
+    p = O.make_params(lattice=lattice, smol=O.FV, coupling=O.SMOL_ONLY, shape=shape, a=0.04,
+                      b=0.0, kappa=0.05, M=0.1, kT=1e-5)
+    L, H, Dv = T.smol_linear_operators(p)
+    C = T.stationary_covariance(L, H, Dv, 1e-5, 0.1)
+    nx, ny, nz = shape
+    d = O.d_of(p)
+    idx = np.arange(O.nsites(p))
+    xyz = [idx % nx, (idx // nx) % ny, idx // (nx * ny)]
+    for m in [(1, 0, 0), (0, 2, 0), (1, 1, 0), (2, 3, 0)] + ([(1, 0, 2), (2, 1, 3)] if d == 3 else []):
+        q = np.array([2 * np.pi * m[k] / shape[k] for k in range(3)])[:d]
+        v = np.exp(1j * sum(q[k] * xyz[k] for k in range(d)))
+        got = np.real(np.conj(v) @ C @ v) / O.nsites(p)
+        want = T.smol_static_sk(q.reshape(d, 1), lattice, O.FV, 0.1, 0.04, 0.05, 1e-5)[0]
+        assert abs(got / want - 1) < 1e-10, (m, got, want)

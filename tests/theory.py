@@ -136,3 +136,51 @@ def height_gain(h, l):
     gain tends to 1."""
     h = np.asarray(h, dtype=float)
     return float(np.mean(interp_gain(h - np.floor(h), l)))
+
+
+def smol_linear_operators(p):
+    """Matrices of the oracle's SMOL with B = 0 and no flow: the right-hand
+    side L (G(phi) = L phi + N), the free-energy Hessian H = A - K L_SO and
+    the divergence Dv that maps node noise to N, each built column by column
+    from unit fields (so they carry whatever boundary rules the oracle has)."""
+    import oracle as O
+    N, d = O.nsites(p), O.d_of(p)
+    L = np.zeros((N, N))
+    H = np.zeros((N, N))
+    Dv = np.zeros((N, d * N))
+    zu, zn = np.zeros((d, N)), np.zeros(N)
+    for k in range(N):
+        e = np.zeros(N)
+        e[k] = 1.0
+        L[:, k] = O.smol_rhs(p, e, zu, zn)
+        H[:, k] = p.a * e - p.kappa * O.laplacian(p, e)
+    for k in range(d * N):
+        e = np.zeros(d * N)
+        e[k] = 1.0
+        Dv[:, k] = O.divergence(p, e.reshape(d, N))
+    return L, H, Dv
+
+
+def stationary_covariance(L, H, Dv, kT, M, stages=2):
+    """Stationary covariance of psi - mean(psi) under the frozen-noise
+    Runge-Kutta step psi' = R(L) psi + Phi(L) N, N of covariance
+    2 kT M Dv Dv^T (the node noise of amplitude sqrt(2 kT M)), with R and Phi
+    the stage polynomials of rk_poly.  It solves C = R C R^T + Phi S Phi^T.
+    With L = M Dv Grad H, H symmetric positive definite and Dv Grad
+    symmetric, L is symmetric in the metric of H: in the basis
+    H^(1/2) (eigenvectors U of H^(1/2) L H^(-1/2)) the equation is diagonal,
+    C'_ij = Q'_ij / (1 - r_i r_j); the conserved uniform mode (r = 1) carries
+    no noise and is left out."""
+    w, V = np.linalg.eigh((H + H.T) / 2)
+    S = V @ np.diag(np.sqrt(w)) @ V.T
+    Si = V @ np.diag(1 / np.sqrt(w)) @ V.T
+    Lh = S @ L @ Si
+    lam, U = np.linalg.eigh((Lh + Lh.T) / 2)
+    r, ph = rk_poly(lam, stages)
+    Q = U.T @ S @ (2 * kT * M * Dv @ Dv.T) @ S @ U
+    Q = ph[:, None] * Q * ph[None, :]
+    den = 1 - r[:, None] * r[None, :]
+    cons = np.abs(lam) < 1e-12 * np.abs(lam).max()
+    C = np.where(cons[:, None] | cons[None, :], 0.0, Q / np.where(cons[:, None] | cons[None, :],
+                                                                   1.0, den))
+    return Si @ U @ C @ U.T @ Si
