@@ -718,7 +718,7 @@ struct Impl {
     // Walls (an FV option) run the tiled SMOL kernels with the wall rules.
     constexpr bool kTiledWalls = SMOL == kFV;
     const bool walls_tiled = walls && kTiledWalls;
-    const bool split = !walls && prep_noise && s->overlap == 2;
+    const bool split = prep_noise && s->overlap == 2;
     if (split) {
       if (int rc = ensure_aux(s)) return rc;
       if (int rc = hip_check(s, hipEventRecord(s->ev_fork, s->stream), "fork")) return rc;
@@ -765,7 +765,7 @@ struct Impl {
     // and the first stage (at t_n) are independent: with `overlap` the first
     // stage runs on the second stream while the velocity pass runs here.
     const bool uend = cpl == LBL_FULL && s->p.rk_stages > 1;
-    const bool fork = uend && s->overlap == 1 && !walls;
+    const bool fork = uend && s->overlap == 1;
     if (fork) {
       if (int rc = ensure_aux(s)) return rc;
       if (int rc = hip_check(s, hipEventRecord(s->ev_fork, s->stream), "fork")) return rc;
