@@ -854,7 +854,9 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
         so.template push<W>(spsi.v + (tx + 1) + W * (ty + 1));
         if (emit)
           a.mu[x + g.nx * (y + g.ny * (p - 1))] =
-              WALLS ? so.mu_walled(a.c, p - 1 == 0, p - 1 == g.nz - 1) : so.mu(a.c);
+              (WALLS && (p - 1 == 0 || p - 1 == g.nz - 1))
+                  ? so.mu_walled(a.c, p - 1 == 0, p - 1 == g.nz - 1)
+                  : so.mu(a.c);
         so.roll();
       }
       __syncthreads();
@@ -1408,8 +1410,9 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
       const int e = tid + k * NT;
       so[k].template push<WP>(sphi + (e % WM + 1) + WP * (e / WM + 1));
       if (do_mu)
-        smu[mslot][e] = WALLS ? so[k].mu_walled(a.c, p - 1 == 0, p - 1 == g.nz - 1)
-                              : so[k].mu(a.c);
+        smu[mslot][e] = (WALLS && (p - 1 == 0 || p - 1 == g.nz - 1))
+                            ? so[k].mu_walled(a.c, p - 1 == 0, p - 1 == g.nz - 1)
+                            : so[k].mu(a.c);
     }
     __syncthreads();
     // J(p-2) from mu(p-3), mu(p-2), mu(p-1).
@@ -1420,14 +1423,26 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
         if (!jon[k]) continue;
         const int e = tid + k * NT;
         S gm[3] = {0, 0, 0};
+        if (WALLS && (jlo || jhi)) {
+          // an end plane: the links across the wall read the centre's mu
 #pragma unroll
-        for (int q = 1; q < Q; ++q) {
-          const bool cut = (jlo && L::cz[q] < 0) || (jhi && L::cz[q] > 0);
-          const S t = S(L::w[q]) * (cut ? smu[ring(p - 2, 3)][e]
-                                        : smu[ring(p - 2 + L::cz[q], 3)][e + L::cx[q] + WM * L::cy[q]]);
-          if (L::cx[q]) gm[0] += L::cx[q] * t;
-          if (L::cy[q]) gm[1] += L::cy[q] * t;
-          if (L::cz[q]) gm[2] += L::cz[q] * t;
+          for (int q = 1; q < Q; ++q) {
+            const bool cut = (jlo && L::cz[q] < 0) || (jhi && L::cz[q] > 0);
+            const S t = S(L::w[q]) * (cut ? smu[ring(p - 2, 3)][e]
+                                          : smu[ring(p - 2 + L::cz[q], 3)]
+                                               [e + L::cx[q] + WM * L::cy[q]]);
+            if (L::cx[q]) gm[0] += L::cx[q] * t;
+            if (L::cy[q]) gm[1] += L::cy[q] * t;
+            if (L::cz[q]) gm[2] += L::cz[q] * t;
+          }
+        } else {
+#pragma unroll
+          for (int q = 1; q < Q; ++q) {
+            const S t = S(L::w[q]) * smu[ring(p - 2 + L::cz[q], 3)][e + L::cx[q] + WM * L::cy[q]];
+            if (L::cx[q]) gm[0] += L::cx[q] * t;
+            if (L::cy[q]) gm[1] += L::cy[q] * t;
+            if (L::cz[q]) gm[2] += L::cz[q] * t;
+          }
         }
         const S ph = so[k].c[0];  // phi(p-2)
 #pragma unroll
