@@ -450,6 +450,9 @@ int lbl_pool_destroy(lbl_pool *pool);
  * the last call's contents: calls that overlap in time on one device race,
  * so order them on one stream.  The first call on a device resolves the
  * workspace's address (hipGetSymbolAddress); make it outside graph capture.
+ * After that a call only enqueues kernels on `stream` (the workspace is
+ * cleared by a kernel, not a memset), so it can be captured into a graph and
+ * replayed; each replay repeats the captured step0 and nsteps.
  * Errors: LBL_E_INVAL (NULL pointers, nsteps < 0, invalid parameters as for
  * lbl_create, fd_noise = LBL_FDNOISE_FOURIER, sample_every or sample_full_k
  * not 0), LBL_E_NOMEM (the lattice's buffers, lbl_sim_bytes(params) plus

@@ -107,3 +107,44 @@ def test_static_refusals():
     assert lbl.lbl_step_static(small, 0, 0, -1, pop.data_ptr(), pop.data_ptr()) == \
         lbl.LBL_E_INVAL
     assert lbl.lbl_step_static(small, 0, 0, 1, 0, pop.data_ptr()) == lbl.LBL_E_INVAL
+
+
+def test_static_call_captured_in_a_graph():
+    """The entry point that allocates nothing may be captured: one call
+    (6 steps of a 13x11x9 D3Q19 FV two-phase state between sliding walls)
+    recorded into a HIP graph and replayed three times, each from the same
+    input state reset eagerly, with other eager work between the replays;
+    every replay equals the eager call bit for bit."""
+    import torch
+    from paper_1104_0078_amd import lbl
+    c = H.config(lattice=H.D3Q19, smol=H.FV, shape=(13, 11, 9), a=-0.04, b=0.04, kappa=0.05,
+                 init=1, kT=1e-5, seed=78, walls=1, u_wall=((0.01, 0, 0), (-0.01, 0, 0)))
+    params = H.lbl_params(c)
+    f0, p0 = _state(c, 3)
+    pop_a = torch.from_numpy(f0.reshape(-1).copy()).cuda()
+    psi_a = torch.from_numpy(p0.copy()).cuda()
+    stream = torch.cuda.Stream()
+    pop, psi = pop_a.clone(), psi_a.clone()
+    torch.cuda.synchronize()
+    # eager call (also resolves the workspace address before any capture)
+    assert lbl.lbl_step_static(params, stream.cuda_stream, 3, 6, pop.data_ptr(),
+                               psi.data_ptr()) == lbl.LBL_OK
+    stream.synchronize()
+    want_f, want_p = pop.cpu().numpy(), psi.cpu().numpy()
+    pop.copy_(pop_a)
+    psi.copy_(psi_a)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        rc = lbl.lbl_step_static(params, stream.cuda_stream, 3, 6, pop.data_ptr(),
+                                 psi.data_ptr())
+    assert rc == lbl.LBL_OK, lbl.lbl_last_error(None)
+    for k in range(3):
+        pop.copy_(pop_a)
+        psi.copy_(psi_a)
+        torch.randn(1000, device="cuda").sum().item()
+        graph.replay()
+        torch.cuda.synchronize()
+        print("graph replay %d" % k, flush=True)
+        np.testing.assert_array_equal(pop.cpu().numpy(), want_f)
+        np.testing.assert_array_equal(psi.cpu().numpy(), want_p)
