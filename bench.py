@@ -457,6 +457,35 @@ def run_served(lbl, torch, rate, seconds, budget_gb=200, tick=200, seed=1234):
                    "FP32/FP64 50/50; steps log-uniform [500, 20000]; S(k) and totals returned"}
 
 
+def leg_error_vs_oracle(lbl, w, shape=None, nsteps=20):
+    """Error against the FP64 oracle of a leg's kind of run (lattice, variant,
+    options, parameters, initial state and seed as in the leg) on a smaller
+    lattice: `nsteps` steps on the GPU in FP64 and in FP32-deviation storage,
+    every site compared with the oracle's run of the same steps."""
+    import numpy as np
+    import oracle as O
+    if shape is None:
+        shape = (61, 47, 1) if w["lattice"] == 9 else (41, 37, 33)
+    uw = w.get("u_wall", ((0, 0, 0), (0, 0, 0)))
+    op = O.make_params(lattice=w["lattice"], smol=w["smol"], shape=shape, eta=w["eta"], M=w["M"],
+                       a=w["a"], b=w["b"], kappa=w["kappa"], kT=w["kT"], seed=1234,
+                       fd_noise=w.get("fd_noise", 0), force_form=w.get("force_form", 0),
+                       walls=w.get("walls", 0), u_wall=tuple(uw[0]) + tuple(uw[1]))
+    f, psi = O.init(op, w["init"], w["psi_std"])
+    O.run(op, f, psi, 0, nsteps)
+    out = {"shape": list(shape), "steps": nsteps,
+           "measure": "max |gpu - oracle| / max |oracle| over all sites",
+           "bound": {"fp64": 1e-12, "fp32dev": 1e-5}}
+    for prec, name in ((0, "fp64"), (1, "fp32dev")):
+        p = make_sim_params(lbl, dict(w, shape=shape), prec)
+        with lbl.Sim(p, lbl.make_init(kind=w["init"], psi_std=w["psi_std"])) as sim:
+            sim.step(nsteps)
+            fg, pg = sim.observe(lbl.LBL_OBS_POP), sim.observe(lbl.LBL_OBS_PSI)
+        out[name] = {"psi": float(np.abs(pg - psi).max() / np.abs(psi).max()),
+                     "pop": float(np.abs(np.reshape(fg, f.shape) - f).max() / np.abs(f).max())}
+    return out
+
+
 def pool_error_vs_oracle(lbl, kinds, nsteps=100):
     """Error against the FP64 oracle of pooled requests: one request of each
     kind (lattice, variant, phase, storage) at the kind's smallest side runs
@@ -660,7 +689,8 @@ def main():
             legs[name] = {"value": round(rf["mlups"], 2), "unit": "MLUPS",
                           "ms_per_step": round(rf["ms_per_step"], 4),
                           "kernels_ms_per_step": {t[0]: round(t[2] / min(args.steps, 30), 4)
-                                                  for t in rf["ktimes"]}}
+                                                  for t in rf["ktimes"]},
+                          "error_vs_oracle": leg_error_vs_oracle(lbl, wf)}
         out["fd_noise_same_lattice"] = legs
         print("fd noise legs done: link %.1f, Fourier %.1f MLUPS" % (
             legs["link"]["value"], legs["fourier"]["value"]), file=sys.stderr, flush=True)
@@ -672,7 +702,8 @@ def main():
         out["stress_force_same_workload"] = {
             "value": round(rs_["mlups"], 2), "unit": "MLUPS",
             "ms_per_step": round(rs_["ms_per_step"], 4),
-            "kernels_ms_per_step": {t[0]: round(t[2] / nst, 4) for t in rs_["ktimes"]}}
+            "kernels_ms_per_step": {t[0]: round(t[2] / nst, 4) for t in rs_["ktimes"]},
+            "error_vs_oracle": leg_error_vs_oracle(lbl, dict(w, force_form=1))}
         print("stress force leg done: %.1f MLUPS" % rs_["mlups"], file=sys.stderr, flush=True)
     if not args.no_walls and w["smol"] == 1:
         # The same workload between walls across the last axis sliding at
@@ -684,7 +715,8 @@ def main():
         out["walls_same_workload"] = {
             "value": round(rw["mlups"], 2), "unit": "MLUPS",
             "ms_per_step": round(rw["ms_per_step"], 4),
-            "kernels_ms_per_step": {t[0]: round(t[2] / nw, 4) for t in rw["ktimes"]}}
+            "kernels_ms_per_step": {t[0]: round(t[2] / nw, 4) for t in rw["ktimes"]},
+            "error_vs_oracle": leg_error_vs_oracle(lbl, ww)}
         print("walls leg done: %.1f MLUPS" % rw["mlups"], file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = {}
