@@ -222,3 +222,32 @@ def test_walls_fluctuation_profile(lattice, shape, precision):
         want[0] / want[nl // 2], got[0] / got[nl // 2]), flush=True)
     assert np.all(np.abs(ratio - 1) <= np.maximum(0.02, 3 * rse))
     assert want[0] > 1.2 * want[nl // 2]
+
+
+@pytest.mark.parametrize("lattice,shape", [(H.D2Q9, (16, 24, 1)), (H.D3Q19, (8, 8, 16))])
+def test_walls_lb_equipartition(lattice, shape):
+    """The fluctuating fluid between static walls (LB alone, kT = 1e-5, from
+    rest): per layer and velocity component, <u_a^2> rho0 / kT = 1 within
+    max(2%, 3 SE) (4000 samples every 20 steps after 5000; SE from 20 batch
+    means).  Halfway bounce-back permutes a site's populations between
+    directions of equal weight, so it keeps the equilibrium fluctuations,
+    including those of the layers next to the walls (measured 0.99-1.01)."""
+    from paper_1104_0078_amd import lbl
+    c = H.config(lattice=lattice, smol=H.FV, coupling=H.LB_ONLY, shape=shape, kT=1e-5, eta=0.1,
+                 walls=1, psi_std=0.0)
+    d = 2 if lattice == H.D2Q9 else 3
+    nl = shape[d - 1]
+    nsamp = 4000
+    series = np.empty((nsamp, d, nl))
+    print("walls equipartition case:", lattice, shape, flush=True)
+    with lbl.Sim(H.lbl_params(c), lbl.make_init(psi_std=0.0)) as sim:
+        sim.step(5000)
+        for k in range(nsamp):
+            sim.step(20)
+            u = sim.observe(lbl.LBL_OBS_U).reshape(d, -1)
+            series[k] = (u ** 2).reshape(d, nl, -1).mean(axis=2) / 1e-5
+    nb = 20
+    bm = series.reshape(nb, -1, d, nl).mean(axis=1)
+    got, se = bm.mean(axis=0), bm.std(axis=0, ddof=1) / np.sqrt(nb)
+    print("  <u_a^2> rho0/kT per layer:", np.round(got, 3).tolist(), flush=True)
+    assert np.all(np.abs(got - 1) <= np.maximum(0.02, 3 * se))
