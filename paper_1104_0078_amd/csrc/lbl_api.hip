@@ -969,70 +969,59 @@ struct Impl {
   }
 
   // Enqueue `nsteps` batched steps of a group on `stream` (captured by the
-  // caller into a graph).
+  // caller into a graph).  The launches of step k take k; the replicas'
+  // states move once, after the last step.
   static int enqueue_group(hipStream_t stream, const void* reps_dev, RepState* states, int nrep,
                            const Work* wlb, int nlb, int lb_lw, const Work* wtile, int ntile,
                            int rk, bool ghost, int nt, bool walls, int64_t nsteps) {
+    if (nsteps < 0 || nsteps > (1 << 30)) return LBL_E_INVAL;
     if constexpr (SMOL == kFV)
       if (walls)
-        return enqueue_walls(stream, reps_dev, states, nrep, wlb, nlb, lb_lw, wtile, ntile, rk,
-                             ghost, nt, nsteps);
+        return enqueue_steps<true>(stream, reps_dev, states, nrep, wlb, nlb, lb_lw, wtile, ntile,
+                                   rk, ghost, nt, static_cast<int>(nsteps));
     if (walls) return LBL_E_INVAL;
-    const Replica<S>* reps = static_cast<const Replica<S>*>(reps_dev);
-    const dim3 bsite(kSiteBlock), btile(kTX, kTY);
-    for (int64_t k = 0; k < nsteps; ++k) {
-      kb_prep<S, Q, SMOL><<<ntile, btile, 0, stream>>>(reps, states, wtile);
-      if (ghost && nt)
-        kb_lb<S, DEV, Q, SMOL, true, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw);
-      else if (ghost)
-        kb_lb<S, DEV, Q, SMOL, true, false><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw);
-      else if (nt)
-        kb_lb<S, DEV, Q, SMOL, false, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw);
-      else
-        kb_lb<S, DEV, Q, SMOL, false, false><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw);
-      if (rk > 1 && nt)
-        kb_uend<S, DEV, Q, SMOL, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw, rk);
-      else if (rk > 1)
-        kb_uend<S, DEV, Q, SMOL, false><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw, rk);
-      for (int st = 0; st < rk; ++st)
-        kb_stage<S, Q, SMOL><<<ntile, btile, 0, stream>>>(reps, states, wtile, st, rk);
-      kb_advance<S><<<(nrep + 255) / 256, 256, 0, stream>>>(reps, states, nrep);
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return LBL_E_DEVICE;
-    }
-    return LBL_OK;
+    return enqueue_steps<false>(stream, reps_dev, states, nrep, wlb, nlb, lb_lw, wtile, ntile, rk,
+                                ghost, nt, static_cast<int>(nsteps));
   }
 
-  // The same for a group whose replicas have walls (FV only).
-  static int enqueue_walls(hipStream_t stream, const void* reps_dev, RepState* states, int nrep,
+  // WALLS: every replica of the group has walls (FV only; the ghost-rate
+  // variant of the LB pass keeps the default cache policy there).
+  template <bool WALLS>
+  static int enqueue_steps(hipStream_t stream, const void* reps_dev, RepState* states, int nrep,
                            const Work* wlb, int nlb, int lb_lw, const Work* wtile, int ntile,
-                           int rk, bool ghost, int nt, int64_t nsteps) {
+                           int rk, bool ghost, int nt, int nsteps) {
     const Replica<S>* reps = static_cast<const Replica<S>*>(reps_dev);
     const dim3 bsite(kSiteBlock), btile(kTX, kTY);
-    for (int64_t k = 0; k < nsteps; ++k) {
-      kb_prep<S, Q, SMOL, true><<<ntile, btile, 0, stream>>>(reps, states, wtile);
-      if (ghost)
-        kb_lb<S, DEV, Q, SMOL, true, false, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
-                                                                               lb_lw);
+    for (int k = 0; k < nsteps; ++k) {
+      kb_prep<S, Q, SMOL, WALLS><<<ntile, btile, 0, stream>>>(reps, states, wtile, k);
+      bool ghost_nt = false;
+      if constexpr (!WALLS) ghost_nt = ghost && nt;
+      if (ghost_nt) {
+        if constexpr (!WALLS)
+          kb_lb<S, DEV, Q, SMOL, true, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw,
+                                                                          k);
+      } else if (ghost)
+        kb_lb<S, DEV, Q, SMOL, true, false, WALLS><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
+                                                                                lb_lw, k);
       else if (nt)
-        kb_lb<S, DEV, Q, SMOL, false, true, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
-                                                                               lb_lw);
+        kb_lb<S, DEV, Q, SMOL, false, true, WALLS><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
+                                                                                lb_lw, k);
       else
-        kb_lb<S, DEV, Q, SMOL, false, false, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
-                                                                                lb_lw);
+        kb_lb<S, DEV, Q, SMOL, false, false, WALLS><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
+                                                                                 lb_lw, k);
       if (rk > 1 && nt)
-        kb_uend<S, DEV, Q, SMOL, true, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw,
-                                                                          rk);
+        kb_uend<S, DEV, Q, SMOL, true, WALLS><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw,
+                                                                           rk, k);
       else if (rk > 1)
-        kb_uend<S, DEV, Q, SMOL, false, true><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
-                                                                           lb_lw, rk);
+        kb_uend<S, DEV, Q, SMOL, false, WALLS><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
+                                                                            lb_lw, rk, k);
       for (int st = 0; st < rk; ++st)
-        kb_stage<S, Q, SMOL, true><<<ntile, btile, 0, stream>>>(reps, states, wtile, st, rk);
-      kb_advance<S><<<(nrep + 255) / 256, 256, 0, stream>>>(reps, states, nrep);
+        kb_stage<S, Q, SMOL, WALLS><<<ntile, btile, 0, stream>>>(reps, states, wtile, st, rk, k);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return LBL_E_DEVICE;
     }
-    return LBL_OK;
+    kb_advance<S><<<(nrep + 255) / 256, 256, 0, stream>>>(reps, states, nrep, nsteps);
+    return hipGetLastError() == hipSuccess ? LBL_OK : LBL_E_DEVICE;
   }
 
   // Observables into a device FP64 buffer `dst`.

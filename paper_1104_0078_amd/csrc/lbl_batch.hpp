@@ -34,13 +34,26 @@ struct Replica {
   uint32_t k0, k1;
 };
 
-// Device-side state of one replica; it is advanced while remaining > 0.
+// Device-side state of one replica at the start of a tick; it is advanced
+// while remaining > 0.
 struct RepState {
   int cur;    // population buffer holding f*
   int pcur;   // psi buffer holding psi^n
   uint32_t step;
   int remaining;
 };
+
+// The state k steps into a tick: the buffers flip every step (those the
+// coupling updates), the counters move by k.  The launches of step k of a
+// captured tick take k as an argument, so no kernel has to advance the state
+// between steps; kb_advance moves it once, at the end of the tick.
+__device__ __forceinline__ RepState at_step(RepState s, int coupling, int k) {
+  if (coupling != kCplSmolOnly && (k & 1)) s.cur = 1 - s.cur;
+  if (coupling != kCplLbOnly && (k & 1)) s.pcur = 1 - s.pcur;
+  s.step += static_cast<uint32_t>(k);
+  s.remaining -= k;
+  return s;
+}
 
 struct Work {
   int rep;
@@ -51,11 +64,11 @@ struct Work {
 template <typename S, int Q, int SMOL, bool WALLS = false>
 __global__ __launch_bounds__(kTX* kTY) void kb_prep(const Replica<S>* __restrict__ reps,
                                                    const RepState* __restrict__ st,
-                                                   const Work* __restrict__ work) {
+                                                   const Work* __restrict__ work, int k) {
   const Work w = work[blockIdx.x];
-  const RepState rs = st[w.rep];
-  if (rs.remaining <= 0) return;
   const Replica<S>& r = reps[w.rep];
+  const RepState rs = at_step(st[w.rep], r.coupling, k);
+  if (rs.remaining <= 0) return;
   PrepArgs<S> a;
   a.g = r.g;
   a.c = r.c;
@@ -84,10 +97,11 @@ __device__ __forceinline__ void lb_tile_site(const Work& w, int lw, int& x, int&
 template <typename S, bool DEV, int Q, int SMOL, bool GHOST, bool NT, bool WALLS = false>
 __global__ __launch_bounds__(kSiteBlock) void kb_lb(const Replica<S>* __restrict__ reps,
                                                       const RepState* __restrict__ st,
-                                                      const Work* __restrict__ work, int lw) {
+                                                      const Work* __restrict__ work, int lw,
+                                                      int k) {
   const Work w = work[blockIdx.x];
-  const RepState rs = st[w.rep];
   const Replica<S>& r = reps[w.rep];
+  const RepState rs = at_step(st[w.rep], r.coupling, k);
   if (rs.remaining <= 0 || r.coupling == kCplSmolOnly) return;
   LBArgs<S> a;
   a.g = r.g;
@@ -123,10 +137,11 @@ __global__ __launch_bounds__(kSiteBlock) void kb_lb(const Replica<S>* __restrict
 template <typename S, bool DEV, int Q, int SMOL, bool NT, bool WALLS = false>
 __global__ __launch_bounds__(kSiteBlock) void kb_uend(const Replica<S>* __restrict__ reps,
                                                      const RepState* __restrict__ st,
-                                                     const Work* __restrict__ work, int lw, int rk) {
+                                                     const Work* __restrict__ work, int lw, int rk,
+                                                     int k) {
   const Work w = work[blockIdx.x];
-  const RepState rs = st[w.rep];
   const Replica<S>& r = reps[w.rep];
+  const RepState rs = at_step(st[w.rep], r.coupling, k);
   if (rs.remaining <= 0 || r.coupling != kCplFull || rk < 2) return;
   LBArgs<S> a;
   a.g = r.g;
@@ -153,10 +168,10 @@ template <typename S, int Q, int SMOL, bool WALLS = false>
 __global__ __launch_bounds__(kTX* kTY) void kb_stage(const Replica<S>* __restrict__ reps,
                                                     const RepState* __restrict__ state,
                                                     const Work* __restrict__ work, int st,
-                                                    int ns) {
+                                                    int ns, int k) {
   const Work w = work[blockIdx.x];
-  const RepState rs = state[w.rep];
   const Replica<S>& r = reps[w.rep];
+  const RepState rs = at_step(state[w.rep], r.coupling, k);
   if (rs.remaining <= 0 || r.coupling == kCplLbOnly) return;
   StageArgs<S> a;
   a.g = r.g;
@@ -190,19 +205,16 @@ __global__ __launch_bounds__(kTX* kTY) void kb_stage(const Replica<S>* __restric
     stage_fd_body<S, Q>(a, w.bx, w.by, w.bz);
 }
 
-// End of a step: flip the buffers the step wrote, count it.
+// End of a tick of `nsteps` steps: each replica's state after the steps it
+// took (up to its own count).
 template <typename S>
-__global__ void kb_advance(const Replica<S>* __restrict__ reps, RepState* __restrict__ st, int n) {
+__global__ void kb_advance(const Replica<S>* __restrict__ reps, RepState* __restrict__ st, int n,
+                           int nsteps) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  RepState s = st[i];
+  const RepState s = st[i];
   if (s.remaining <= 0) return;
-  const int cpl = reps[i].coupling;
-  if (cpl != kCplSmolOnly) s.cur = 1 - s.cur;
-  if (cpl != kCplLbOnly) s.pcur = 1 - s.pcur;
-  s.step += 1;
-  s.remaining -= 1;
-  st[i] = s;
+  st[i] = at_step(s, reps[i].coupling, s.remaining < nsteps ? s.remaining : nsteps);
 }
 
 }  // namespace lbl
