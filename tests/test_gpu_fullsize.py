@@ -112,3 +112,54 @@ def test_window_128_sampled_parity(oracle_window, precision):
     print("  rel err populations %.3e psi %.3e over %d sites" % (ef, ep, s.size), flush=True)
     tol = H.TOL[precision]
     assert ef <= tol and ep <= tol
+
+
+@pytest.fixture(scope="module")
+def oracle_walls():
+    """The same 256^3 two-phase workload between walls sliding at
+    (0.02, -0.01, 0) and (-0.015, 0.01, 0), as the bench's walls leg runs it;
+    two oracle steps over the whole lattice."""
+    c = H.config(lattice=H.D3Q19, smol=H.FV, shape=SHAPE, a=-0.04, b=0.04, kappa=0.05, M=0.1,
+                 kT=1e-5, eta=0.1, init=1, psi_std=1e-3, walls=1,
+                 u_wall=((0.02, -0.01, 0.0), (-0.015, 0.01, 0.0)))
+    print("full-size walls oracle: %s, %d steps" % (SHAPE, NSTEPS), flush=True)
+    f, psi = H.oracle_run(c, NSTEPS)
+    return c, f.reshape(19, -1), psi.reshape(-1)
+
+
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32DEV])
+def test_full_size_walls_sampled_parity(oracle_walls, precision):
+    """256^3 between sliding walls: 200 000 sampled sites plus both wall
+    layers and the interface plane against the oracle (1e-12 FP64, 1e-5
+    FP32-dev), and conservation of mass and psi."""
+    import torch
+    from paper_1104_0078_amd import lbl
+    c0, f_ref, psi_ref = oracle_walls
+    c = dict(c0, precision=precision)
+    print("full-size walls case: precision %d" % precision, flush=True)
+    N = SHAPE[0] * SHAPE[1] * SHAPE[2]
+    plane = SHAPE[0] * SHAPE[1]
+    rng = np.random.default_rng(13)
+    rows = [np.arange(plane) + z * plane for z in (0, SHAPE[2] // 4, SHAPE[2] - 1)]
+    s_np = np.unique(np.concatenate([rng.choice(N, size=200000, replace=False)] + rows))
+    sites = torch.from_numpy(s_np).cuda()
+    with lbl.Sim(H.lbl_params(c), lbl.make_init(kind=1, psi_std=1e-3)) as sim:
+        tot0 = sim.observe(lbl.LBL_OBS_TOTALS)
+        sim.step(NSTEPS)
+        tot1 = sim.observe(lbl.LBL_OBS_TOTALS)
+        pop = torch.empty(19 * N, dtype=torch.float64, device="cuda")
+        sim.observe_into(lbl.LBL_OBS_POP, pop)
+        f_gpu = pop.view(19, N)[:, sites].cpu().numpy()
+        del pop
+        psi = torch.empty(N, dtype=torch.float64, device="cuda")
+        sim.observe_into(lbl.LBL_OBS_PSI, psi)
+        psi_gpu = psi[sites].cpu().numpy()
+        del psi
+    tol = H.TOL[precision]
+    ef = float(np.abs(f_gpu - f_ref[:, s_np]).max() / np.abs(f_ref).max())
+    ep = float(np.abs(psi_gpu - psi_ref[s_np]).max() / np.abs(psi_ref).max())
+    print("  rel err populations %.3e psi %.3e over %d sites" % (ef, ep, s_np.size), flush=True)
+    assert ef <= tol and ep <= tol
+    ctol = 1e-13 if precision == H.FP64 else 1e-6
+    assert abs(tot1[0] - tot0[0]) <= ctol * abs(tot0[0])
+    assert abs(tot1[4] - tot0[4]) <= ctol * tot0[9] + 1e-300
