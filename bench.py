@@ -544,6 +544,8 @@ def main():
                     help="skip the run of the same workload with the stress-divergence force")
     ap.add_argument("--no-walls", action="store_true",
                     help="skip the leg with sliding walls across the last axis")
+    ap.add_argument("--no-slab", action="store_true",
+                    help="skip the leg on one GPU's share of an 8-way z-slab decomposition")
     ap.add_argument("--no-tune", action="store_true", help="no autotuning of the pool legs")
     ap.add_argument("--tune-single", action="store_true",
                     help="autotune the single-run schedule too (default: the library's own)")
@@ -718,6 +720,20 @@ def main():
             "kernels_ms_per_step": {t[0]: round(t[2] / nw, 4) for t in rw["ktimes"]},
             "error_vs_oracle": leg_error_vs_oracle(lbl, ww)}
         print("walls leg done: %.1f MLUPS" % rw["mlups"], file=sys.stderr, flush=True)
+    if not args.no_slab and w["lattice"] != 9 and w["shape"][2] % 8 == 0:
+        # One GPU's share of the same lattice split into 8 z-slabs: the step
+        # on nx x ny x nz/8 sites (periodic along z standing in for the halo
+        # exchange, which is not run).
+        nsl = min(args.steps, 30)
+        ws = dict(w, shape=(w["shape"][0], w["shape"][1], w["shape"][2] // 8))
+        rsl = run_single(lbl, torch, ws, args.workload, nsl, args.warmup, False)
+        out["shard_slab_one_gpu"] = {
+            "shape": list(ws["shape"]), "value": round(rsl["mlups"], 2), "unit": "MLUPS",
+            "ms_per_step": round(rsl["ms_per_step"], 4),
+            "kernels_ms_per_step": {t[0]: round(t[2] / nsl, 4) for t in rsl["ktimes"]},
+            "note": "one GPU's share of an 8-way z-slab decomposition; periodic along z "
+                    "in place of the halo exchange, which is not run"}
+        print("slab leg done: %.1f MLUPS" % rsl["mlups"], file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = {}
         for prec, name in ((1, "fp32"), (0, "fp64")):
