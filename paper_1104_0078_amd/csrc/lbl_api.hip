@@ -673,6 +673,23 @@ struct Impl {
     });
   }
 
+  // The FV stage kernel, in the fixed form `form` on 3-D lattices.
+  template <bool WALLS>
+  static int launch_stage_fv(lbl_sim* s, hipStream_t ss, const StageArgs<S>& a,
+                             const TileMap& tm, dim3 tg, dim3 tb, int form) {
+    if constexpr (Lat<Q>::D == 3) {
+      if (form == kStageHeun1)
+        return launch_on(s, ss, "k_stage", [&] {
+          k_stage_fv<S, Q, WALLS, kStageHeun1><<<tg, tb, 0, ss>>>(a, tm);
+        });
+      if (form == kStageHeun2)
+        return launch_on(s, ss, "k_stage", [&] {
+          k_stage_fv<S, Q, WALLS, kStageHeun2><<<tg, tb, 0, ss>>>(a, tm);
+        });
+    }
+    return launch_on(s, ss, "k_stage", [&] { k_stage_fv<S, Q, WALLS><<<tg, tb, 0, ss>>>(a, tm); });
+  }
+
   static int launch_mu(lbl_sim* s, const S* phi, S* mu) {
     const dim3 grid = site_grid(s), block(kBX, kBY);
     const Geom g = geom(s);
@@ -811,12 +828,14 @@ struct Impl {
         a.out = a.last ? psout : static_cast<S*>(s->phi[st & 1]);
         const hipStream_t ss = (fork && st == 0) ? s->aux : s->stream;
         int rc;
+        // Heun under full coupling: its two stages as fixed forms (3-D FV)
+        int form = kStageAny;
+        if (ns == 2 && cpl == LBL_FULL) form = st == 0 ? kStageHeun1 : kStageHeun2;
         if constexpr (kTiledWalls) {
           if (walls_tiled)
-            rc = launch_on(s, ss, "k_stage",
-                           [&] { k_stage_fv<S, Q, true><<<tg, tb, 0, ss>>>(a, tm); });
+            rc = launch_stage_fv<true>(s, ss, a, tm, tg, tb, form);
           else
-            rc = launch_on(s, ss, "k_stage", [&] { k_stage_fv<S, Q><<<tg, tb, 0, ss>>>(a, tm); });
+            rc = launch_stage_fv<false>(s, ss, a, tm, tg, tb, form);
         } else if (SMOL == kFV)
           rc = launch_on(s, ss, "k_stage", [&] { k_stage_fv<S, Q><<<tg, tb, 0, ss>>>(a, tm); });
         else

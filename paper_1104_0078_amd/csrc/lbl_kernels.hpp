@@ -1241,6 +1241,47 @@ __device__ __forceinline__ void combine_in(const StageArgs<S>& a, int s, S G, co
   }
 }
 
+// Stage forms fixed at compile time, so that the z-marching loop carries no
+// uniform branches on the velocity's time level or the combination: the two
+// stages of Heun's method under full coupling.  kStageAny reads them from the
+// arguments.
+enum : int { kStageAny = 0, kStageHeun1 = 1, kStageHeun2 = 2 };
+
+template <int SF, typename S>
+__device__ __forceinline__ S uval_sf(const StageArgs<S>& a, int comp, int site) {
+  const size_t k = static_cast<size_t>(comp) * a.g.N + site;
+  if constexpr (SF == kStageHeun1)
+    return a.u[k];
+  else if constexpr (SF == kStageHeun2)
+    return a.u_end[k];
+  else
+    return uval(a, comp, site);
+}
+
+template <int SF, typename S>
+__device__ __forceinline__ SiteIn<S> fetch_site_sf(const StageArgs<S>& a, int s) {
+  if constexpr (SF == kStageAny) {
+    return fetch_site(a, s);
+  } else {
+    SiteIn<S> v;
+    v.noise = a.noise[s];
+    v.psi_n = a.psi_n[s];
+    v.phi = SF == kStageHeun2 ? a.phi[s] : S(0);
+    v.acc = S(0);
+    return v;
+  }
+}
+
+template <int SF, typename S>
+__device__ __forceinline__ void combine_sf(const StageArgs<S>& a, int s, S G, const SiteIn<S>& v) {
+  if constexpr (SF == kStageHeun1)
+    a.out[s] = v.psi_n + a.cnext * G;
+  else if constexpr (SF == kStageHeun2)
+    a.out[s] = S(0.5) * (v.psi_n + v.phi + G);
+  else
+    combine_in(a, s, G, v);
+}
+
 // FV stage (Sec. V.B, Eq. fvft): G = Gamma . J + N with the node flux
 // J = -u phi + M Gamma mu(phi).  2-D: one plane, phi (halo 3), mu (halo 2)
 // and J (halo 1) in LDS, one phase each.
@@ -1322,7 +1363,7 @@ __device__ __forceinline__ void stage_fv2_body(const StageArgs<S>& a, int bx, in
 // WALLS: walls across z.  The Laplacian and Gamma mu take the centre's value
 // beyond a wall; a J plane beyond a wall is not folded, and the links across
 // it take minus the centre's J (a term +-W J_z on the end planes).
-template <typename S, int Q, bool WALLS = false>
+template <typename S, int Q, bool WALLS = false, int SF = kStageAny>
 __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, int by, int bz) {
   using L = Lat<Q>;
   constexpr int D = 3;
@@ -1390,14 +1431,14 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
     if (p < z1 + 2) fetch_phi(plane * zf);
     const int s = x + g.nx * (y + g.ny * (p - 3));
     SiteIn<S> sv{};
-    if (do_G) sv = fetch_site(a, s);
+    if (do_G) sv = fetch_site_sf<SF>(a, s);
     if (do_J) {
       const int zo = plane * zu;
 #pragma unroll
       for (int k = 0; k < NE; ++k)
         if (jon[k]) {
 #pragma unroll
-          for (int c = 0; c < D; ++c) uv[k][c] = uval(a, c, pxy[k] + zo);
+          for (int c = 0; c < D; ++c) uv[k][c] = uval_sf<SF>(a, c, pxy[k] + zo);
         }
     }
     zu = next_plane(zu, g.nz);
@@ -1471,7 +1512,7 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
         if (p - 2 == 0) gpart[1] += kWall * jz;
         if (p - 2 == g.nz - 1) gpart[1] -= kWall * jz;
       }
-      if (do_G) combine_in(a, s, S(3) * gpart[0] + sv.noise, sv);
+      if (do_G) combine_sf<SF>(a, s, S(3) * gpart[0] + sv.noise, sv);
       gpart[0] = gpart[1];
       gpart[1] = gpart[2];
       gpart[2] = 0;
@@ -1479,18 +1520,18 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
   }
 }
 
-template <typename S, int Q, bool WALLS = false>
+template <typename S, int Q, bool WALLS = false, int SF = kStageAny>
 __device__ __forceinline__ void stage_fv_body(const StageArgs<S>& a, int bx, int by, int bz) {
   if constexpr (Lat<Q>::D == 3)
-    stage_fv3_body<S, Q, WALLS>(a, bx, by, bz);
+    stage_fv3_body<S, Q, WALLS, SF>(a, bx, by, bz);
   else
     stage_fv2_body<S, Q, WALLS>(a, bx, by);
 }
 
-template <typename S, int Q, bool WALLS = false>
+template <typename S, int Q, bool WALLS = false, int SF = kStageAny>
 __global__ __launch_bounds__(kTX* kTY) void k_stage_fv(StageArgs<S> a, TileMap m) {
   int bx, by, bz;
-  if (tile_of(m, bx, by, bz)) stage_fv_body<S, Q, WALLS>(a, bx, by, bz);
+  if (tile_of(m, bx, by, bz)) stage_fv_body<S, Q, WALLS, SF>(a, bx, by, bz);
 }
 
 // FD stage (Sec. V.A): G = -D.(u phi) + M L_SO mu(phi) + N with the central
