@@ -1372,6 +1372,10 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
   constexpr int NT = kTX * kTY;
   constexpr int NPF = (WP * HP + NT - 1) / NT;
   constexpr int NE = (WM * HM + NT - 1) / NT;
+  // FP64: the elements every thread owns are known at compile time (fewer
+  // masked branches; measured 5% faster).  FP32 keeps the run-time test,
+  // which measured 6% faster there.
+  constexpr bool kFixed = sizeof(S) == 8;
   __shared__ S sphi[WP * HP];
   __shared__ S smu[3][WM * HM];
   __shared__ S sJ[D][WM * HM];
@@ -1391,7 +1395,7 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
   for (int k = 0; k < NE; ++k) {
     const int e = tid + k * NT;
     const int i = e % WM, j = e / WM;
-    pon[k] = e < WM * HM;
+    pon[k] = (kFixed && (k + 1) * NT <= WM * HM) || e < WM * HM;
     jon[k] = pon[k] && i >= 1 && i < WM - 1 && j >= 1 && j < HM - 1;
     pxy[k] = wrap_r(x0 - 2 + i, g.nx, near) + g.nx * wrap_r(y0 - 2 + j, g.ny, near);
   }
@@ -1408,7 +1412,8 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
   auto fetch_phi = [&](int zoff) {
 #pragma unroll
     for (int k = 0; k < NPF; ++k)
-      if (tid + k * NT < WP * HP) pf[k] = a.phi[fxy[k] + zoff];
+      if ((kFixed && (k + 1) * NT <= WP * HP) || tid + k * NT < WP * HP)
+        pf[k] = a.phi[fxy[k] + zoff];
   };
 
   SoPlanes<S> so[NE];                  // phi planes p-2, p-1, p
@@ -1426,7 +1431,8 @@ __device__ __forceinline__ void stage_fv3_body(const StageArgs<S>& a, int bx, in
     const bool do_mu = p >= z0 - 1, do_J = p >= z0 + 1, do_G = p >= z0 + 3 && live;
 #pragma unroll
     for (int k = 0; k < NPF; ++k)
-      if (tid + k * NT < WP * HP) sphi[tid + k * NT] = pf[k];
+      if ((kFixed && (k + 1) * NT <= WP * HP) || tid + k * NT < WP * HP)
+        sphi[tid + k * NT] = pf[k];
     zf = next_plane(zf, g.nz);
     if (p < z1 + 2) fetch_phi(plane * zf);
     const int s = x + g.nx * (y + g.ny * (p - 3));
