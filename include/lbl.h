@@ -294,8 +294,9 @@ int lbl_timing_read(lbl_sim *sim, lbl_kernel_time *out, int max_entries, int *n_
  * (32, 64, 128 or 256; a block covers 256 / lb_width rows of one plane);
  * xcd_swizzle, bit 0: the LB blocks, bit 1: the SMOL tiles are ordered so
  * that each of the 8 XCDs sweeps one contiguous eighth of them (reads across
- * block edges then hit the same L2); zc: planes per block of the z-marching SMOL kernels of a 3-D
- * lattice, stage and preparation kernels alike (0 restores the library's
+ * block edges then hit the same L2); zc: planes per block of the z-marching
+ * kernels of a 3-D lattice, the stage, the preparation kernel and the velocity
+ * pass that draws the noise alike (0 restores the library's
  * per-kernel defaults below, larger than nz is clamped; lbl_get_schedule
  * reports the stage's); overlap:
  * 1 runs the first Runge-Kutta stage on a second stream of the library's
@@ -303,13 +304,17 @@ int lbl_timing_read(lbl_sim *sim, lbl_kernel_time *out, int max_entries, int *n_
  * streamed populations that only the later stages read (full coupling, 2 or
  * 4 stages); 2 draws the SMOL noise on that second stream, concurrently with
  * the LB passes (the noise depends on the counter alone), and joins it before
- * the first stage; 0 runs everything on the simulation's stream.  Default: the
- * widest width up to 256 that fits nx, no swizzle, zc per kernel from its
- * occupancy (the stage's blocks fill the device's resident slots in one
- * round, the preparation kernel's in two; at least 8 planes), overlap 0.
- * The z-marching stress pass of force_form STRESS (FV, 3-D) keeps its own
- * default (two rounds) whatever zc is.  Errors: LBL_E_INVAL (NULL,
- * unsupported width, zc < 0, overlap not 0, 1 or 2). */
+ * the first stage; 3 (FV on 3-D lattices) draws the SMOL noise inside the
+ * velocity pass, one z-marching kernel on the stream, where a velocity pass
+ * runs (full coupling, 2 or 4 stages, kT > 0), and is 0 elsewhere; 0 runs
+ * everything on the simulation's stream, the noise in the preparation
+ * kernel.  Default: the widest width up to 256 that fits nx, no swizzle, zc
+ * per kernel from its occupancy (the stage's blocks fill the device's
+ * resident slots in one round, the preparation kernel's and the velocity
+ * pass's in two; at least 8 planes), overlap 3 for FV on 3-D lattices and 0
+ * otherwise.  The z-marching stress pass of force_form STRESS (FV, 3-D) keeps
+ * its own default (two rounds) whatever zc is.  Errors: LBL_E_INVAL (NULL,
+ * unsupported width, zc < 0, overlap not 0, 1, 2 or 3). */
 typedef struct lbl_schedule {
   int32_t lb_width;
   int32_t xcd_swizzle;

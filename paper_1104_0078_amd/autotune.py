@@ -13,7 +13,8 @@ Schedule knobs (see lbl_set_schedule / lbl_pool_set_schedule in lbl.h):
   xcd_swizzle  block order that hands each XCD a contiguous part of the work
                (single simulations: bit 0 the LB kernels, bit 1 the SMOL tiles);
   zc           planes per block of the z-marching SMOL kernels (3-D);
-  overlap      1: the first stage, 2: the SMOL noise on a second stream
+  overlap      1: the first stage, 2: the SMOL noise on a second stream,
+               3: the SMOL noise inside the velocity pass (FV, 3-D), 0: none
                (single simulations).
 """
 import json
@@ -54,14 +55,14 @@ def sim_key(params):
         params.nx, params.ny, params.nz, params.rk_stages)
 
 
-def sim_candidates(params):
+def sim_candidates(params, overlap=0):
     widths = [w for w in (32, 64, 128, 256) if w <= max(32, params.nx)]
     widths = widths[-3:]
     zcs = [0]  # 0: the library's per-kernel defaults (from occupancy)
     if params.nz > 1:
         zcs = [0] + sorted({z for z in (8, 16, 32, 64) if z <= params.nz} or {params.nz})
     swz = (0, 1, 2, 3) if params.nz > 1 else (0, 1)
-    return [dict(lb_width=w, xcd_swizzle=s, zc=z, overlap=0) for w in widths for s in swz
+    return [dict(lb_width=w, xcd_swizzle=s, zc=z, overlap=overlap) for w in widths for s in swz
             for z in zcs]
 
 
@@ -90,20 +91,26 @@ def tune_sim(sim, params, steps=6, use_cache=True, candidates=None):
             sim.set_schedule(**hit["schedule"])
             return dict(hit, from_cache=True)
     table = []
+    ov0 = sim.schedule()["overlap"]  # the library's default for this lattice
     sim.step(8)  # clocks and caches settle before the first candidate
-    for cand in candidates or sim_candidates(params):
+    for cand in candidates or sim_candidates(params, ov0):
         table.append({"schedule": cand, "ms_per_step": round(_time_sim(sim, cand, steps), 4)})
     best = min(table, key=lambda r: r["ms_per_step"])
     # Last dimension, on top of the best schedule so far: the first stage on
     # a second stream, concurrent with the velocity pass (full coupling,
-    # several stages), or the SMOL noise on it, concurrent with the LB passes.
-    overlaps = []
+    # several stages), the SMOL noise on it, concurrent with the LB passes,
+    # the noise inside the velocity pass (FV, 3-D), or none of these.
+    overlaps = [0]
     if params.coupling == 0 and params.rk_stages > 1:
         overlaps.append(1)
     if params.coupling != 2 and params.kT > 0:
         overlaps.append(2)
+    if ov0 == 3:
+        overlaps.append(3)
     base = best["schedule"]
     for ov in overlaps:
+        if ov == base["overlap"]:
+            continue
         cand = dict(base, overlap=ov)
         table.append({"schedule": cand, "ms_per_step": round(_time_sim(sim, cand, steps), 4)})
     best = min(table, key=lambda r: r["ms_per_step"])

@@ -76,10 +76,12 @@ struct lbl_sim {
   int zc = 1;       // planes per block of the z-marching SMOL stage kernels
   int zc_prep = 1;  // planes per block of the z-marching preparation kernel
   int zc_stress = 1;  // planes per block of the z-marching FV stress kernels (3-D)
+  int zc_uend = 1;    // planes per block of the velocity pass with the noise (FV, 3-D)
   int lb_lw = 6;       // log2 of the LB block width along x
   int lb_swizzle = 0;  // XCD-contiguous block order: bit 0 LB kernels, bit 1 tile kernels
   int overlap = 0;     // 1: first RK stage on `aux`, concurrent with the velocity pass;
-                       // 2: SMOL noise on `aux`, concurrent with the LB passes
+                       // 2: SMOL noise on `aux`, concurrent with the LB passes;
+                       // 3: SMOL noise drawn inside the velocity pass (FV, 3-D)
   hipStream_t aux = nullptr;  // created on first use (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double gamma_s = 0, gamma_b = 0, gamma_g = 0, sigma_s = 0, sigma_b = 0, sigma_g = 0;
@@ -351,8 +353,9 @@ struct Impl {
 
   // Default z-chunks of the tiled SMOL kernels (3-D): as many chunks as fill
   // the device's resident block slots of each kernel in whole rounds, one
-  // round for the stage kernel, two for the preparation kernel (measured best
-  // on 256^3), and never fewer than 8 planes per chunk.
+  // round for the stage kernel, two for the preparation kernel and the
+  // velocity pass with the noise (measured best on 256^3), and never fewer
+  // than 8 planes per chunk.
   static int default_chunks(lbl_sim* s) {
     if (Lat<Q>::D != 3) return LBL_OK;
     int cus = 0, nb_stage = 0, nb_prep = 0;
@@ -373,12 +376,17 @@ struct Impl {
                                                                          kTX * kTY, 0), "occupancy");
       }
     }
-    int nb_stress = 0;
-    if constexpr (SMOL == kFV && Lat<Q>::D == 3)
+    int nb_stress = 0, nb_uend = 0;
+    if constexpr (SMOL == kFV && Lat<Q>::D == 3) {
       if (!rc)
         rc = hip_check(s, hipOccupancyMaxActiveBlocksPerMultiprocessor(
                               &nb_stress, k_stress_force_fv3<S, Q>, kTX * kTY, 0),
                        "occupancy");
+      if (!rc)
+        rc = hip_check(s, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &nb_uend, k_uend_noise<S, DEV, Q, false>, kTX * kTY, 0),
+                       "occupancy");
+    }
     if (rc) return rc;
     const int nz = s->p.nz;
     const long bxy = static_cast<long>((s->p.nx + kTX - 1) / kTX) * ((s->p.ny + kTY - 1) / kTY);
@@ -391,6 +399,7 @@ struct Impl {
     s->zc = pick(nb_stage, 1);
     s->zc_prep = pick(nb_prep, 2);
     s->zc_stress = pick(nb_stress, 2);
+    s->zc_uend = pick(nb_uend, 2);
     return LBL_OK;
   }
 
@@ -690,6 +699,44 @@ struct Impl {
     return launch_on(s, ss, "k_stage", [&] { k_stage_fv<S, Q, WALLS><<<tg, tb, 0, ss>>>(a, tm); });
   }
 
+  // The velocity pass with the SMOL noise N^n of step `la.step` (FV, 3-D).
+  static int launch_uend_noise(lbl_sim* s, const LBArgs<S>& la, S* noise) {
+    if constexpr (SMOL == kFV && Lat<Q>::D == 3) {
+      PrepArgs<S> pa;
+      pa.g = la.g;
+      pa.c = coef(s);
+      pa.amp = S(std::sqrt(2.0 * s->p.kT * s->p.M));
+      pa.k0 = s->k0;
+      pa.k1 = s->k1;
+      pa.step = la.step;
+      pa.zc = s->zc_uend;
+      pa.psi = nullptr;
+      pa.noise = noise;
+      pa.mu = nullptr;
+      const TileMap tm = make_tile_map(s->p.nx, s->p.ny, (s->p.nz + s->zc_uend - 1) / s->zc_uend,
+                                       (s->lb_swizzle & 2) != 0);
+      const dim3 tg(tile_map_blocks(tm)), tb(kTX, kTY);
+      const hipStream_t st = s->stream;
+      const bool walls = s->p.walls == LBL_WALLS_LAST;
+      return launch(s, "k_uend", [&] {
+        if (walls) {
+          if (la.nt)
+            k_uend_noise<S, DEV, Q, true, true><<<tg, tb, 0, st>>>(la, pa, tm);
+          else
+            k_uend_noise<S, DEV, Q, false, true><<<tg, tb, 0, st>>>(la, pa, tm);
+        } else if (la.nt) {
+          k_uend_noise<S, DEV, Q, true><<<tg, tb, 0, st>>>(la, pa, tm);
+        } else {
+          k_uend_noise<S, DEV, Q, false><<<tg, tb, 0, st>>>(la, pa, tm);
+        }
+      });
+    } else {
+      (void)la;
+      (void)noise;
+      return fail(s, LBL_E_INVAL, "the velocity pass draws the noise only with FV on 3-D lattices");
+    }
+  }
+
   static int launch_mu(lbl_sim* s, const S* phi, S* mu) {
     const dim3 grid = site_grid(s), block(kBX, kBY);
     const Geom g = geom(s);
@@ -736,6 +783,11 @@ struct Impl {
     constexpr bool kTiledWalls = SMOL == kFV;
     const bool walls_tiled = walls && kTiledWalls;
     const bool split = prep_noise && s->overlap == 2;
+    // The velocity of the streamed populations is needed by the stages at
+    // t_{n+1}; with overlap 3 (FV, 3-D) the same pass draws the SMOL noise,
+    // which the first stage is the first to read.
+    const bool uend = cpl == LBL_FULL && s->p.rk_stages > 1;
+    const bool fuse = SMOL == kFV && Lat<Q>::D == 3 && prep_noise && uend && s->overlap == 3;
     if (split) {
       if (int rc = ensure_aux(s)) return rc;
       if (int rc = hip_check(s, hipEventRecord(s->ev_fork, s->stream), "fork")) return rc;
@@ -743,7 +795,7 @@ struct Impl {
     }
     for (int part = split ? 0 : 1; part < 2; ++part) {
       // part 0: the noise alone on `aux`; part 1: what remains on the stream
-      const bool do_noise = prep_noise && (part == 0 || !split);
+      const bool do_noise = prep_noise && !fuse && (part == 0 || !split);
       const bool do_mu = want_mu && part == 1;
       if (!do_noise && !do_mu) continue;
       const hipStream_t ps = part == 0 ? s->aux : s->stream;
@@ -779,9 +831,8 @@ struct Impl {
       if (int rc = launch_lb(s, a, true, "k_lb")) return rc;
     }
     // The velocity of the streamed populations (for the stages at t_{n+1})
-    // and the first stage (at t_n) are independent: with `overlap` the first
+    // and the first stage (at t_n) are independent: with `overlap` 1 the first
     // stage runs on the second stream while the velocity pass runs here.
-    const bool uend = cpl == LBL_FULL && s->p.rk_stages > 1;
     const bool fork = uend && s->overlap == 1;
     if (fork) {
       if (int rc = ensure_aux(s)) return rc;
@@ -790,7 +841,11 @@ struct Impl {
     }
     if (uend && !fork) {
       const LBArgs<S> a = lb_args(s, fout, nullptr, psin, static_cast<S*>(s->u_end), 1, n);
-      if (int rc = launch_lb(s, a, false, "k_uend")) return rc;
+      if (fuse) {
+        if (int rc = launch_uend_noise(s, a, noise)) return rc;
+      } else if (int rc = launch_lb(s, a, false, "k_uend")) {
+        return rc;
+      }
     }
     if (split)
       if (int rc = hip_check(s, hipStreamWaitEvent(s->stream, s->ev_join, 0), "join")) return rc;
@@ -1234,7 +1289,9 @@ void setup_fields(lbl_sim* s, const lbl_params* params) {
   s->sigma_b = sig(s->gamma_b);
   s->sigma_g = sig(s->gamma_g);
   // z-chunks of the tiled SMOL kernels: set from their occupancy at init.
-  s->zc = s->zc_prep = params->nz;
+  s->zc = s->zc_prep = s->zc_uend = params->nz;
+  // FV on 3-D lattices: the SMOL noise is drawn in the velocity pass.
+  s->overlap = params->smol == LBL_SMOL_FV && params->lattice != LBL_D2Q9 ? 3 : 0;
   // LB blocks: the widest power of two up to 256 that fits along x (whole
   // rows where possible, so that pulls shifted along x stay inside a block).
   s->lb_lw = 5;
@@ -1945,13 +2002,13 @@ int lbl_set_schedule(lbl_sim* sim, const lbl_schedule* sch) {
   for (int k = 5; k <= 8; ++k)
     if (w == (1 << k)) lw = k;
   if (lw < 0) return fail(sim, LBL_E_INVAL, "lb_width must be 32, 64, 128 or 256");
-  if (sch->zc < 0 || sch->overlap < 0 || sch->overlap > 2)
-    return fail(sim, LBL_E_INVAL, "zc < 0 or overlap not 0, 1 or 2");
+  if (sch->zc < 0 || sch->overlap < 0 || sch->overlap > 3)
+    return fail(sim, LBL_E_INVAL, "zc < 0 or overlap not 0, 1, 2 or 3");
   sim->lb_lw = lw;
   sim->lb_swizzle = sch->xcd_swizzle & 3;
   sim->overlap = sch->overlap;
   if (sch->zc > 0) {
-    sim->zc = sim->zc_prep = std::min(sch->zc, sim->p.nz);
+    sim->zc = sim->zc_prep = sim->zc_uend = std::min(sch->zc, sim->p.nz);
   } else {
     if (int rc = hip_check(sim, hipSetDevice(sim->device), "hipSetDevice")) return rc;
     if (int rc = select(sim->p).chunks(sim)) return rc;

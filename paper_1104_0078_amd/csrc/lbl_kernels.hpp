@@ -488,8 +488,10 @@ __device__ __forceinline__ void lb_body(const LBArgs<S>& a, int x, int y, int z)
         if (L::cx[i]) cU += L::cx[i] * U[0];
         if (L::cy[i]) cU += L::cy[i] * U[1];
         if (L::cz[i]) cU += L::cz[i] * U[2];
-        fv[i] = a.f_in[static_cast<size_t>(kOpp<Q>.i[i]) * g.N + s] +
-                S(6.0 * L::w[i]) * a.rho0 * cU;
+        // one explicit fma: the same rounding in every kernel that inlines
+        // this (the product is loop-invariant in the z-marching ones)
+        fv[i] = fma(S(6.0 * L::w[i]) * a.rho0, cU,
+                    a.f_in[static_cast<size_t>(kOpp<Q>.i[i]) * g.N + s]);
         continue;
       }
     }
@@ -766,8 +768,15 @@ __device__ __forceinline__ S prep_mu2(const PsiPlane<S>& r, const Coef<S>& c, in
 // +-W xi_z on the end planes) and the Laplacian the centre's psi
 // (SoPlanes::mu_walled).  2-D: a link to a row beyond a wall takes minus the
 // centre's xi, and the Laplacian the centre's psi.
-template <typename S, int Q, bool WALLS = false>
-__device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int by, int bz) {
+// 3-D: `plane_work(p)` runs at the start of iteration p, for kernels that do
+// per-plane work of their own beside the noise.
+struct NoPlaneWork {
+  __device__ __forceinline__ void operator()(int) const {}
+};
+
+template <typename S, int Q, bool WALLS = false, typename PW = NoPlaneWork>
+__device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int by, int bz,
+                                             PW plane_work = PW{}) {
   using L = Lat<Q>;
   constexpr int D = L::D;
   constexpr int W = kTX + 2, H = kTY + 2, RS = W * H;
@@ -833,6 +842,7 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
     int pz = wrap_any(z0 - 1, g.nz);
     for (int p = z0 - 1; p <= z1; ++p, pz = next_plane(pz, g.nz)) {
       const bool ghost = WALLS && (p < 0 || p >= g.nz);  // a plane beyond a wall
+      plane_work(p);
       if (a.noise && !ghost) gen(plane * pz);
       if (a.mu) prep_load_psi(spsi, a.psi, rxy, plane * pz, tid);
       __syncthreads();
@@ -868,6 +878,30 @@ template <typename S, int Q, bool WALLS = false>
 __global__ __launch_bounds__(kTX* kTY) void k_prep_fv(PrepArgs<S> a, TileMap m) {
   int bx, by, bz;
   if (tile_of(m, bx, by, bz)) prep_fv_body<S, Q, WALLS>(a, bx, by, bz);
+}
+
+// FV, 3-D: the velocity pass of the streamed populations (lb_body without
+// the collision: u-bar^1 for the later stages) and the SMOL noise N^n of
+// prep_fv_body in one z-marching launch.  The noise is arithmetic (the
+// Box-Muller normals) and the velocity pass reads the populations with its
+// vector units mostly idle, so in one kernel the two overlap.  The block of
+// in-plane tile t pulls, on each of its planes, the sites t*NT ... t*NT+NT-1
+// of that plane in x-fastest order (contiguous runs, read as the row blocks
+// of k_lb read them; the tiles of a plane cover it); its noise keeps the
+// tile's columns.  The preparation kernel then computes mu alone.
+template <typename S, bool DEV, int Q, bool NT, bool WALLS = false>
+__global__ __launch_bounds__(kTX* kTY) void k_uend_noise(LBArgs<S> la, PrepArgs<S> pa, TileMap m) {
+  static_assert(Lat<Q>::D == 3, "3-D lattices");
+  int bx, by, bz;
+  if (!tile_of(m, bx, by, bz)) return;
+  const Geom& g = la.g;
+  const int z0 = bz * pa.zc, z1 = min(z0 + pa.zc, g.nz);
+  const int e = (bx + m.ntx * by) * (kTX * kTY) + threadIdx.y * kTX + threadIdx.x;
+  const bool pulls = e < g.nx * g.ny;
+  const int x = pulls ? e % g.nx : 0, y = pulls ? e / g.nx : 0;
+  prep_fv_body<S, Q, WALLS>(pa, bx, by, bz, [&](int p) {
+    if (pulls && p >= z0 && p < z1) lb_body<S, DEV, Q, kFV, false, false, NT, WALLS>(la, x, y, p);
+  });
 }
 
 // Stress-divergence force of the FV variant in 3-D (sigma and F = -G.sigma of

@@ -167,14 +167,15 @@ def test_conservation_on_gpu(lattice, precision):
 @pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q19])
 def test_schedule_does_not_change_results(lattice):
     """Every launch schedule (LB block width, XCD-contiguous block order,
-    planes per SMOL tile, first stage or SMOL noise on a second stream) gives
-    bitwise the same fields."""
+    planes per SMOL tile, first stage or SMOL noise on a second stream, SMOL
+    noise drawn in the velocity pass) gives bitwise the same fields."""
     from paper_1104_0078_amd import lbl
     c = H.config(lattice=lattice, smol=H.FV, shape=SHAPES[lattice], init=0)
     ini = lbl.make_init(kind=0, psi_std=1e-3)
     out = []
     for w, swz, zc, ov in ((64, 0, 0, 0), (256, 0, 0, 1), (128, 1, 0, 0), (32, 3, 3, 1),
-                           (256, 2, 5, 0), (64, 0, 0, 2), (128, 3, 4, 2)):
+                           (256, 2, 5, 0), (64, 0, 0, 2), (128, 3, 4, 2), (64, 0, 0, 3),
+                           (128, 2, 3, 3)):
         with lbl.Sim(H.lbl_params(c), ini) as sim:
             sim.set_schedule(lb_width=w, xcd_swizzle=swz, zc=zc, overlap=ov)
             assert sim.schedule()["lb_width"] == w
@@ -254,7 +255,8 @@ def test_wide_lattice_schedules_do_not_change_results(force_form):
                  force_form=force_form)
     ini = lbl.make_init(kind=0, psi_std=1e-3)
     out = []
-    for swz, zc, ov in ((0, 0, 0), (2, 4, 0), (0, 5, 1), (3, 13, 0), (1, 6, 2)):
+    for swz, zc, ov in ((0, 0, 0), (2, 4, 0), (0, 5, 1), (3, 13, 0), (1, 6, 2), (0, 0, 3),
+                        (2, 4, 3), (1, 13, 3)):
         with lbl.Sim(H.lbl_params(c), ini) as sim:
             sim.set_schedule(lb_width=64, xcd_swizzle=swz, zc=zc, overlap=ov)
             sim.step(6)

@@ -114,7 +114,8 @@ def test_walls_schedules_do_not_change_results():
                  kappa=0.05, walls=1, u_wall=SLIDE)
     out = []
     # z-chunks of 4 and 5 planes put chunk edges next to both walls (nz = 13)
-    for w, swz, zc, ov in ((64, 0, 0, 0), (32, 1, 4, 1), (256, 3, 5, 2), (128, 2, 13, 0)):
+    for w, swz, zc, ov in ((64, 0, 0, 0), (32, 1, 4, 1), (256, 3, 5, 2), (128, 2, 13, 0),
+                           (64, 0, 0, 3), (128, 2, 4, 3), (32, 0, 5, 3)):
         with lbl.Sim(H.lbl_params(c), lbl.make_init(kind=1, psi_std=1e-3)) as sim:
             sim.set_schedule(lb_width=w, xcd_swizzle=swz, zc=zc, overlap=ov)
             sim.step(6)
