@@ -63,27 +63,38 @@ def alg_bytes_per_site(w):
     return 2 * w["lattice"] * b + 2 * b
 
 
-def kernel_alg_bytes_per_site(name, w, rk=2):
+def noise_in_velocity_pass(w, schedule):
+    """True when the step draws the SMOL noise inside the velocity pass
+    (schedule overlap 3, FV on a 3-D lattice; the workloads here run full
+    coupling with two stages and kT > 0)."""
+    return (schedule is not None and schedule.get("overlap") == 3 and w["smol"] == 1
+            and w["lattice"] != 9)
+
+
+def kernel_alg_bytes_per_site(name, w, rk=2, schedule=None):
     """Algorithmic bytes per site of one launch of each kernel: every field
     the kernel needs read once and every field it produces written once (no
     halo re-reads); b bytes per stored value, d dimensions.
       k_lb:    pull the Q populations, read psi and mu (force), write the Q
                post-collision populations and u^n:          (2Q + 2 + d) b;
       k_uend:  pull the Q streamed populations, read psi and mu, write the
-               stage velocity at t_{n+1}:                   (Q + 2 + d) b;
-      k_prep:  read psi, write mu and the SMOL noise:        3 b;
+               stage velocity at t_{n+1}:                   (Q + 2 + d) b,
+               and the SMOL noise where it draws it:        + b;
+      k_prep:  read psi, write mu and the SMOL noise:        3 b,
+               or mu alone where the velocity pass draws the noise: 2 b;
       k_stage: read the stage input, the velocity (d values) and the noise,
                write the output; the final Heun stage also reads psi^n
                (mean over the two launches of a step):      (3 + d) b + b/2."""
     b = 8 if w["precision"] == 0 else 4
     d = 2 if w["lattice"] == 9 else 3
     q = w["lattice"]
+    fused = noise_in_velocity_pass(w, schedule)
     if name.startswith("k_lb"):
         return (2 * q + 2 + d) * b
     if name.startswith("k_uend"):
-        return (q + 2 + d) * b
+        return (q + 2 + d + (1 if fused else 0)) * b
     if name.startswith("k_prep"):
-        return 3 * b
+        return (2 if fused else 3) * b
     if name.startswith("k_stage"):
         return (3 + d) * b + (b / 2 if rk == 2 else 0)
     return None
@@ -597,7 +608,7 @@ def main():
     per_kernel = {}
     for kname, klaunch, kms in r["ktimes"]:
         avg_s = kms / klaunch / 1e3
-        kb = kernel_alg_bytes_per_site(kname, w)
+        kb = kernel_alg_bytes_per_site(kname, w, schedule=r["schedule"])
         if kb is None:
             continue
         achieved = kb * N / avg_s / 1e9

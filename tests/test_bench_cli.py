@@ -28,6 +28,13 @@ def test_algorithmic_bytes_of_the_headline_workload():
     assert bench.kernel_alg_bytes_per_site("k_uend", w) == (19 + 2 + 3) * 8
     assert bench.kernel_alg_bytes_per_site("k_prep", w) == 3 * 8
     assert bench.kernel_alg_bytes_per_site("k_stage", w) == (3 + 3) * 8 + 4
+    # the default schedule of FV on 3-D lattices draws the noise in the
+    # velocity pass: its b bytes move from the preparation kernel to it
+    fused = {"overlap": 3}
+    assert bench.kernel_alg_bytes_per_site("k_uend", w, schedule=fused) == (19 + 3 + 3) * 8
+    assert bench.kernel_alg_bytes_per_site("k_prep", w, schedule=fused) == 2 * 8
+    wfd = dict(w, smol=0)
+    assert bench.kernel_alg_bytes_per_site("k_prep", wfd, schedule=fused) == 3 * 8
     w32 = dict(w, precision=1)
     assert bench.alg_bytes_per_site(w32) == 160
     assert bench.kernel_alg_bytes_per_site("k_white", w) is None
