@@ -837,14 +837,27 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
     }
     if (a.mu && live) a.mu[x + g.nx * y] = prep_mu2<S, WALLS>(spsi, a.c, tx, ty, y, g.ny);
   } else {
-    // Iteration p: xi(p) and psi(p) staged; N(p-1) and mu(p-1) emitted.
+    // Iteration p: xi(p) and psi(p) staged; N(p-1) and mu(p-1) emitted.  The
+    // psi plane is fetched into registers one iteration ahead.
     const int plane = g.nx * g.ny;
     int pz = wrap_any(z0 - 1, g.nz);
+    S pv[2];
+    auto fetch_psi = [&](int zoff) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        if (tid + k * NT < RS) pv[k] = a.psi[rxy[k] + zoff];
+    };
+    if (a.mu) fetch_psi(plane * pz);
     for (int p = z0 - 1; p <= z1; ++p, pz = next_plane(pz, g.nz)) {
       const bool ghost = WALLS && (p < 0 || p >= g.nz);  // a plane beyond a wall
       plane_work(p);
       if (a.noise && !ghost) gen(plane * pz);
-      if (a.mu) prep_load_psi(spsi, a.psi, rxy, plane * pz, tid);
+      if (a.mu) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+          if (tid + k * NT < RS) spsi.v[tid + k * NT] = pv[k];
+        if (p < z1) fetch_psi(plane * next_plane(pz, g.nz));
+      }
       __syncthreads();
       const bool emit = p - 1 >= z0 && p - 1 < z1;
       if (a.noise) {
@@ -1068,6 +1081,14 @@ __device__ __forceinline__ void prep_fd_body(const PrepArgs<S>& a, int bx, int b
   const int pbeg = D == 3 ? z0 - 1 : 0, pend = D == 3 ? z1 : 0;
   const int plane = g.nx * g.ny;
   int pz = wrap_any(pbeg, g.nz);
+  // the psi plane is fetched into registers one iteration ahead
+  S pv[2];
+  auto fetch_psi = [&](int zoff) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      if (tid + k * kTX * kTY < PsiPlane<S>::RS) pv[k] = a.psi[pxy[k] + zoff];
+  };
+  if (a.mu) fetch_psi(plane * pz);
   for (int p = pbeg; p <= pend; ++p, pz = next_plane(pz, g.nz)) {
     if (a.noise) {
 #pragma unroll 1
@@ -1085,7 +1106,12 @@ __device__ __forceinline__ void prep_fd_body(const PrepArgs<S>& a, int bx, int b
         }
       }
     }
-    if (a.mu) prep_load_psi(pr, a.psi, pxy, plane * pz, tid);
+    if (a.mu) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        if (tid + k * kTX * kTY < PsiPlane<S>::RS) pr.v[tid + k * kTX * kTY] = pv[k];
+      if (p < pend) fetch_psi(plane * next_plane(pz, g.nz));
+    }
     __syncthreads();
     if (a.mu && live) {
       if constexpr (D == 2) {
