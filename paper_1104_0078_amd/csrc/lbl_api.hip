@@ -1083,12 +1083,21 @@ struct Impl {
       else
         kb_lb<S, DEV, Q, SMOL, false, false, WALLS><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
                                                                                  lb_lw, k);
-      if (rk > 1 && nt)
+      if constexpr (noise_in_uend<Q, SMOL>()) {
+        // the velocity pass and the SMOL noise on the SMOL tiles
+        if (nt)
+          kb_uend_noise<S, DEV, Q, true, WALLS><<<ntile, btile, 0, stream>>>(reps, states, wtile,
+                                                                              rk, k);
+        else
+          kb_uend_noise<S, DEV, Q, false, WALLS><<<ntile, btile, 0, stream>>>(reps, states, wtile,
+                                                                               rk, k);
+      } else if (rk > 1 && nt) {
         kb_uend<S, DEV, Q, SMOL, true, WALLS><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw,
                                                                            rk, k);
-      else if (rk > 1)
+      } else if (rk > 1) {
         kb_uend<S, DEV, Q, SMOL, false, WALLS><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
                                                                             lb_lw, rk, k);
+      }
       for (int st = 0; st < rk; ++st)
         kb_stage<S, Q, SMOL, WALLS><<<ntile, btile, 0, stream>>>(reps, states, wtile, st, rk, k);
       const hipError_t e = hipGetLastError();

@@ -60,6 +60,13 @@ struct Work {
   int bx, by, bz;
 };
 
+// FV on 3-D lattices: the SMOL noise is drawn in kb_uend_noise, the
+// preparation computes mu alone.
+template <int Q, int SMOL>
+constexpr bool noise_in_uend() {
+  return SMOL == kFV && Lat<Q>::D == 3;
+}
+
 // WALLS: every replica of the launch has walls across the last axis (FV).
 template <typename S, int Q, int SMOL, bool WALLS = false>
 __global__ __launch_bounds__(kTX* kTY) void kb_prep(const Replica<S>* __restrict__ reps,
@@ -78,7 +85,8 @@ __global__ __launch_bounds__(kTX* kTY) void kb_prep(const Replica<S>* __restrict
   a.step = rs.step;
   a.zc = r.zc;
   a.psi = r.psi[rs.pcur];
-  a.noise = (r.coupling != kCplLbOnly && r.noise_on) ? r.noise : nullptr;
+  a.noise = (r.coupling != kCplLbOnly && r.noise_on && !noise_in_uend<Q, SMOL>()) ? r.noise
+                                                                                : nullptr;
   a.mu = r.coupling == kCplFull ? r.mu : nullptr;
   if (!a.noise && !a.mu) return;
   if constexpr (SMOL == kFV)
@@ -160,6 +168,49 @@ __global__ __launch_bounds__(kSiteBlock) void kb_uend(const Replica<S>* __restri
   int x, y;
   lb_tile_site(w, lw, x, y);
   if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, false, false, NT, WALLS>(a, x, y, w.bz);
+}
+
+// FV, 3-D: the velocity pass (full coupling, rk >= 2) and the SMOL noise
+// (kT > 0, a coupling with the SMOL update) in one z-marching launch over
+// the SMOL tiles, as k_uend_noise; each replica does the parts it needs.
+template <typename S, bool DEV, int Q, bool NT, bool WALLS = false>
+__global__ __launch_bounds__(kTX* kTY) void kb_uend_noise(const Replica<S>* __restrict__ reps,
+                                                         const RepState* __restrict__ st,
+                                                         const Work* __restrict__ work, int rk,
+                                                         int k) {
+  const Work w = work[blockIdx.x];
+  const Replica<S>& r = reps[w.rep];
+  const RepState rs = at_step(st[w.rep], r.coupling, k);
+  if (rs.remaining <= 0) return;
+  const bool pull = r.coupling == kCplFull && rk >= 2;
+  const bool noise = r.coupling != kCplLbOnly && r.noise_on;
+  if (!pull && !noise) return;
+  LBArgs<S> la;
+  la.g = r.g;
+  la.f_in = r.f[1 - rs.cur];
+  la.f_out = nullptr;
+  la.psi = r.psi[rs.pcur];
+  la.mu = r.mu;
+  la.u_out = r.u_end;
+  la.rho0 = r.rho0;
+  la.force = 1;
+  la.Fext = nullptr;
+  la.noise = 0;
+  la.nt = NT;
+  for (int c = 0; c < 2; ++c)
+    for (int d = 0; d < 3; ++d) la.uw[c][d] = r.uw[c][d];
+  PrepArgs<S> pa;
+  pa.g = r.g;
+  pa.c = r.c;
+  pa.amp = r.amp;
+  pa.k0 = r.k0;
+  pa.k1 = r.k1;
+  pa.step = rs.step;
+  pa.zc = r.zc;
+  pa.psi = nullptr;
+  pa.noise = noise ? r.noise : nullptr;
+  pa.mu = nullptr;
+  uend_noise_body<S, DEV, Q, NT, WALLS>(la, pa, pull, w.bx, w.by, w.bz);
 }
 
 // Stage `st` of `ns` (ns = 1, 2 or 4), with the same combinations as the

@@ -902,19 +902,26 @@ __global__ __launch_bounds__(kTX* kTY) void k_prep_fv(PrepArgs<S> a, TileMap m) 
 // of that plane in x-fastest order (contiguous runs, read as the row blocks
 // of k_lb read them; the tiles of a plane cover it); its noise keeps the
 // tile's columns.  The preparation kernel then computes mu alone.
-template <typename S, bool DEV, int Q, bool NT, bool WALLS = false>
-__global__ __launch_bounds__(kTX* kTY) void k_uend_noise(LBArgs<S> la, PrepArgs<S> pa, TileMap m) {
+// `pull`: whether this launch forms u-bar^1 (pa.noise null: no noise).
+template <typename S, bool DEV, int Q, bool NT, bool WALLS>
+__device__ __forceinline__ void uend_noise_body(const LBArgs<S>& la, const PrepArgs<S>& pa,
+                                                bool pull, int bx, int by, int bz) {
   static_assert(Lat<Q>::D == 3, "3-D lattices");
-  int bx, by, bz;
-  if (!tile_of(m, bx, by, bz)) return;
   const Geom& g = la.g;
+  const int ntx = (g.nx + kTX - 1) / kTX;
   const int z0 = bz * pa.zc, z1 = min(z0 + pa.zc, g.nz);
-  const int e = (bx + m.ntx * by) * (kTX * kTY) + threadIdx.y * kTX + threadIdx.x;
-  const bool pulls = e < g.nx * g.ny;
+  const int e = (bx + ntx * by) * (kTX * kTY) + threadIdx.y * kTX + threadIdx.x;
+  const bool pulls = pull && e < g.nx * g.ny;
   const int x = pulls ? e % g.nx : 0, y = pulls ? e / g.nx : 0;
   prep_fv_body<S, Q, WALLS>(pa, bx, by, bz, [&](int p) {
     if (pulls && p >= z0 && p < z1) lb_body<S, DEV, Q, kFV, false, false, NT, WALLS>(la, x, y, p);
   });
+}
+
+template <typename S, bool DEV, int Q, bool NT, bool WALLS = false>
+__global__ __launch_bounds__(kTX* kTY) void k_uend_noise(LBArgs<S> la, PrepArgs<S> pa, TileMap m) {
+  int bx, by, bz;
+  if (tile_of(m, bx, by, bz)) uend_noise_body<S, DEV, Q, NT, WALLS>(la, pa, true, bx, by, bz);
 }
 
 // Stress-divergence force of the FV variant in 3-D (sigma and F = -G.sigma of

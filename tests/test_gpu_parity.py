@@ -164,6 +164,20 @@ def test_conservation_on_gpu(lattice, precision):
     assert abs(t1[4] - t0[4]) <= tol * t0[9]
 
 
+@pytest.mark.parametrize("lattice,smol,overlap", [(H.D3Q19, H.FV, 3), (H.D3Q15, H.FV, 3),
+                                                   (H.D3Q19, H.FD, 0), (H.D2Q9, H.FV, 0)])
+def test_default_schedule_draws_the_fv_noise_in_the_velocity_pass(lattice, smol, overlap):
+    """The default schedule: FV on 3-D lattices draws the SMOL noise inside
+    the velocity pass (overlap 3); other lattices and variants run overlap 0.
+    z-chunks passed to lbl_set_schedule apply to that pass as well."""
+    from paper_1104_0078_amd import lbl
+    c = H.config(lattice=lattice, smol=smol, shape=SHAPES[lattice], init=0)
+    with lbl.Sim(H.lbl_params(c), lbl.make_init(kind=0, psi_std=1e-3)) as sim:
+        assert sim.schedule()["overlap"] == overlap
+        sim.set_schedule(lb_width=64, xcd_swizzle=0, zc=0, overlap=overlap)
+        assert sim.schedule()["overlap"] == overlap
+
+
 @pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q19])
 def test_schedule_does_not_change_results(lattice):
     """Every launch schedule (LB block width, XCD-contiguous block order,

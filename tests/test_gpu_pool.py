@@ -59,6 +59,15 @@ MIX = [
               u_wall=((0.02, 0, 0), (-0.01, 0, 0))), 21),
     (H.config(lattice=H.D3Q15, smol=H.FV, precision=H.FP32DEV, shape=(14, 12, 10), seed=25,
               rk=4, walls=1, u_wall=((0.01, 0.01, 0), (0, 0, 0))), 12),
+    # FV on 3-D lattices draws the noise in the velocity pass's launch: a
+    # request with the noise and no velocity pass (SMOL alone; Euler), and
+    # one with the velocity pass and no noise (kT = 0)
+    (H.config(lattice=H.D3Q19, smol=H.FV, coupling=H.SMOL_ONLY, shape=(14, 12, 10), seed=26,
+              u_imposed=(0.02, 0.01, -0.01)), 15),
+    (H.config(lattice=H.D3Q19, smol=H.FV, shape=(16, 12, 10), seed=27, rk=1, a=-0.04, b=0.04,
+              init=1), 13),
+    (H.config(lattice=H.D3Q15, smol=H.FV, shape=(12, 10, 14), seed=28, kT=0.0, a=-0.04, b=0.04,
+              init=1), 11),
 ]
 
 
