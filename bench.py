@@ -65,10 +65,11 @@ def alg_bytes_per_site(w):
 
 def noise_in_velocity_pass(w, schedule):
     """True when the step draws the SMOL noise inside the velocity pass
-    (schedule overlap 3, FV on a 3-D lattice; the workloads here run full
-    coupling with two stages and kT > 0)."""
-    return (schedule is not None and schedule.get("overlap") == 3 and w["smol"] == 1
-            and w["lattice"] != 9)
+    (schedule overlap 3, the default; the noise built in Fourier space is
+    drawn apart; the workloads here run full coupling with two stages and
+    kT > 0)."""
+    return (schedule is not None and schedule.get("overlap") == 3
+            and not (w["smol"] == 0 and w.get("fd_noise", 0) == 1))
 
 
 def kernel_alg_bytes_per_site(name, w, rk=2, schedule=None):

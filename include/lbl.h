@@ -304,15 +304,15 @@ int lbl_timing_read(lbl_sim *sim, lbl_kernel_time *out, int max_entries, int *n_
  * streamed populations that only the later stages read (full coupling, 2 or
  * 4 stages); 2 draws the SMOL noise on that second stream, concurrently with
  * the LB passes (the noise depends on the counter alone), and joins it before
- * the first stage; 3 (FV on 3-D lattices) draws the SMOL noise inside the
- * velocity pass, one z-marching kernel on the stream, where a velocity pass
- * runs (full coupling, 2 or 4 stages, kT > 0), and is 0 elsewhere; 0 runs
- * everything on the simulation's stream, the noise in the preparation
- * kernel.  Default: the widest width up to 256 that fits nx, no swizzle, zc
- * per kernel from its occupancy (the stage's blocks fill the device's
- * resident slots in one round, the preparation kernel's and the velocity
- * pass's in two; at least 8 planes), overlap 3 for FV on 3-D lattices and 0
- * otherwise.  The z-marching stress pass of force_form STRESS (FV, 3-D) keeps
+ * the first stage; 3 draws the SMOL noise inside the velocity pass, one
+ * kernel on the SMOL tiles (z-marching in 3-D) on the stream, where a
+ * velocity pass runs (full coupling, 2 or 4 stages) and the preparation
+ * kernel would draw the noise (kT > 0; not the FD noise built in Fourier
+ * space), and is 0 elsewhere; 0 runs everything on the simulation's stream,
+ * the noise in the preparation kernel.  Default: the widest width up to 256
+ * that fits nx, no swizzle, zc per kernel from its occupancy (the stage's
+ * blocks fill the device's resident slots in one round, the preparation
+ * kernel's and the velocity pass's in two; at least 8 planes), overlap 3.  The z-marching stress pass of force_form STRESS (FV, 3-D) keeps
  * its own default (two rounds) whatever zc is.  Errors: LBL_E_INVAL (NULL,
  * unsupported width, zc < 0, overlap not 0, 1, 2 or 3). */
 typedef struct lbl_schedule {

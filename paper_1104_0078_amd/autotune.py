@@ -14,7 +14,7 @@ Schedule knobs (see lbl_set_schedule / lbl_pool_set_schedule in lbl.h):
                (single simulations: bit 0 the LB kernels, bit 1 the SMOL tiles);
   zc           planes per block of the z-marching SMOL kernels (3-D);
   overlap      1: the first stage, 2: the SMOL noise on a second stream,
-               3: the SMOL noise inside the velocity pass (FV, 3-D), 0: none
+               3: the SMOL noise inside the velocity pass (the default), 0: none
                (single simulations).
 """
 import json
@@ -99,7 +99,7 @@ def tune_sim(sim, params, steps=6, use_cache=True, candidates=None):
     # Last dimension, on top of the best schedule so far: the first stage on
     # a second stream, concurrent with the velocity pass (full coupling,
     # several stages), the SMOL noise on it, concurrent with the LB passes,
-    # the noise inside the velocity pass (FV, 3-D), or none of these.
+    # the noise inside the velocity pass (the default), or none of these.
     overlaps = [0]
     if params.coupling == 0 and params.rk_stages > 1:
         overlaps.append(1)

@@ -76,12 +76,12 @@ struct lbl_sim {
   int zc = 1;       // planes per block of the z-marching SMOL stage kernels
   int zc_prep = 1;  // planes per block of the z-marching preparation kernel
   int zc_stress = 1;  // planes per block of the z-marching FV stress kernels (3-D)
-  int zc_uend = 1;    // planes per block of the velocity pass with the noise (FV, 3-D)
+  int zc_uend = 1;    // planes per block of the velocity pass with the noise (3-D)
   int lb_lw = 6;       // log2 of the LB block width along x
   int lb_swizzle = 0;  // XCD-contiguous block order: bit 0 LB kernels, bit 1 tile kernels
   int overlap = 0;     // 1: first RK stage on `aux`, concurrent with the velocity pass;
                        // 2: SMOL noise on `aux`, concurrent with the LB passes;
-                       // 3: SMOL noise drawn inside the velocity pass (FV, 3-D)
+                       // 3: SMOL noise drawn inside the velocity pass (the default)
   hipStream_t aux = nullptr;  // created on first use (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double gamma_s = 0, gamma_b = 0, gamma_g = 0, sigma_s = 0, sigma_b = 0, sigma_g = 0;
@@ -377,16 +377,15 @@ struct Impl {
       }
     }
     int nb_stress = 0, nb_uend = 0;
-    if constexpr (SMOL == kFV && Lat<Q>::D == 3) {
+    if constexpr (SMOL == kFV && Lat<Q>::D == 3)
       if (!rc)
         rc = hip_check(s, hipOccupancyMaxActiveBlocksPerMultiprocessor(
                               &nb_stress, k_stress_force_fv3<S, Q>, kTX * kTY, 0),
                        "occupancy");
-      if (!rc)
-        rc = hip_check(s, hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &nb_uend, k_uend_noise<S, DEV, Q, false>, kTX * kTY, 0),
-                       "occupancy");
-    }
+    if (!rc)
+      rc = hip_check(s, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &nb_uend, k_uend_noise<S, DEV, Q, SMOL, false>, kTX * kTY, 0),
+                     "occupancy");
     if (rc) return rc;
     const int nz = s->p.nz;
     const long bxy = static_cast<long>((s->p.nx + kTX - 1) / kTX) * ((s->p.ny + kTY - 1) / kTY);
@@ -699,42 +698,41 @@ struct Impl {
     return launch_on(s, ss, "k_stage", [&] { k_stage_fv<S, Q, WALLS><<<tg, tb, 0, ss>>>(a, tm); });
   }
 
-  // The velocity pass with the SMOL noise N^n of step `la.step` (FV, 3-D).
+  // The velocity pass with the SMOL noise N^n of step `la.step`, on the
+  // SMOL tiles (z-chunks of zc_uend planes in 3-D).
   static int launch_uend_noise(lbl_sim* s, const LBArgs<S>& la, S* noise) {
-    if constexpr (SMOL == kFV && Lat<Q>::D == 3) {
-      PrepArgs<S> pa;
-      pa.g = la.g;
-      pa.c = coef(s);
-      pa.amp = S(std::sqrt(2.0 * s->p.kT * s->p.M));
-      pa.k0 = s->k0;
-      pa.k1 = s->k1;
-      pa.step = la.step;
-      pa.zc = s->zc_uend;
-      pa.psi = nullptr;
-      pa.noise = noise;
-      pa.mu = nullptr;
-      const TileMap tm = make_tile_map(s->p.nx, s->p.ny, (s->p.nz + s->zc_uend - 1) / s->zc_uend,
-                                       (s->lb_swizzle & 2) != 0);
-      const dim3 tg(tile_map_blocks(tm)), tb(kTX, kTY);
-      const hipStream_t st = s->stream;
-      const bool walls = s->p.walls == LBL_WALLS_LAST;
-      return launch(s, "k_uend", [&] {
-        if (walls) {
+    constexpr bool k3 = Lat<Q>::D == 3;
+    PrepArgs<S> pa;
+    pa.g = la.g;
+    pa.c = coef(s);
+    pa.amp = S(std::sqrt(2.0 * s->p.kT * s->p.M));
+    pa.k0 = s->k0;
+    pa.k1 = s->k1;
+    pa.step = la.step;
+    pa.zc = k3 ? s->zc_uend : 1;
+    pa.psi = nullptr;
+    pa.noise = noise;
+    pa.mu = nullptr;
+    const TileMap tm = make_tile_map(s->p.nx, s->p.ny,
+                                     k3 ? (s->p.nz + s->zc_uend - 1) / s->zc_uend : 1,
+                                     (s->lb_swizzle & 2) != 0);
+    const dim3 tg(tile_map_blocks(tm)), tb(kTX, kTY);
+    const hipStream_t st = s->stream;
+    if constexpr (SMOL == kFV) {
+      if (s->p.walls == LBL_WALLS_LAST)
+        return launch(s, "k_uend", [&] {
           if (la.nt)
-            k_uend_noise<S, DEV, Q, true, true><<<tg, tb, 0, st>>>(la, pa, tm);
+            k_uend_noise<S, DEV, Q, SMOL, true, true><<<tg, tb, 0, st>>>(la, pa, tm);
           else
-            k_uend_noise<S, DEV, Q, false, true><<<tg, tb, 0, st>>>(la, pa, tm);
-        } else if (la.nt) {
-          k_uend_noise<S, DEV, Q, true><<<tg, tb, 0, st>>>(la, pa, tm);
-        } else {
-          k_uend_noise<S, DEV, Q, false><<<tg, tb, 0, st>>>(la, pa, tm);
-        }
-      });
-    } else {
-      (void)la;
-      (void)noise;
-      return fail(s, LBL_E_INVAL, "the velocity pass draws the noise only with FV on 3-D lattices");
+            k_uend_noise<S, DEV, Q, SMOL, false, true><<<tg, tb, 0, st>>>(la, pa, tm);
+        });
     }
+    return launch(s, "k_uend", [&] {
+      if (la.nt)
+        k_uend_noise<S, DEV, Q, SMOL, true><<<tg, tb, 0, st>>>(la, pa, tm);
+      else
+        k_uend_noise<S, DEV, Q, SMOL, false><<<tg, tb, 0, st>>>(la, pa, tm);
+    });
   }
 
   static int launch_mu(lbl_sim* s, const S* phi, S* mu) {
@@ -784,10 +782,10 @@ struct Impl {
     const bool walls_tiled = walls && kTiledWalls;
     const bool split = prep_noise && s->overlap == 2;
     // The velocity of the streamed populations is needed by the stages at
-    // t_{n+1}; with overlap 3 (FV, 3-D) the same pass draws the SMOL noise,
-    // which the first stage is the first to read.
+    // t_{n+1}; with overlap 3 the same pass draws the SMOL noise, which the
+    // first stage is the first to read.
     const bool uend = cpl == LBL_FULL && s->p.rk_stages > 1;
-    const bool fuse = SMOL == kFV && Lat<Q>::D == 3 && prep_noise && uend && s->overlap == 3;
+    const bool fuse = prep_noise && uend && s->overlap == 3;
     if (split) {
       if (int rc = ensure_aux(s)) return rc;
       if (int rc = hip_check(s, hipEventRecord(s->ev_fork, s->stream), "fork")) return rc;
@@ -1083,21 +1081,13 @@ struct Impl {
       else
         kb_lb<S, DEV, Q, SMOL, false, false, WALLS><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
                                                                                  lb_lw, k);
-      if constexpr (noise_in_uend<Q, SMOL>()) {
-        // the velocity pass and the SMOL noise on the SMOL tiles
-        if (nt)
-          kb_uend_noise<S, DEV, Q, true, WALLS><<<ntile, btile, 0, stream>>>(reps, states, wtile,
-                                                                              rk, k);
-        else
-          kb_uend_noise<S, DEV, Q, false, WALLS><<<ntile, btile, 0, stream>>>(reps, states, wtile,
-                                                                               rk, k);
-      } else if (rk > 1 && nt) {
-        kb_uend<S, DEV, Q, SMOL, true, WALLS><<<nlb, bsite, 0, stream>>>(reps, states, wlb, lb_lw,
-                                                                           rk, k);
-      } else if (rk > 1) {
-        kb_uend<S, DEV, Q, SMOL, false, WALLS><<<nlb, bsite, 0, stream>>>(reps, states, wlb,
-                                                                            lb_lw, rk, k);
-      }
+      // the velocity pass and the SMOL noise on the SMOL tiles
+      if (nt)
+        kb_uend_noise<S, DEV, Q, SMOL, true, WALLS><<<ntile, btile, 0, stream>>>(reps, states,
+                                                                                  wtile, rk, k);
+      else
+        kb_uend_noise<S, DEV, Q, SMOL, false, WALLS><<<ntile, btile, 0, stream>>>(reps, states,
+                                                                                   wtile, rk, k);
       for (int st = 0; st < rk; ++st)
         kb_stage<S, Q, SMOL, WALLS><<<ntile, btile, 0, stream>>>(reps, states, wtile, st, rk, k);
       const hipError_t e = hipGetLastError();
@@ -1299,8 +1289,8 @@ void setup_fields(lbl_sim* s, const lbl_params* params) {
   s->sigma_g = sig(s->gamma_g);
   // z-chunks of the tiled SMOL kernels: set from their occupancy at init.
   s->zc = s->zc_prep = s->zc_uend = params->nz;
-  // FV on 3-D lattices: the SMOL noise is drawn in the velocity pass.
-  s->overlap = params->smol == LBL_SMOL_FV && params->lattice != LBL_D2Q9 ? 3 : 0;
+  // The SMOL noise is drawn in the velocity pass where there is one.
+  s->overlap = 3;
   // LB blocks: the widest power of two up to 256 that fits along x (whole
   // rows where possible, so that pulls shifted along x stay inside a block).
   s->lb_lw = 5;

@@ -60,13 +60,6 @@ struct Work {
   int bx, by, bz;
 };
 
-// FV on 3-D lattices: the SMOL noise is drawn in kb_uend_noise, the
-// preparation computes mu alone.
-template <int Q, int SMOL>
-constexpr bool noise_in_uend() {
-  return SMOL == kFV && Lat<Q>::D == 3;
-}
-
 // WALLS: every replica of the launch has walls across the last axis (FV).
 template <typename S, int Q, int SMOL, bool WALLS = false>
 __global__ __launch_bounds__(kTX* kTY) void kb_prep(const Replica<S>* __restrict__ reps,
@@ -85,10 +78,10 @@ __global__ __launch_bounds__(kTX* kTY) void kb_prep(const Replica<S>* __restrict
   a.step = rs.step;
   a.zc = r.zc;
   a.psi = r.psi[rs.pcur];
-  a.noise = (r.coupling != kCplLbOnly && r.noise_on && !noise_in_uend<Q, SMOL>()) ? r.noise
-                                                                                : nullptr;
+  // the SMOL noise is drawn in kb_uend_noise; the preparation computes mu
+  a.noise = nullptr;
   a.mu = r.coupling == kCplFull ? r.mu : nullptr;
-  if (!a.noise && !a.mu) return;
+  if (!a.mu) return;
   if constexpr (SMOL == kFV)
     prep_fv_body<S, Q, WALLS>(a, w.bx, w.by, w.bz);
   else
@@ -139,41 +132,12 @@ __global__ __launch_bounds__(kSiteBlock) void kb_lb(const Replica<S>* __restrict
   if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, GHOST, true, NT, WALLS>(a, x, y, w.bz);
 }
 
-// Velocity of the streamed populations, (jbar^{n+1} + F^n/2)/rho^{n+1}, for
-// the Runge-Kutta stages at t_{n+1}: the LB body without collision, pulling
-// the populations the step just wrote.
+// The velocity of the streamed populations, (jbar^{n+1} + F^n/2)/rho^{n+1},
+// for the Runge-Kutta stages at t_{n+1} (full coupling, rk >= 2: the LB body
+// without collision, pulling the populations the step just wrote), and the
+// SMOL noise (kT > 0, a coupling with the SMOL update) in one launch over the
+// SMOL tiles, as k_uend_noise; each replica does the parts it needs.
 template <typename S, bool DEV, int Q, int SMOL, bool NT, bool WALLS = false>
-__global__ __launch_bounds__(kSiteBlock) void kb_uend(const Replica<S>* __restrict__ reps,
-                                                     const RepState* __restrict__ st,
-                                                     const Work* __restrict__ work, int lw, int rk,
-                                                     int k) {
-  const Work w = work[blockIdx.x];
-  const Replica<S>& r = reps[w.rep];
-  const RepState rs = at_step(st[w.rep], r.coupling, k);
-  if (rs.remaining <= 0 || r.coupling != kCplFull || rk < 2) return;
-  LBArgs<S> a;
-  a.g = r.g;
-  a.f_in = r.f[1 - rs.cur];
-  a.f_out = nullptr;
-  a.psi = r.psi[rs.pcur];
-  a.mu = r.mu;
-  a.u_out = r.u_end;
-  a.rho0 = r.rho0;
-  a.force = 1;
-  a.Fext = nullptr;
-  a.noise = 0;
-  a.nt = NT;
-  for (int k = 0; k < 2; ++k)
-    for (int c = 0; c < 3; ++c) a.uw[k][c] = r.uw[k][c];
-  int x, y;
-  lb_tile_site(w, lw, x, y);
-  if (x < r.g.nx && y < r.g.ny) lb_body<S, DEV, Q, SMOL, false, false, NT, WALLS>(a, x, y, w.bz);
-}
-
-// FV, 3-D: the velocity pass (full coupling, rk >= 2) and the SMOL noise
-// (kT > 0, a coupling with the SMOL update) in one z-marching launch over
-// the SMOL tiles, as k_uend_noise; each replica does the parts it needs.
-template <typename S, bool DEV, int Q, bool NT, bool WALLS = false>
 __global__ __launch_bounds__(kTX* kTY) void kb_uend_noise(const Replica<S>* __restrict__ reps,
                                                          const RepState* __restrict__ st,
                                                          const Work* __restrict__ work, int rk,
@@ -210,7 +174,7 @@ __global__ __launch_bounds__(kTX* kTY) void kb_uend_noise(const Replica<S>* __re
   pa.psi = nullptr;
   pa.noise = noise ? r.noise : nullptr;
   pa.mu = nullptr;
-  uend_noise_body<S, DEV, Q, NT, WALLS>(la, pa, pull, w.bx, w.by, w.bz);
+  uend_noise_body<S, DEV, Q, SMOL, NT, WALLS>(la, pa, pull, w.bx, w.by, w.bz);
 }
 
 // Stage `st` of `ns` (ns = 1, 2 or 4), with the same combinations as the

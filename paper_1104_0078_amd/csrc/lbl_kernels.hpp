@@ -768,13 +768,14 @@ __device__ __forceinline__ S prep_mu2(const PsiPlane<S>& r, const Coef<S>& c, in
 // +-W xi_z on the end planes) and the Laplacian the centre's psi
 // (SoPlanes::mu_walled).  2-D: a link to a row beyond a wall takes minus the
 // centre's xi, and the Laplacian the centre's psi.
-// 3-D: `plane_work(p)` runs at the start of iteration p, for kernels that do
-// per-plane work of their own beside the noise.
+// `plane_work(p)` runs at the start of iteration p (plane 0 in 2-D), for
+// kernels that do per-plane work of their own beside the noise; MU = false
+// compiles the chemical potential out (a.mu is then ignored).
 struct NoPlaneWork {
   __device__ __forceinline__ void operator()(int) const {}
 };
 
-template <typename S, int Q, bool WALLS = false, typename PW = NoPlaneWork>
+template <typename S, int Q, bool WALLS = false, bool MU = true, typename PW = NoPlaneWork>
 __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int by, int bz,
                                              PW plane_work = PW{}) {
   using L = Lat<Q>;
@@ -828,14 +829,15 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
     }
   };
   if constexpr (D == 2) {
+    plane_work(0);
     if (a.noise) gen(0);
-    if (a.mu) prep_load_psi(spsi, a.psi, rxy, 0, tid);
+    if (MU && a.mu) prep_load_psi(spsi, a.psi, rxy, 0, tid);
     __syncthreads();
     if (a.noise) {
       fold();
       if (live) a.noise[x + g.nx * y] = S(3) * a.amp * npart[1];
     }
-    if (a.mu && live) a.mu[x + g.nx * y] = prep_mu2<S, WALLS>(spsi, a.c, tx, ty, y, g.ny);
+    if (MU && a.mu && live) a.mu[x + g.nx * y] = prep_mu2<S, WALLS>(spsi, a.c, tx, ty, y, g.ny);
   } else {
     // Iteration p: xi(p) and psi(p) staged; N(p-1) and mu(p-1) emitted.  The
     // psi plane is fetched into registers one iteration ahead.
@@ -847,12 +849,12 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
       for (int k = 0; k < 2; ++k)
         if (tid + k * NT < RS) pv[k] = a.psi[rxy[k] + zoff];
     };
-    if (a.mu) fetch_psi(plane * pz);
+    if (MU && a.mu) fetch_psi(plane * pz);
     for (int p = z0 - 1; p <= z1; ++p, pz = next_plane(pz, g.nz)) {
       const bool ghost = WALLS && (p < 0 || p >= g.nz);  // a plane beyond a wall
       plane_work(p);
       if (a.noise && !ghost) gen(plane * pz);
-      if (a.mu) {
+      if (MU && a.mu) {
 #pragma unroll
         for (int k = 0; k < 2; ++k)
           if (tid + k * NT < RS) spsi.v[tid + k * NT] = pv[k];
@@ -873,7 +875,7 @@ __device__ __forceinline__ void prep_fv_body(const PrepArgs<S>& a, int bx, int b
         npart[1] = npart[2];
         npart[2] = 0;
       }
-      if (a.mu && live) {
+      if (MU && a.mu && live) {
         so.template push<W>(spsi.v + (tx + 1) + W * (ty + 1));
         if (emit)
           a.mu[x + g.nx * (y + g.ny * (p - 1))] =
@@ -891,37 +893,6 @@ template <typename S, int Q, bool WALLS = false>
 __global__ __launch_bounds__(kTX* kTY) void k_prep_fv(PrepArgs<S> a, TileMap m) {
   int bx, by, bz;
   if (tile_of(m, bx, by, bz)) prep_fv_body<S, Q, WALLS>(a, bx, by, bz);
-}
-
-// FV, 3-D: the velocity pass of the streamed populations (lb_body without
-// the collision: u-bar^1 for the later stages) and the SMOL noise N^n of
-// prep_fv_body in one z-marching launch.  The noise is arithmetic (the
-// Box-Muller normals) and the velocity pass reads the populations with its
-// vector units mostly idle, so in one kernel the two overlap.  The block of
-// in-plane tile t pulls, on each of its planes, the sites t*NT ... t*NT+NT-1
-// of that plane in x-fastest order (contiguous runs, read as the row blocks
-// of k_lb read them; the tiles of a plane cover it); its noise keeps the
-// tile's columns.  The preparation kernel then computes mu alone.
-// `pull`: whether this launch forms u-bar^1 (pa.noise null: no noise).
-template <typename S, bool DEV, int Q, bool NT, bool WALLS>
-__device__ __forceinline__ void uend_noise_body(const LBArgs<S>& la, const PrepArgs<S>& pa,
-                                                bool pull, int bx, int by, int bz) {
-  static_assert(Lat<Q>::D == 3, "3-D lattices");
-  const Geom& g = la.g;
-  const int ntx = (g.nx + kTX - 1) / kTX;
-  const int z0 = bz * pa.zc, z1 = min(z0 + pa.zc, g.nz);
-  const int e = (bx + ntx * by) * (kTX * kTY) + threadIdx.y * kTX + threadIdx.x;
-  const bool pulls = pull && e < g.nx * g.ny;
-  const int x = pulls ? e % g.nx : 0, y = pulls ? e / g.nx : 0;
-  prep_fv_body<S, Q, WALLS>(pa, bx, by, bz, [&](int p) {
-    if (pulls && p >= z0 && p < z1) lb_body<S, DEV, Q, kFV, false, false, NT, WALLS>(la, x, y, p);
-  });
-}
-
-template <typename S, bool DEV, int Q, bool NT, bool WALLS = false>
-__global__ __launch_bounds__(kTX* kTY) void k_uend_noise(LBArgs<S> la, PrepArgs<S> pa, TileMap m) {
-  int bx, by, bz;
-  if (tile_of(m, bx, by, bz)) uend_noise_body<S, DEV, Q, NT, WALLS>(la, pa, true, bx, by, bz);
 }
 
 // Stress-divergence force of the FV variant in 3-D (sigma and F = -G.sigma of
@@ -1057,8 +1028,10 @@ __global__ __launch_bounds__(kTX* kTY) void k_stress_force_fv3(Geom g, Coef<S> c
 // amplitude A_l = amp sqrt(lambda_l), N(x) = sum_l A_l [zeta_l(x - c_l) - zeta_l(x)].
 // Each plane's link normals are drawn once into LDS; every thread accumulates
 // its site's sums for planes p-1, p, p+1 in registers.
-template <typename S, int Q>
-__device__ __forceinline__ void prep_fd_body(const PrepArgs<S>& a, int bx, int by, int bz) {
+// plane_work and MU as for prep_fv_body.
+template <typename S, int Q, bool MU = true, typename PW = NoPlaneWork>
+__device__ __forceinline__ void prep_fd_body(const PrepArgs<S>& a, int bx, int by, int bz,
+                                             PW plane_work = PW{}) {
   using L = Lat<Q>;
   constexpr int D = L::D;
   constexpr int NL = L::NLINKS;
@@ -1095,8 +1068,9 @@ __device__ __forceinline__ void prep_fd_body(const PrepArgs<S>& a, int bx, int b
     for (int k = 0; k < 2; ++k)
       if (tid + k * kTX * kTY < PsiPlane<S>::RS) pv[k] = a.psi[pxy[k] + zoff];
   };
-  if (a.mu) fetch_psi(plane * pz);
+  if (MU && a.mu) fetch_psi(plane * pz);
   for (int p = pbeg; p <= pend; ++p, pz = next_plane(pz, g.nz)) {
+    plane_work(p);
     if (a.noise) {
 #pragma unroll 1
       for (int k = 0; k < 2; ++k) {  // not unrolled: one copy of the normal generator
@@ -1113,14 +1087,14 @@ __device__ __forceinline__ void prep_fd_body(const PrepArgs<S>& a, int bx, int b
         }
       }
     }
-    if (a.mu) {
+    if (MU && a.mu) {
 #pragma unroll
       for (int k = 0; k < 2; ++k)
         if (tid + k * kTX * kTY < PsiPlane<S>::RS) pr.v[tid + k * kTX * kTY] = pv[k];
       if (p < pend) fetch_psi(plane * next_plane(pz, g.nz));
     }
     __syncthreads();
-    if (a.mu && live) {
+    if (MU && a.mu && live) {
       if constexpr (D == 2) {
         a.mu[x + g.nx * y] = prep_mu2(pr, a.c, tx, ty);
       } else {
@@ -1156,6 +1130,43 @@ template <typename S, int Q>
 __global__ __launch_bounds__(kTX* kTY) void k_prep_fd(PrepArgs<S> a, TileMap m) {
   int bx, by, bz;
   if (tile_of(m, bx, by, bz)) prep_fd_body<S, Q>(a, bx, by, bz);
+}
+
+// The velocity pass of the streamed populations (lb_body without the
+// collision: u-bar^1 for the later stages) and the SMOL noise N^n of
+// prep_fv_body or prep_fd_body in one launch on the SMOL tiles (z-marching
+// in 3-D).  The noise is arithmetic (the
+// Box-Muller normals) and the velocity pass reads the populations with its
+// vector units mostly idle, so in one kernel the two overlap.  The block of
+// in-plane tile t pulls, on each of its planes, the sites t*NT ... t*NT+NT-1
+// of that plane in x-fastest order (contiguous runs, read as the row blocks
+// of k_lb read them; the tiles of a plane cover it); its noise keeps the
+// tile's columns.  The preparation kernel then computes mu alone.
+// `pull`: whether this launch forms u-bar^1 (pa.noise null: no noise).
+template <typename S, bool DEV, int Q, int SMOL, bool NT, bool WALLS>
+__device__ __forceinline__ void uend_noise_body(const LBArgs<S>& la, const PrepArgs<S>& pa,
+                                                bool pull, int bx, int by, int bz) {
+  constexpr int D = Lat<Q>::D;
+  const Geom& g = la.g;
+  const int ntx = (g.nx + kTX - 1) / kTX;
+  const int z0 = D == 3 ? bz * pa.zc : 0, z1 = D == 3 ? min(z0 + pa.zc, g.nz) : 1;
+  const int e = (bx + ntx * by) * (kTX * kTY) + threadIdx.y * kTX + threadIdx.x;
+  const bool pulls = pull && e < g.nx * g.ny;
+  const int x = pulls ? e % g.nx : 0, y = pulls ? e / g.nx : 0;
+  auto work = [&](int p) {
+    if (pulls && p >= z0 && p < z1) lb_body<S, DEV, Q, SMOL, false, false, NT, WALLS>(la, x, y, p);
+  };
+  if constexpr (SMOL == kFV)
+    prep_fv_body<S, Q, WALLS, false>(pa, bx, by, bz, work);
+  else
+    prep_fd_body<S, Q, false>(pa, bx, by, bz, work);
+}
+
+template <typename S, bool DEV, int Q, int SMOL, bool NT, bool WALLS = false>
+__global__ __launch_bounds__(kTX* kTY) void k_uend_noise(LBArgs<S> la, PrepArgs<S> pa, TileMap m) {
+  int bx, by, bz;
+  if (tile_of(m, bx, by, bz))
+    uend_noise_body<S, DEV, Q, SMOL, NT, WALLS>(la, pa, true, bx, by, bz);
 }
 
 // ---------------------------------------------------------------------------

@@ -34,7 +34,11 @@ def test_algorithmic_bytes_of_the_headline_workload():
     assert bench.kernel_alg_bytes_per_site("k_uend", w, schedule=fused) == (19 + 3 + 3) * 8
     assert bench.kernel_alg_bytes_per_site("k_prep", w, schedule=fused) == 2 * 8
     wfd = dict(w, smol=0)
-    assert bench.kernel_alg_bytes_per_site("k_prep", wfd, schedule=fused) == 3 * 8
+    assert bench.kernel_alg_bytes_per_site("k_prep", wfd, schedule=fused) == 2 * 8
+    # the noise built in Fourier space is drawn apart from both
+    wff = dict(w, smol=0, fd_noise=1)
+    assert bench.kernel_alg_bytes_per_site("k_prep", wff, schedule=fused) == 3 * 8
+    assert bench.kernel_alg_bytes_per_site("k_uend", wff, schedule=fused) == (19 + 2 + 3) * 8
     w32 = dict(w, precision=1)
     assert bench.alg_bytes_per_site(w32) == 160
     assert bench.kernel_alg_bytes_per_site("k_white", w) is None

@@ -164,12 +164,12 @@ def test_conservation_on_gpu(lattice, precision):
     assert abs(t1[4] - t0[4]) <= tol * t0[9]
 
 
-@pytest.mark.parametrize("lattice,smol,overlap", [(H.D3Q19, H.FV, 3), (H.D3Q15, H.FV, 3),
-                                                   (H.D3Q19, H.FD, 0), (H.D2Q9, H.FV, 0)])
-def test_default_schedule_draws_the_fv_noise_in_the_velocity_pass(lattice, smol, overlap):
-    """The default schedule: FV on 3-D lattices draws the SMOL noise inside
-    the velocity pass (overlap 3); other lattices and variants run overlap 0.
-    z-chunks passed to lbl_set_schedule apply to that pass as well."""
+@pytest.mark.parametrize("lattice,smol", [(H.D3Q19, H.FV), (H.D3Q15, H.FV), (H.D3Q19, H.FD),
+                                          (H.D2Q9, H.FV), (H.D2Q9, H.FD)])
+def test_default_schedule_draws_the_noise_in_the_velocity_pass(lattice, smol):
+    """The default schedule draws the SMOL noise inside the velocity pass
+    (overlap 3) on every lattice and variant."""
+    overlap = 3
     from paper_1104_0078_amd import lbl
     c = H.config(lattice=lattice, smol=smol, shape=SHAPES[lattice], init=0)
     with lbl.Sim(H.lbl_params(c), lbl.make_init(kind=0, psi_std=1e-3)) as sim:
@@ -178,13 +178,14 @@ def test_default_schedule_draws_the_fv_noise_in_the_velocity_pass(lattice, smol,
         assert sim.schedule()["overlap"] == overlap
 
 
+@pytest.mark.parametrize("smol", [H.FV, H.FD])
 @pytest.mark.parametrize("lattice", [H.D2Q9, H.D3Q19])
-def test_schedule_does_not_change_results(lattice):
+def test_schedule_does_not_change_results(lattice, smol):
     """Every launch schedule (LB block width, XCD-contiguous block order,
     planes per SMOL tile, first stage or SMOL noise on a second stream, SMOL
     noise drawn in the velocity pass) gives bitwise the same fields."""
     from paper_1104_0078_amd import lbl
-    c = H.config(lattice=lattice, smol=H.FV, shape=SHAPES[lattice], init=0)
+    c = H.config(lattice=lattice, smol=smol, shape=SHAPES[lattice], init=0)
     ini = lbl.make_init(kind=0, psi_std=1e-3)
     out = []
     for w, swz, zc, ov in ((64, 0, 0, 0), (256, 0, 0, 1), (128, 1, 0, 0), (32, 3, 3, 1),
